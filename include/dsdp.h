@@ -1,0 +1,230 @@
+/*
+ * dsdp.h -- C ABI of the MI355X (gfx950) docking library libdsdp.so.
+ *
+ * The library implements the docking stage of DSDP (Huang et al., arXiv
+ * 2303.09916): Vina-scored Monte Carlo search of ligand poses inside a box,
+ * with score-and-gradient grid maps (Section 2, "Binding pose search", first
+ * modification; Appendix eqs. 1-4), Vina's BFGS local optimisation (same
+ * section, second modification names it; ref. [36]), many short independent
+ * chains ("copies", Section 2, parallelisation paragraph) and ranked,
+ * RMSD-clustered output poses (same paragraph, Figure 4).
+ *
+ * Conventions
+ *   - Every call that can fail returns dsdp_status: DSDP_OK (0) or a negative
+ *     error code.  dsdp_last_error() gives a message for the calling thread's
+ *     last failure.  No C++ exception crosses this boundary.
+ *   - Host arrays passed in are borrowed for the duration of the call only.
+ *   - Device memory is owned by the caller (for example torch tensors).  The
+ *     library never allocates or frees device memory; it tells the caller how
+ *     many bytes a call needs (the *_bytes queries) and fails with
+ *     DSDP_ERR_WORKSPACE_TOO_SMALL when a buffer is too small.
+ *   - Streams are hipStream_t passed as void* (NULL = the default stream).
+ *   - Device buffers must be 256-byte aligned.
+ *   - Units: Angstrom, radians, kcal/mol.
+ *   - Pose layout (float): [p_x p_y p_z q_w q_x q_y q_z theta_1 .. theta_Nt],
+ *     stride 7 + Nt; gradient layout: [dE/dp (3), dE/dw (3), dE/dtheta (Nt)]
+ *     where w is a rotation vector applied on the left, q <- quat(w) q.
+ */
+#ifndef DSDP_H
+#define DSDP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dsdp_status;
+
+#define DSDP_OK 0
+#define DSDP_ERR_INVALID_ARG (-1)          /* malformed input; message says which */
+#define DSDP_ERR_UNSUPPORTED (-2)          /* valid but beyond the limits below */
+#define DSDP_ERR_WORKSPACE_TOO_SMALL (-3)  /* a caller buffer is smaller than the query says */
+#define DSDP_ERR_DEVICE (-4)               /* HIP runtime error; message carries its text */
+
+#define DSDP_MAX_ATOMS 64                  /* ligand heavy atoms (one wavefront per chain) */
+#define DSDP_MAX_TORSIONS 31               /* rotatable bonds; fragments = torsions + 1 */
+#define DSDP_N_XS 17                       /* XS atom types */
+
+/*
+ * XS atom types (Vina's X-Score typing, ref. [6]):
+ *  0 C_H  1 C_P  2 N_P  3 N_D  4 N_A  5 N_DA  6 O_P  7 O_D  8 O_A  9 O_DA
+ * 10 S_P 11 P_P 12 F_H 13 Cl_H 14 Br_H 15 I_H 16 Met_D
+ */
+typedef struct {
+    float x, y, z;       /* Angstrom */
+    int32_t xs_type;     /* 0 .. DSDP_N_XS-1 */
+} dsdp_atom;
+
+/* Search box: nodes per axis n = floor(size/spacing) + 1, centred on centre. */
+typedef struct {
+    float centre[3];
+    float size[3];
+    float spacing;
+} dsdp_box;
+
+typedef struct dsdp_grids_s *dsdp_grids;   /* view over caller-owned device maps */
+
+/*
+ * Ligand torsion tree (Vina's flexible-ligand model, kept by the paper).
+ *   atoms        reference conformation, fragment-contiguous;
+ *   frag_start   [n_frags + 1], frag_start[0] = 0, frag_start[n_frags] = n_atoms;
+ *   frag_parent  [n_frags], -1 for fragment 0 (the root), 0 <= parent < k otherwise;
+ *   axis         [n_frags][2]: for k >= 1 the bond fragment k turns about,
+ *                (parent-side atom, child-side atom); row 0 is ignored;
+ *   bonds        [n_bonds][2]: every covalent bond (used for the 1-2/1-3/1-4
+ *                exclusions of intra-ligand pairs; each axis must be a bond).
+ * Torsion theta_k turns fragment k (k >= 1) about its axis, right-handed.
+ */
+typedef struct {
+    int32_t n_atoms;
+    const dsdp_atom *atoms;
+    int32_t n_frags;
+    const int32_t *frag_start;
+    const int32_t *frag_parent;
+    const int32_t *axis;
+    int32_t n_bonds;
+    const int32_t *bonds;
+} dsdp_ligand;
+
+/* Search constants; the paper leaves these open.  Fill with dsdp_params_default(). */
+typedef struct {
+    uint32_t struct_size;    /* sizeof(dsdp_params) */
+    float temperature;       /* Metropolis temperature (1.2) */
+    float wall_slope;        /* energy per Angstrom outside the box (10) */
+    float rmsd_cluster;      /* output poses differ by more than this heavy-atom RMSD (1.0) */
+    float trans_amp;         /* translation amplitude; rotation amplitude = trans_amp / Rg (2.0) */
+    int32_t bfgs_iters;      /* BFGS iterations per local optimisation (20) */
+    int32_t ls_trials;       /* Armijo trials per iteration (10) */
+    float ls_shrink;         /* step shrink factor per failed trial (0.1) */
+    float armijo_c1;         /* sufficient-decrease constant (1e-4) */
+} dsdp_params;
+
+/* One ranked output pose. */
+typedef struct {
+    float pos[3];
+    float quat[4];                   /* w, x, y, z */
+    float tors[DSDP_MAX_TORSIONS];   /* first n_frags-1 used */
+    float e_total;                   /* search objective: e_inter + e_intra */
+    float e_inter;                   /* ligand-receptor energy, wall included */
+    float e_intra;                   /* intra-ligand energy */
+    float e_wall;                    /* wall part of e_inter */
+    float score;                     /* e_inter / (1 + 0.0585 * n_torsions), Vina's normalisation */
+    int32_t chain;                   /* chain that found it */
+} dsdp_pose;
+
+/* Work counters of one dock call. */
+typedef struct {
+    int64_t pose_evals;              /* energy+gradient evaluations, every line-search trial counted */
+    int64_t local_opts;              /* local optimisations (= chains x steps) */
+    int64_t accepted;                /* Metropolis acceptances */
+    int32_t n_nonfinite;             /* chains whose best energy is not finite (excluded from ranking) */
+    float kernel_ms;                 /* device time of the search and ranking kernels */
+} dsdp_dock_stats;
+
+/* Message of the calling thread's last error ("" if none).  Never NULL. */
+const char *dsdp_last_error(void);
+
+/* Library version string. */
+const char *dsdp_version(void);
+
+/* Default search constants (struct_size set). */
+void dsdp_params_default(dsdp_params *p);
+
+/*
+ * Grid geometry of a box: n[3] nodes per axis, origin[3] = centre - (n-1)*spacing/2.
+ * DSDP_ERR_INVALID_ARG for non-positive or non-finite sizes/spacing.
+ */
+dsdp_status dsdp_grid_dims(const dsdp_box *box, int32_t *n, float *origin);
+
+/*
+ * Bytes of the map buffer for `n_types` maps: n_x*n_y*n_z*n_types*16.  Layout
+ * float4 maps[type][z][y][x] = (E, dE/dx, dE/dy, dE/dz) (Section 2, first
+ * modification: grids that store scores and their gradients).  0 on bad input.
+ */
+size_t dsdp_grids_bytes(const dsdp_box *box, int32_t n_types);
+
+/* Bytes of device workspace dsdp_build_grids needs for n_rec receptor atoms. */
+size_t dsdp_build_grids_workspace_bytes(int32_t n_rec, const dsdp_box *box);
+
+/*
+ * Receptor grid maps (Appendix eq. 1 and its gradient).  For every node m and
+ * every requested XS type t:  E_t(m) = sum_j h(t, type_j, |m - r_j|) and
+ * G_t(m) = sum_j h'(d) (m - r_j)/|m - r_j| over receptor atoms with
+ * |m - r_j| < 8 A, h being Vina's pair energy on the surface distance
+ * d = r - R_t - R_j.
+ *   rec, n_rec        receptor heavy atoms (host, borrowed), n_rec >= 0;
+ *   types, n_types    XS types to map (host), 1..17 distinct; NULL = all 17;
+ *   d_maps            device buffer >= dsdp_grids_bytes(box, n_types);
+ *   d_ws              device workspace >= dsdp_build_grids_workspace_bytes;
+ *   stream            hipStream_t or NULL;
+ *   out               receives a handle (a view of d_maps; release it with
+ *                     dsdp_grids_release; it must not outlive d_maps).
+ * Asynchronous: the maps are ready when `stream` reaches this point.  The host
+ * bins receptor atoms into cells and copies them to d_ws before returning.
+ */
+dsdp_status dsdp_build_grids(const dsdp_atom *rec, int32_t n_rec, const dsdp_box *box, const int32_t *types,
+                             int32_t n_types, void *d_maps, size_t maps_bytes, void *d_ws, size_t ws_bytes,
+                             void *stream, dsdp_grids *out);
+
+/* Free a grid handle (not the device maps).  NULL is ignored. */
+void dsdp_grids_release(dsdp_grids g);
+
+/*
+ * Device workspace bytes for dsdp_dock / dsdp_eval_poses / dsdp_local_opt on
+ * this ligand with up to n_chains chains (or poses).  0 on invalid input.
+ */
+size_t dsdp_dock_workspace_bytes(const dsdp_ligand *lig, int32_t n_chains);
+
+/*
+ * Energies and pose gradients of given poses (a test and benchmark entry of the
+ * search kernel's evaluation: forward kinematics, eq. 2 energy and eq. 4
+ * gradient from the maps, box wall, intra-ligand terms, force/torque
+ * back-propagation).
+ *   d_poses  [n_poses][7 + Nt] device floats;
+ *   d_energy [n_poses][4] device out: (e_total, e_inter incl. wall, e_intra, wall);
+ *   d_grad   [n_poses][6 + Nt] device out;
+ *   d_xyz    nullable [n_poses][n_atoms][3] device out: atom coordinates.
+ * Asynchronous on `stream`.
+ */
+dsdp_status dsdp_eval_poses(dsdp_grids g, const dsdp_ligand *lig, const float *d_poses, int32_t n_poses,
+                            const dsdp_params *prm, float *d_energy, float *d_grad, float *d_xyz, void *d_ws,
+                            size_t ws_bytes, void *stream);
+
+/*
+ * One BFGS local optimisation per given pose (the search kernel's local
+ * optimiser; Armijo backtracking, inverse-BFGS update when y.s > 0).
+ *   d_poses_in / d_poses_out  [n_poses][7 + Nt] device (may alias);
+ *   d_energy                  [n_poses][4] device out (as dsdp_eval_poses);
+ *   d_evals                   nullable [n_poses] int32 device out: evaluations used.
+ * Asynchronous on `stream`.
+ */
+dsdp_status dsdp_local_opt(dsdp_grids g, const dsdp_ligand *lig, const float *d_poses_in, int32_t n_poses,
+                           const dsdp_params *prm, float *d_poses_out, float *d_energy, int32_t *d_evals,
+                           void *d_ws, size_t ws_bytes, void *stream);
+
+/*
+ * Dock one ligand: n_chains independent Monte Carlo chains of n_steps steps
+ * (mutate, BFGS local optimisation, Metropolis), each chain's random numbers
+ * drawn from Philox4x32-10 keyed by `seed` with counters (chain, step, stream,
+ * block), then ranking by e_total and greedy heavy-atom RMSD clustering
+ * (keep a pose if its RMSD to every kept pose exceeds rmsd_cluster), up to top_k.
+ *   prm        nullable (defaults);
+ *   out        host [top_k] ranked poses;  out_xyz nullable host [top_k][n_atoms][3];
+ *   n_out      number of poses written (<= top_k);
+ *   chains_out nullable host [n_chains]: every chain's best pose;
+ *   stats      nullable host: work counters and device time.
+ * Synchronous: returns after the results are on the host.  A chain result
+ * depends only on (seed, chain index, ligand, grids, params): not on n_chains,
+ * on other chains or on launch shape.
+ */
+dsdp_status dsdp_dock(dsdp_grids g, const dsdp_ligand *lig, int32_t n_chains, int32_t n_steps, uint64_t seed,
+                      const dsdp_params *prm, int32_t top_k, void *d_ws, size_t ws_bytes, void *stream,
+                      dsdp_pose *out, float *out_xyz, int32_t *n_out, dsdp_pose *chains_out,
+                      dsdp_dock_stats *stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DSDP_H */

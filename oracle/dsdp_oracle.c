@@ -771,8 +771,11 @@ static void quat_mul(const double *a, const double *b, double *o)
     o[2] = a[0] * b[2] - a[1] * b[3] + a[2] * b[0] + a[3] * b[1];
     o[3] = a[0] * b[3] + a[1] * b[2] - a[2] * b[1] + a[3] * b[0];
 }
+/* into (-pi, pi]; non-finite values pass through, huge ones are reduced first */
 static double wrap_angle(double t)
 {
+    if (!isfinite(t)) return t;
+    if (fabs(t) > 1.0e4) t = fmod(t, 2 * ORC_PI);
     while (t > ORC_PI) t -= 2 * ORC_PI;
     while (t <= -ORC_PI) t += 2 * ORC_PI;
     return t;

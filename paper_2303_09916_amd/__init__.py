@@ -1,0 +1,266 @@
+"""Python binding of libdsdp.so, the MI355X docking library (C ABI in include/dsdp.h).
+
+Argument marshalling only: every function here has the name of the C entry point
+it calls, converts NumPy host arrays and torch device tensors into pointers, and
+raises DsdpError on a non-zero status.  All computation runs in the library's
+HIP kernels; there is no fallback when the library is missing.
+
+Device memory is torch tensors (``torch.empty(nbytes, dtype=torch.uint8,
+device="cuda")``); streams are ``torch.cuda.Stream`` objects or None.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdsdp.so")
+_LIB = None
+
+DSDP_OK = 0
+DSDP_ERR_INVALID_ARG = -1
+DSDP_ERR_UNSUPPORTED = -2
+DSDP_ERR_WORKSPACE_TOO_SMALL = -3
+DSDP_ERR_DEVICE = -4
+MAX_ATOMS = 64
+MAX_TORSIONS = 31
+N_XS = 17
+
+
+class DsdpError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"dsdp status {status}: {msg}")
+        self.status = status
+
+
+class dsdp_atom(C.Structure):
+    _fields_ = [("x", C.c_float), ("y", C.c_float), ("z", C.c_float), ("xs_type", C.c_int32)]
+
+
+class dsdp_box(C.Structure):
+    _fields_ = [("centre", C.c_float * 3), ("size", C.c_float * 3), ("spacing", C.c_float)]
+
+
+class dsdp_ligand(C.Structure):
+    _fields_ = [("n_atoms", C.c_int32), ("atoms", C.POINTER(dsdp_atom)), ("n_frags", C.c_int32),
+                ("frag_start", C.POINTER(C.c_int32)), ("frag_parent", C.POINTER(C.c_int32)),
+                ("axis", C.POINTER(C.c_int32)), ("n_bonds", C.c_int32), ("bonds", C.POINTER(C.c_int32))]
+
+
+class dsdp_params(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("temperature", C.c_float), ("wall_slope", C.c_float),
+                ("rmsd_cluster", C.c_float), ("trans_amp", C.c_float), ("bfgs_iters", C.c_int32),
+                ("ls_trials", C.c_int32), ("ls_shrink", C.c_float), ("armijo_c1", C.c_float)]
+
+
+class dsdp_pose(C.Structure):
+    _fields_ = [("pos", C.c_float * 3), ("quat", C.c_float * 4), ("tors", C.c_float * MAX_TORSIONS),
+                ("e_total", C.c_float), ("e_inter", C.c_float), ("e_intra", C.c_float), ("e_wall", C.c_float),
+                ("score", C.c_float), ("chain", C.c_int32)]
+
+
+class dsdp_dock_stats(C.Structure):
+    _fields_ = [("pose_evals", C.c_int64), ("local_opts", C.c_int64), ("accepted", C.c_int64),
+                ("n_nonfinite", C.c_int32), ("kernel_ms", C.c_float)]
+
+
+_vp = C.c_void_p
+_SIGS = {
+    "dsdp_last_error": (C.c_char_p, []),
+    "dsdp_version": (C.c_char_p, []),
+    "dsdp_params_default": (None, [C.POINTER(dsdp_params)]),
+    "dsdp_grid_dims": (C.c_int32, [C.POINTER(dsdp_box), C.POINTER(C.c_int32), C.POINTER(C.c_float)]),
+    "dsdp_grids_bytes": (C.c_size_t, [C.POINTER(dsdp_box), C.c_int32]),
+    "dsdp_build_grids_workspace_bytes": (C.c_size_t, [C.c_int32, C.POINTER(dsdp_box)]),
+    "dsdp_build_grids": (C.c_int32, [C.POINTER(dsdp_atom), C.c_int32, C.POINTER(dsdp_box), C.POINTER(C.c_int32),
+                                     C.c_int32, _vp, C.c_size_t, _vp, C.c_size_t, _vp, C.POINTER(_vp)]),
+    "dsdp_grids_release": (None, [_vp]),
+    "dsdp_dock_workspace_bytes": (C.c_size_t, [C.POINTER(dsdp_ligand), C.c_int32]),
+    "dsdp_eval_poses": (C.c_int32, [_vp, C.POINTER(dsdp_ligand), _vp, C.c_int32, C.POINTER(dsdp_params), _vp, _vp,
+                                    _vp, _vp, C.c_size_t, _vp]),
+    "dsdp_local_opt": (C.c_int32, [_vp, C.POINTER(dsdp_ligand), _vp, C.c_int32, C.POINTER(dsdp_params), _vp, _vp,
+                                   _vp, _vp, C.c_size_t, _vp]),
+    "dsdp_dock": (C.c_int32, [_vp, C.POINTER(dsdp_ligand), C.c_int32, C.c_int32, C.c_uint64,
+                              C.POINTER(dsdp_params), C.c_int32, _vp, C.c_size_t, _vp, C.POINTER(dsdp_pose),
+                              C.POINTER(C.c_float), C.POINTER(C.c_int32), C.POINTER(dsdp_pose),
+                              C.POINTER(dsdp_dock_stats)]),
+}
+EXPORTED = tuple(_SIGS)
+
+
+def lib():
+    """Load libdsdp.so (built in-tree by build.py).  Raises if it is missing."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run paper_2303_09916_amd/build.py (or __graft_entry__.build())")
+    L = C.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _LIB = L
+    return L
+
+
+def _check(st):
+    if st != DSDP_OK:
+        raise DsdpError(st, lib().dsdp_last_error().decode())
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (None -> NULL)."""
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _nbytes(t):
+    return 0 if t is None else t.numel() * t.element_size()
+
+
+def _stream(s):
+    if s is None:
+        return None
+    return C.c_void_p(s.cuda_stream if hasattr(s, "cuda_stream") else int(s))
+
+
+def _box(box):
+    if isinstance(box, dsdp_box):
+        return box
+    b = dsdp_box()
+    c = np.broadcast_to(np.asarray(box["centre"], dtype=np.float32), (3,))
+    s = np.broadcast_to(np.asarray(box["size"], dtype=np.float32), (3,))
+    for a in range(3):
+        b.centre[a] = float(c[a])
+        b.size[a] = float(s[a])
+    b.spacing = float(np.float32(box["spacing"]))
+    return b
+
+
+def atoms_array(xyz, types):
+    """(n,3) coordinates + (n,) XS types -> ctypes dsdp_atom array."""
+    xyz = np.asarray(xyz, dtype=np.float32).reshape(-1, 3)
+    types = np.asarray(types, dtype=np.int32).reshape(-1)
+    arr = (dsdp_atom * max(len(types), 1))()
+    for i in range(len(types)):
+        arr[i].x, arr[i].y, arr[i].z = (float(v) for v in xyz[i])
+        arr[i].xs_type = int(types[i])
+    return arr
+
+
+class Ligand:
+    """Marshalled dsdp_ligand; keeps its arrays alive."""
+
+    def __init__(self, xyz, types, frag_start, frag_parent, axis, bonds):
+        self.n_atoms = int(np.asarray(types).size)
+        self.n_frags = int(np.asarray(frag_parent).size)
+        self.n_tors = self.n_frags - 1
+        self._atoms = atoms_array(xyz, types)
+        self._fs = np.ascontiguousarray(frag_start, dtype=np.int32)
+        self._fp = np.ascontiguousarray(frag_parent, dtype=np.int32)
+        self._ax = np.ascontiguousarray(axis, dtype=np.int32).reshape(-1)
+        self._bd = np.ascontiguousarray(bonds, dtype=np.int32).reshape(-1)
+        ip = C.POINTER(C.c_int32)
+        self.c = dsdp_ligand(self.n_atoms, self._atoms, self.n_frags, self._fs.ctypes.data_as(ip),
+                             self._fp.ctypes.data_as(ip), self._ax.ctypes.data_as(ip), len(self._bd) // 2,
+                             self._bd.ctypes.data_as(ip))
+
+    @classmethod
+    def from_synth(cls, lig):
+        return cls(lig.xyz, lig.types, lig.frag_start, lig.frag_parent, lig.axis, lig.bonds)
+
+    @property
+    def nx(self):
+        return 7 + self.n_tors
+
+    @property
+    def D(self):
+        return 6 + self.n_tors
+
+
+def dsdp_version():
+    return lib().dsdp_version().decode()
+
+
+def dsdp_last_error():
+    return lib().dsdp_last_error().decode()
+
+
+def dsdp_params_default(**over):
+    p = dsdp_params()
+    lib().dsdp_params_default(C.byref(p))
+    for k, v in over.items():
+        setattr(p, k, v)
+    return p
+
+
+def dsdp_grid_dims(box):
+    n = (C.c_int32 * 3)()
+    o = (C.c_float * 3)()
+    _check(lib().dsdp_grid_dims(C.byref(_box(box)), n, o))
+    return tuple(n), np.array(list(o), dtype=np.float32)
+
+
+def dsdp_grids_bytes(box, n_types):
+    return int(lib().dsdp_grids_bytes(C.byref(_box(box)), int(n_types)))
+
+
+def dsdp_build_grids_workspace_bytes(n_rec, box):
+    return int(lib().dsdp_build_grids_workspace_bytes(int(n_rec), C.byref(_box(box))))
+
+
+def dsdp_build_grids(rec_xyz, rec_types, box, types, d_maps, d_ws, stream=None):
+    """Returns an opaque grids handle (release with dsdp_grids_release)."""
+    atoms = atoms_array(rec_xyz, rec_types)
+    n_rec = int(np.asarray(rec_types).size)
+    if types is None:
+        tp, nt = None, N_XS
+    else:
+        tarr = np.ascontiguousarray(types, dtype=np.int32)
+        tp, nt = tarr.ctypes.data_as(C.POINTER(C.c_int32)), len(tarr)
+    h = C.c_void_p()
+    _check(lib().dsdp_build_grids(atoms, n_rec, C.byref(_box(box)), tp, nt, _ptr(d_maps), _nbytes(d_maps),
+                                  _ptr(d_ws), _nbytes(d_ws), _stream(stream), C.byref(h)))
+    return h
+
+
+def dsdp_grids_release(h):
+    lib().dsdp_grids_release(h)
+
+
+def dsdp_dock_workspace_bytes(lig, n_chains):
+    return int(lib().dsdp_dock_workspace_bytes(C.byref(lig.c), int(n_chains)))
+
+
+def dsdp_eval_poses(grids, lig, d_poses, n_poses, d_energy, d_grad, d_xyz, d_ws, params=None, stream=None):
+    _check(lib().dsdp_eval_poses(grids, C.byref(lig.c), _ptr(d_poses), int(n_poses),
+                                 C.byref(params) if params is not None else None, _ptr(d_energy), _ptr(d_grad),
+                                 _ptr(d_xyz), _ptr(d_ws), _nbytes(d_ws), _stream(stream)))
+
+
+def dsdp_local_opt(grids, lig, d_poses_in, n_poses, d_poses_out, d_energy, d_evals, d_ws, params=None, stream=None):
+    _check(lib().dsdp_local_opt(grids, C.byref(lig.c), _ptr(d_poses_in), int(n_poses),
+                                C.byref(params) if params is not None else None, _ptr(d_poses_out),
+                                _ptr(d_energy), _ptr(d_evals), _ptr(d_ws), _nbytes(d_ws), _stream(stream)))
+
+
+def dsdp_dock(grids, lig, n_chains, n_steps, seed, top_k, d_ws, params=None, stream=None, want_xyz=True,
+              want_chains=False):
+    """Returns (poses list[dsdp_pose], xyz ndarray [n_out, n_atoms, 3] or None, chains or None, stats)."""
+    out = (dsdp_pose * max(top_k, 1))()
+    xyz = np.zeros((max(top_k, 1), lig.n_atoms, 3), dtype=np.float32) if want_xyz else None
+    n_out = C.c_int32(0)
+    chains = (dsdp_pose * n_chains)() if want_chains else None
+    stats = dsdp_dock_stats()
+    _check(lib().dsdp_dock(grids, C.byref(lig.c), int(n_chains), int(n_steps), C.c_uint64(int(seed)),
+                           C.byref(params) if params is not None else None, int(top_k), _ptr(d_ws), _nbytes(d_ws),
+                           _stream(stream), out,
+                           xyz.ctypes.data_as(C.POINTER(C.c_float)) if want_xyz else None, C.byref(n_out),
+                           chains, C.byref(stats)))
+    n = n_out.value
+    return list(out)[:n], (xyz[:n] if want_xyz else None), (list(chains) if want_chains else None), stats
+
+
+def pose_array(p, n_tors):
+    """dsdp_pose -> pose vector [p(3), q(4), theta(n_tors)] (float64)."""
+    return np.array(list(p.pos) + list(p.quat) + list(p.tors)[:n_tors], dtype=np.float64)

@@ -1,0 +1,673 @@
+// Host side of libdsdp.so: the C ABI declared in include/dsdp.h.
+//
+// Validates inputs, prepares the receptor (cell binning) and the ligand (torsion
+// tree, intra-ligand pair list, packed blob) on the host -- the paper's "copies
+// are initialised and packaged on the CPU" step (Section 2, parallelisation
+// paragraph; Figure 4) -- uploads them, launches the gfx950 kernels and turns
+// the ranked chain results into output poses.
+#include "../../include/dsdp.h"
+#include "dsdp_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace dsdp;
+
+struct dsdp_grids_s {
+    GridView view;
+    dsdp_box box;
+    int types[kNXS];
+    size_t bytes;
+};
+
+namespace {
+
+thread_local std::string g_error;
+
+dsdp_status fail(dsdp_status code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return code;
+}
+
+dsdp_status hip_fail(hipError_t e, const char *where)
+{
+    return fail(DSDP_ERR_DEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, where)                   \
+    do {                                       \
+        hipError_t e_ = (expr);                \
+        if (e_ != hipSuccess) return hip_fail(e_, where); \
+    } while (0)
+
+constexpr size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+bool finite3(float a, float b, float c) { return std::isfinite(a) && std::isfinite(b) && std::isfinite(c); }
+
+dsdp_status geometry(const dsdp_box *box, int n[3], double origin[3])
+{
+    if (!box) return fail(DSDP_ERR_INVALID_ARG, "box is NULL");
+    if (!(std::isfinite(box->spacing) && box->spacing >= 0.05f && box->spacing <= 4.0f))
+        return fail(DSDP_ERR_INVALID_ARG, "box spacing %g outside [0.05, 4] A", (double)box->spacing);
+    for (int a = 0; a < 3; a++) {
+        if (!std::isfinite(box->centre[a]) || !std::isfinite(box->size[a]))
+            return fail(DSDP_ERR_INVALID_ARG, "box centre/size not finite");
+        if (box->size[a] < box->spacing)
+            return fail(DSDP_ERR_INVALID_ARG, "box size %g smaller than the spacing", (double)box->size[a]);
+        const double nn = std::floor((double)box->size[a] / (double)box->spacing) + 1.0;
+        if (nn > 2048) return fail(DSDP_ERR_UNSUPPORTED, "more than 2048 nodes per axis");
+        n[a] = (int)nn;
+        origin[a] = (double)box->centre[a] - 0.5 * (n[a] - 1) * (double)box->spacing;
+    }
+    return DSDP_OK;
+}
+
+// cell binning geometry: the box grown by the cutoff, cell edge chosen so that a
+// 8x8x4 node tile plus the cutoff spans at most 9 cells per axis
+struct CellGeom {
+    int cn[3];
+    float clo[3];
+    float cell;
+    long ncell;
+};
+CellGeom cell_geometry(const int n[3], const double origin[3], double h)
+{
+    CellGeom c;
+    c.cell = (float)std::max(4.0, (8.0 * h + 2.0 * kCutoff) / 9.0);
+    c.ncell = 1;
+    for (int a = 0; a < 3; a++) {
+        const double lo = origin[a] - kCutoff, hi = origin[a] + (n[a] - 1) * h + kCutoff;
+        c.clo[a] = (float)lo;
+        c.cn[a] = (int)std::floor((hi - lo) / c.cell) + 1;
+        c.ncell *= c.cn[a];
+    }
+    return c;
+}
+
+// ---------------------------------------------------------------- ligand preparation
+
+struct Prepared {
+    LigHeader h;
+    std::vector<uint32_t> blob;
+    std::vector<int> map_index;   // per atom
+};
+
+dsdp_status validate_ligand(const dsdp_ligand *lig)
+{
+    if (!lig) return fail(DSDP_ERR_INVALID_ARG, "ligand is NULL");
+    if (lig->n_atoms < 1) return fail(DSDP_ERR_INVALID_ARG, "ligand has %d atoms", lig->n_atoms);
+    if (lig->n_atoms > kMaxAtoms) return fail(DSDP_ERR_UNSUPPORTED, "ligand has %d atoms (max %d)", lig->n_atoms, kMaxAtoms);
+    if (lig->n_frags < 1) return fail(DSDP_ERR_INVALID_ARG, "ligand has %d fragments", lig->n_frags);
+    if (lig->n_frags > kMaxFrags)
+        return fail(DSDP_ERR_UNSUPPORTED, "ligand has %d torsions (max %d)", lig->n_frags - 1, kMaxTors);
+    if (!lig->atoms || !lig->frag_start || !lig->frag_parent || (lig->n_frags > 1 && !lig->axis))
+        return fail(DSDP_ERR_INVALID_ARG, "ligand array is NULL");
+    if (lig->n_bonds < 0 || (lig->n_bonds > 0 && !lig->bonds)) return fail(DSDP_ERR_INVALID_ARG, "bad bond list");
+    const int na = lig->n_atoms, nf = lig->n_frags;
+    for (int i = 0; i < na; i++) {
+        const dsdp_atom &a = lig->atoms[i];
+        if (!finite3(a.x, a.y, a.z)) return fail(DSDP_ERR_INVALID_ARG, "ligand atom %d not finite", i);
+        if (a.xs_type < 0 || a.xs_type >= kNXS) return fail(DSDP_ERR_INVALID_ARG, "ligand atom %d type %d", i, a.xs_type);
+    }
+    if (lig->frag_start[0] != 0 || lig->frag_start[nf] != na)
+        return fail(DSDP_ERR_INVALID_ARG, "frag_start must run from 0 to n_atoms");
+    for (int k = 0; k < nf; k++) {
+        if (lig->frag_start[k + 1] <= lig->frag_start[k]) return fail(DSDP_ERR_INVALID_ARG, "fragment %d is empty", k);
+        const int p = lig->frag_parent[k];
+        if (k == 0 ? p != -1 : (p < 0 || p >= k))
+            return fail(DSDP_ERR_INVALID_ARG, "fragment %d has parent %d (need -1 for the root, else < k)", k, p);
+    }
+    std::vector<int> frag_of(na);
+    for (int k = 0; k < nf; k++)
+        for (int i = lig->frag_start[k]; i < lig->frag_start[k + 1]; i++) frag_of[i] = k;
+    std::vector<std::vector<int>> adj(na);
+    for (int b = 0; b < lig->n_bonds; b++) {
+        const int i = lig->bonds[2 * b], j = lig->bonds[2 * b + 1];
+        if (i < 0 || i >= na || j < 0 || j >= na || i == j) return fail(DSDP_ERR_INVALID_ARG, "bond %d invalid", b);
+        adj[i].push_back(j);
+        adj[j].push_back(i);
+    }
+    for (int k = 1; k < nf; k++) {
+        const int a = lig->axis[2 * k], b = lig->axis[2 * k + 1];
+        if (a < 0 || a >= na || b < 0 || b >= na || frag_of[a] != lig->frag_parent[k] || frag_of[b] != k)
+            return fail(DSDP_ERR_INVALID_ARG, "fragment %d axis (%d, %d) must join its parent to it", k, a, b);
+        if (std::find(adj[a].begin(), adj[a].end(), b) == adj[a].end())
+            return fail(DSDP_ERR_INVALID_ARG, "fragment %d axis (%d, %d) is not a bond", k, a, b);
+        const float dx = lig->atoms[b].x - lig->atoms[a].x, dy = lig->atoms[b].y - lig->atoms[a].y,
+                    dz = lig->atoms[b].z - lig->atoms[a].z;
+        if (dx * dx + dy * dy + dz * dz < 1e-6f) return fail(DSDP_ERR_INVALID_ARG, "fragment %d axis has zero length", k);
+    }
+    return DSDP_OK;
+}
+
+// map_of_type == nullptr: map indices are left 0 (used only for sizing)
+dsdp_status prepare_ligand(const dsdp_ligand *lig, const int *map_of_type, Prepared &out)
+{
+    dsdp_status st = validate_ligand(lig);
+    if (st) return st;
+    const int na = lig->n_atoms, nf = lig->n_frags;
+    std::vector<int> frag_of(na);
+    for (int k = 0; k < nf; k++)
+        for (int i = lig->frag_start[k]; i < lig->frag_start[k + 1]; i++) frag_of[i] = k;
+    std::vector<double> ref(3 * na);
+    for (int i = 0; i < na; i++) {
+        ref[3 * i] = lig->atoms[i].x;
+        ref[3 * i + 1] = lig->atoms[i].y;
+        ref[3 * i + 2] = lig->atoms[i].z;
+    }
+    // root centre and gyration radius
+    double c0[3] = {0, 0, 0};
+    const int n0 = lig->frag_start[1];
+    for (int i = 0; i < n0; i++)
+        for (int a = 0; a < 3; a++) c0[a] += ref[3 * i + a] / n0;
+    double s2 = 0;
+    for (int i = 0; i < na; i++)
+        for (int a = 0; a < 3; a++) s2 += (ref[3 * i + a] - c0[a]) * (ref[3 * i + a] - c0[a]);
+    const double rg = std::sqrt(s2 / na);
+    auto frag_origin = [&](int k, double o[3]) {
+        if (k == 0)
+            for (int a = 0; a < 3; a++) o[a] = c0[a];
+        else
+            for (int a = 0; a < 3; a++) o[a] = ref[3 * lig->axis[2 * k + 1] + a];
+    };
+    // bond-graph distances -> intra pairs (different fragments, > 3 bonds apart)
+    std::vector<std::vector<int>> adj(na);
+    for (int b = 0; b < lig->n_bonds; b++) {
+        adj[lig->bonds[2 * b]].push_back(lig->bonds[2 * b + 1]);
+        adj[lig->bonds[2 * b + 1]].push_back(lig->bonds[2 * b]);
+    }
+    std::vector<uint32_t> pairs;
+    std::vector<float> rsum;
+    for (int i = 0; i < na; i++) {
+        std::vector<int> dist(na, 1 << 20), queue;
+        dist[i] = 0;
+        queue.push_back(i);
+        for (size_t q = 0; q < queue.size(); q++)
+            for (int v : adj[queue[q]])
+                if (dist[v] > dist[queue[q]] + 1) {
+                    dist[v] = dist[queue[q]] + 1;
+                    queue.push_back(v);
+                }
+        for (int j = i + 1; j < na; j++)
+            if (frag_of[i] != frag_of[j] && dist[j] > 3) {
+                const int ti = lig->atoms[i].xs_type, tj = lig->atoms[j].xs_type;
+                pairs.push_back((uint32_t)i | ((uint32_t)j << 8) | (pair_flags(ti, tj) << 16));
+                rsum.push_back(xs_radius(ti) + xs_radius(tj));
+            }
+    }
+    const int np = (int)pairs.size();
+    // per-atom pair lists (pair order)
+    std::vector<std::vector<uint32_t>> lists(na);
+    for (int p = 0; p < np; p++) {
+        const int i = pairs[p] & 255u, j = (pairs[p] >> 8) & 255u;
+        lists[i].push_back((uint32_t)j | ((uint32_t)p << 8));
+        lists[j].push_back((uint32_t)i | ((uint32_t)p << 8));
+    }
+    // depth and subtree masks
+    int max_depth = 0;
+    std::vector<int> depth(nf, 0);
+    for (int k = 1; k < nf; k++) {
+        depth[k] = depth[lig->frag_parent[k]] + 1;
+        max_depth = std::max(max_depth, depth[k]);
+    }
+    std::vector<uint32_t> sub(nf, 0);
+    for (int m = 0; m < nf; m++)
+        for (int x = m; x >= 0; x = lig->frag_parent[x]) sub[x] |= 1u << m;
+
+    LigHeader h;
+    std::memset(&h, 0, sizeof h);
+    h.n_atoms = na;
+    h.n_frags = nf;
+    h.n_tors = nf - 1;
+    h.n_pairs = np;
+    h.max_depth = max_depth;
+    h.rg = (float)rg;
+    int w = kHeaderWords;
+    auto take = [&](int words, int align) {
+        w = (w + align - 1) / align * align;
+        const int o = w;
+        w += words;
+        return o;
+    };
+    h.off_atom = take(4 * na, 4);
+    h.off_frag_u = take(4 * nf, 4);
+    h.off_frag_off = take(4 * nf, 4);
+    h.off_atom_frag = take(na, 1);
+    h.off_frag_start = take(nf + 1, 1);
+    h.off_pair = take(np, 1);
+    h.off_pair_rsum = take(np, 1);
+    h.off_csr_start = take(na + 1, 1);
+    h.off_csr = take(2 * np, 1);
+    h.total_words = (w + 3) / 4 * 4;
+
+    std::vector<uint32_t> blob((size_t)h.total_words, 0u);
+    std::memcpy(blob.data(), &h, sizeof h);
+    auto fput = [&](int off, float v) { std::memcpy(&blob[(size_t)off], &v, 4); };
+    out.map_index.assign(na, 0);
+    for (int i = 0; i < na; i++) {
+        double o[3];
+        frag_origin(frag_of[i], o);
+        const int t = lig->atoms[i].xs_type;
+        const int mi = map_of_type ? map_of_type[t] : 0;
+        if (mi < 0) return fail(DSDP_ERR_INVALID_ARG, "no map for ligand atom %d of XS type %d", i, t);
+        out.map_index[i] = mi;
+        for (int a = 0; a < 3; a++) fput(h.off_atom + 4 * i + a, (float)(ref[3 * i + a] - o[a]));
+        blob[(size_t)h.off_atom + 4 * i + 3] = (uint32_t)mi;
+        blob[(size_t)h.off_atom_frag + i] = (uint32_t)frag_of[i];
+    }
+    for (int k = 0; k < nf; k++) {
+        if (k == 0) {
+            for (int a = 0; a < 3; a++) fput(h.off_frag_u + a, 0.f);
+            for (int a = 0; a < 3; a++) fput(h.off_frag_off + a, 0.f);
+            blob[(size_t)h.off_frag_u + 3] = (uint32_t)-1;
+        } else {
+            const int ia = lig->axis[2 * k], ib = lig->axis[2 * k + 1];
+            double u[3], nrm = 0, op[3];
+            for (int a = 0; a < 3; a++) {
+                u[a] = ref[3 * ib + a] - ref[3 * ia + a];
+                nrm += u[a] * u[a];
+            }
+            nrm = std::sqrt(nrm);
+            frag_origin(lig->frag_parent[k], op);
+            for (int a = 0; a < 3; a++) {
+                fput(h.off_frag_u + 4 * k + a, (float)(u[a] / nrm));
+                fput(h.off_frag_off + 4 * k + a, (float)(ref[3 * ib + a] - op[a]));
+            }
+            blob[(size_t)h.off_frag_u + 4 * k + 3] = (uint32_t)lig->frag_parent[k];
+        }
+        blob[(size_t)h.off_frag_off + 4 * k + 3] = sub[k];
+    }
+    for (int k = 0; k <= nf; k++) blob[(size_t)h.off_frag_start + k] = (uint32_t)lig->frag_start[k];
+    for (int p = 0; p < np; p++) {
+        blob[(size_t)h.off_pair + p] = pairs[p];
+        fput(h.off_pair_rsum + p, rsum[p]);
+    }
+    int e = 0;
+    for (int i = 0; i < na; i++) {
+        blob[(size_t)h.off_csr_start + i] = (uint32_t)e;
+        for (uint32_t v : lists[i]) blob[(size_t)h.off_csr + e++] = v;
+    }
+    blob[(size_t)h.off_csr_start + na] = (uint32_t)e;
+    out.h = h;
+    out.blob.swap(blob);
+    return DSDP_OK;
+}
+
+SearchParams to_search(const dsdp_params *p)
+{
+    dsdp_params d;
+    dsdp_params_default(&d);
+    if (!p) p = &d;
+    SearchParams s;
+    s.temperature = p->temperature;
+    s.wall_slope = p->wall_slope;
+    s.rmsd_cluster = p->rmsd_cluster;
+    s.trans_amp = p->trans_amp;
+    s.bfgs_iters = p->bfgs_iters;
+    s.ls_trials = p->ls_trials;
+    s.ls_shrink = p->ls_shrink;
+    s.armijo_c1 = p->armijo_c1;
+    return s;
+}
+
+dsdp_status check_params(const dsdp_params *p)
+{
+    if (!p) return DSDP_OK;
+    if (p->struct_size != sizeof(dsdp_params)) return fail(DSDP_ERR_INVALID_ARG, "params.struct_size mismatch");
+    if (!(p->temperature > 0) || !(p->wall_slope >= 0) || !(p->rmsd_cluster >= 0) || !(p->trans_amp >= 0) ||
+        p->bfgs_iters < 0 || p->ls_trials < 1 || !(p->ls_shrink > 0 && p->ls_shrink < 1) || !(p->armijo_c1 >= 0))
+        return fail(DSDP_ERR_INVALID_ARG, "search parameter out of range");
+    return DSDP_OK;
+}
+
+// workspace layout of the search calls
+struct SearchWs {
+    size_t blob, records, xyz, sel, total;
+};
+SearchWs search_ws(const LigHeader &h, int n)
+{
+    SearchWs w;
+    size_t o = 0;
+    w.blob = o; o += align256((size_t)h.total_words * 4);
+    w.records = o; o += align256((size_t)n * kRecWords * 4);
+    w.xyz = o; o += align256((size_t)n * h.n_atoms * 16);
+    w.sel = o; o += align256((size_t)(n + 1) * 4);
+    w.total = o;
+    return w;
+}
+
+dsdp_status upload_blob(const Prepared &pl, char *d_ws, hipStream_t stream)
+{
+    HIP_TRY(hipMemcpyAsync(d_ws, pl.blob.data(), pl.blob.size() * 4, hipMemcpyHostToDevice, stream), "ligand upload");
+    // the host blob is freed when the caller returns: wait for the copy
+    HIP_TRY(hipStreamSynchronize(stream), "ligand upload");
+    return DSDP_OK;
+}
+
+bool aligned256(const void *p) { return ((uintptr_t)p & 255u) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+const char *dsdp_last_error(void) { return g_error.c_str(); }
+
+const char *dsdp_version(void) { return "dsdp-mi355x 0.1 (gfx950)"; }
+
+void dsdp_params_default(dsdp_params *p)
+{
+    if (!p) return;
+    p->struct_size = sizeof(dsdp_params);
+    p->temperature = 1.2f;
+    p->wall_slope = 10.0f;
+    p->rmsd_cluster = 1.0f;
+    p->trans_amp = 2.0f;
+    p->bfgs_iters = 20;
+    p->ls_trials = 10;
+    p->ls_shrink = 0.1f;
+    p->armijo_c1 = 1e-4f;
+}
+
+dsdp_status dsdp_grid_dims(const dsdp_box *box, int32_t *n, float *origin)
+{
+    int nn[3];
+    double o[3];
+    dsdp_status st = geometry(box, nn, o);
+    if (st) return st;
+    for (int a = 0; a < 3; a++) {
+        if (n) n[a] = nn[a];
+        if (origin) origin[a] = (float)o[a];
+    }
+    return DSDP_OK;
+}
+
+size_t dsdp_grids_bytes(const dsdp_box *box, int32_t n_types)
+{
+    int n[3];
+    double o[3];
+    if (n_types < 1 || n_types > kNXS || geometry(box, n, o)) return 0;
+    return (size_t)n[0] * n[1] * n[2] * (size_t)n_types * 16;
+}
+
+size_t dsdp_build_grids_workspace_bytes(int32_t n_rec, const dsdp_box *box)
+{
+    int n[3];
+    double o[3];
+    if (n_rec < 0 || geometry(box, n, o)) return 0;
+    const CellGeom c = cell_geometry(n, o, box->spacing);
+    return align256((size_t)std::max(n_rec, 1) * 16) + align256((size_t)(c.ncell + 1) * 4);
+}
+
+dsdp_status dsdp_build_grids(const dsdp_atom *rec, int32_t n_rec, const dsdp_box *box, const int32_t *types,
+                             int32_t n_types, void *d_maps, size_t maps_bytes, void *d_ws, size_t ws_bytes,
+                             void *stream, dsdp_grids *out)
+{
+    if (!out) return fail(DSDP_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int n[3];
+    double origin[3];
+    dsdp_status st = geometry(box, n, origin);
+    if (st) return st;
+    if (n_rec < 0 || (n_rec > 0 && !rec)) return fail(DSDP_ERR_INVALID_ARG, "bad receptor array");
+    int tl[kNXS];
+    if (!types) {
+        n_types = kNXS;
+        for (int t = 0; t < kNXS; t++) tl[t] = t;
+    } else {
+        if (n_types < 1 || n_types > kNXS) return fail(DSDP_ERR_INVALID_ARG, "n_types %d outside 1..17", n_types);
+        for (int t = 0; t < n_types; t++) {
+            if (types[t] < 0 || types[t] >= kNXS) return fail(DSDP_ERR_INVALID_ARG, "map type %d invalid", types[t]);
+            for (int u = 0; u < t; u++)
+                if (types[u] == types[t]) return fail(DSDP_ERR_INVALID_ARG, "map type %d repeated", types[t]);
+            tl[t] = types[t];
+        }
+    }
+    for (int j = 0; j < n_rec; j++) {
+        if (!finite3(rec[j].x, rec[j].y, rec[j].z)) return fail(DSDP_ERR_INVALID_ARG, "receptor atom %d not finite", j);
+        if (rec[j].xs_type < 0 || rec[j].xs_type >= kNXS)
+            return fail(DSDP_ERR_INVALID_ARG, "receptor atom %d type %d", j, rec[j].xs_type);
+    }
+    const size_t need = dsdp_grids_bytes(box, n_types);
+    if (!d_maps || maps_bytes < need)
+        return fail(DSDP_ERR_WORKSPACE_TOO_SMALL, "maps need %zu bytes, got %zu", need, maps_bytes);
+    const size_t wneed = dsdp_build_grids_workspace_bytes(n_rec, box);
+    if (!d_ws || ws_bytes < wneed)
+        return fail(DSDP_ERR_WORKSPACE_TOO_SMALL, "workspace needs %zu bytes, got %zu", wneed, ws_bytes);
+    if (!aligned256(d_maps) || !aligned256(d_ws)) return fail(DSDP_ERR_INVALID_ARG, "device buffers must be 256-byte aligned");
+
+    // receptor prep: keep atoms within the cutoff of the box, counting sort by cell
+    const CellGeom cg = cell_geometry(n, origin, box->spacing);
+    std::vector<int> key;
+    std::vector<int> keep;
+    key.reserve(n_rec);
+    keep.reserve(n_rec);
+    for (int j = 0; j < n_rec; j++) {
+        const double p[3] = {rec[j].x, rec[j].y, rec[j].z};
+        int c[3];
+        bool in = true;
+        for (int a = 0; a < 3; a++) {
+            const double lo = origin[a] - kCutoff, hi = origin[a] + (n[a] - 1) * (double)box->spacing + kCutoff;
+            if (p[a] < lo || p[a] > hi) in = false;
+            c[a] = std::min(cg.cn[a] - 1, std::max(0, (int)std::floor((p[a] - cg.clo[a]) / cg.cell)));
+        }
+        if (!in) continue;
+        keep.push_back(j);
+        key.push_back((c[2] * cg.cn[1] + c[1]) * cg.cn[0] + c[0]);
+    }
+    std::vector<int> start((size_t)cg.ncell + 1, 0);
+    for (int k : key) start[(size_t)k + 1]++;
+    for (long c = 0; c < cg.ncell; c++) start[(size_t)c + 1] += start[(size_t)c];
+    std::vector<int> fill(start.begin(), start.end() - 1);
+    std::vector<float4> sorted(std::max<size_t>(keep.size(), 1));
+    for (size_t q = 0; q < keep.size(); q++) {
+        const dsdp_atom &a = rec[keep[q]];
+        float4 v;
+        v.x = a.x; v.y = a.y; v.z = a.z;
+        std::memcpy(&v.w, &a.xs_type, 4);
+        sorted[(size_t)fill[(size_t)key[q]]++] = v;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    char *ws = (char *)d_ws;
+    float4 *d_atoms = (float4 *)ws;
+    int *d_start = (int *)(ws + align256((size_t)std::max(n_rec, 1) * 16));
+    HIP_TRY(hipMemcpyAsync(d_atoms, sorted.data(), keep.size() * sizeof(float4), hipMemcpyHostToDevice, s), "receptor upload");
+    HIP_TRY(hipMemcpyAsync(d_start, start.data(), start.size() * sizeof(int), hipMemcpyHostToDevice, s), "cell upload");
+    HIP_TRY(hipStreamSynchronize(s), "receptor upload");
+
+    dsdp_grids g = new dsdp_grids_s();
+    g->box = *box;
+    g->bytes = need;
+    g->view.maps = (const float4 *)d_maps;
+    for (int a = 0; a < 3; a++) {
+        g->view.n[a] = n[a];
+        g->view.origin[a] = (float)origin[a];
+    }
+    g->view.h = box->spacing;
+    g->view.inv_h = 1.0f / box->spacing;
+    g->view.T = n_types;
+    for (int t = 0; t < kNXS; t++) g->view.map_of_type[t] = -1;
+    for (int t = 0; t < n_types; t++) {
+        g->view.map_of_type[tl[t]] = t;
+        g->types[t] = tl[t];
+    }
+    hipError_t e = launch_grid_build(d_atoms, d_start, cg.cn, cg.clo, cg.cell, g->view, tl, (float4 *)d_maps, s);
+    if (e != hipSuccess) {
+        delete g;
+        return hip_fail(e, "grid build launch");
+    }
+    *out = g;
+    return DSDP_OK;
+}
+
+void dsdp_grids_release(dsdp_grids g) { delete g; }
+
+size_t dsdp_dock_workspace_bytes(const dsdp_ligand *lig, int32_t n_chains)
+{
+    Prepared pl;
+    if (n_chains < 1 || prepare_ligand(lig, nullptr, pl)) return 0;
+    return search_ws(pl.h, n_chains).total;
+}
+
+dsdp_status dsdp_eval_poses(dsdp_grids g, const dsdp_ligand *lig, const float *d_poses, int32_t n_poses,
+                            const dsdp_params *prm, float *d_energy, float *d_grad, float *d_xyz, void *d_ws,
+                            size_t ws_bytes, void *stream)
+{
+    if (!g) return fail(DSDP_ERR_INVALID_ARG, "grids handle is NULL");
+    if (n_poses < 0) return fail(DSDP_ERR_INVALID_ARG, "n_poses < 0");
+    if (n_poses > 0 && (!d_poses || !d_energy || !d_grad)) return fail(DSDP_ERR_INVALID_ARG, "device array is NULL");
+    dsdp_status st = check_params(prm);
+    if (st) return st;
+    Prepared pl;
+    st = prepare_ligand(lig, g->view.map_of_type, pl);
+    if (st) return st;
+    const SearchWs w = search_ws(pl.h, std::max(n_poses, 1));
+    if (!d_ws || ws_bytes < w.total) return fail(DSDP_ERR_WORKSPACE_TOO_SMALL, "workspace needs %zu bytes", w.total);
+    if (!aligned256(d_ws)) return fail(DSDP_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    if (n_poses == 0) return DSDP_OK;
+    hipStream_t s = (hipStream_t)stream;
+    char *ws = (char *)d_ws;
+    st = upload_blob(pl, ws + w.blob, s);
+    if (st) return st;
+    HIP_TRY(launch_eval((const uint32_t *)(ws + w.blob), pl.h.total_words, pl.h, g->view, to_search(prm), d_poses,
+                        n_poses, d_energy, d_grad, d_xyz, s),
+            "eval launch");
+    return DSDP_OK;
+}
+
+dsdp_status dsdp_local_opt(dsdp_grids g, const dsdp_ligand *lig, const float *d_poses_in, int32_t n_poses,
+                           const dsdp_params *prm, float *d_poses_out, float *d_energy, int32_t *d_evals,
+                           void *d_ws, size_t ws_bytes, void *stream)
+{
+    if (!g) return fail(DSDP_ERR_INVALID_ARG, "grids handle is NULL");
+    if (n_poses < 0) return fail(DSDP_ERR_INVALID_ARG, "n_poses < 0");
+    if (n_poses > 0 && (!d_poses_in || !d_poses_out || !d_energy))
+        return fail(DSDP_ERR_INVALID_ARG, "device array is NULL");
+    dsdp_status st = check_params(prm);
+    if (st) return st;
+    Prepared pl;
+    st = prepare_ligand(lig, g->view.map_of_type, pl);
+    if (st) return st;
+    const SearchWs w = search_ws(pl.h, std::max(n_poses, 1));
+    if (!d_ws || ws_bytes < w.total) return fail(DSDP_ERR_WORKSPACE_TOO_SMALL, "workspace needs %zu bytes", w.total);
+    if (!aligned256(d_ws)) return fail(DSDP_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    if (n_poses == 0) return DSDP_OK;
+    hipStream_t s = (hipStream_t)stream;
+    char *ws = (char *)d_ws;
+    st = upload_blob(pl, ws + w.blob, s);
+    if (st) return st;
+    HIP_TRY(launch_local_opt((const uint32_t *)(ws + w.blob), pl.h.total_words, pl.h, g->view, to_search(prm),
+                             d_poses_in, n_poses, d_poses_out, d_energy, d_evals, s),
+            "local-opt launch");
+    return DSDP_OK;
+}
+
+dsdp_status dsdp_dock(dsdp_grids g, const dsdp_ligand *lig, int32_t n_chains, int32_t n_steps, uint64_t seed,
+                      const dsdp_params *prm, int32_t top_k, void *d_ws, size_t ws_bytes, void *stream,
+                      dsdp_pose *out, float *out_xyz, int32_t *n_out, dsdp_pose *chains_out,
+                      dsdp_dock_stats *stats)
+{
+    if (n_out) *n_out = 0;
+    if (!g) return fail(DSDP_ERR_INVALID_ARG, "grids handle is NULL");
+    if (n_chains < 1) return fail(DSDP_ERR_INVALID_ARG, "n_chains %d < 1", n_chains);
+    if (n_chains > 65536) return fail(DSDP_ERR_UNSUPPORTED, "n_chains %d > 65536", n_chains);
+    if (n_steps < 0) return fail(DSDP_ERR_INVALID_ARG, "n_steps < 0");
+    if (top_k < 0 || top_k > n_chains) return fail(DSDP_ERR_INVALID_ARG, "top_k %d outside 0..n_chains", top_k);
+    if (top_k > 0 && (!out || !n_out)) return fail(DSDP_ERR_INVALID_ARG, "out/n_out is NULL");
+    dsdp_status st = check_params(prm);
+    if (st) return st;
+    Prepared pl;
+    st = prepare_ligand(lig, g->view.map_of_type, pl);
+    if (st) return st;
+    const SearchWs w = search_ws(pl.h, n_chains);
+    if (!d_ws || ws_bytes < w.total) return fail(DSDP_ERR_WORKSPACE_TOO_SMALL, "workspace needs %zu bytes", w.total);
+    if (!aligned256(d_ws)) return fail(DSDP_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    const SearchParams sp = to_search(prm);
+    hipStream_t s = (hipStream_t)stream;
+    char *ws = (char *)d_ws;
+    st = upload_blob(pl, ws + w.blob, s);
+    if (st) return st;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (stats) {
+        HIP_TRY(hipEventCreate(&ev0), "event");
+        HIP_TRY(hipEventCreate(&ev1), "event");
+        HIP_TRY(hipEventRecord(ev0, s), "event");
+    }
+    float *rec = (float *)(ws + w.records);
+    float4 *bxyz = (float4 *)(ws + w.xyz);
+    int *sel = (int *)(ws + w.sel);
+    HIP_TRY(launch_dock((const uint32_t *)(ws + w.blob), pl.h.total_words, pl.h, g->view, sp, n_chains, n_steps, seed,
+                        rec, bxyz, s),
+            "dock launch");
+    HIP_TRY(launch_rank(rec, bxyz, n_chains, pl.h.n_atoms, top_k, sp.rmsd_cluster, sel, s), "rank launch");
+    if (stats) HIP_TRY(hipEventRecord(ev1, s), "event");
+    std::vector<float> h_rec((size_t)n_chains * kRecWords);
+    std::vector<int> h_sel((size_t)top_k + 1);
+    HIP_TRY(hipMemcpyAsync(h_rec.data(), rec, h_rec.size() * 4, hipMemcpyDeviceToHost, s), "result copy");
+    HIP_TRY(hipMemcpyAsync(h_sel.data(), sel, h_sel.size() * 4, hipMemcpyDeviceToHost, s), "result copy");
+    std::vector<float4> h_xyz;
+    if (out_xyz && top_k > 0) {
+        h_xyz.resize((size_t)n_chains * pl.h.n_atoms);
+        HIP_TRY(hipMemcpyAsync(h_xyz.data(), bxyz, h_xyz.size() * 16, hipMemcpyDeviceToHost, s), "result copy");
+    }
+    HIP_TRY(hipStreamSynchronize(s), "dock");
+    const int nt = pl.h.n_tors, nx = 7 + nt;
+    auto fill_pose = [&](int c, dsdp_pose &p) {
+        std::memset(&p, 0, sizeof p);
+        const float *r = &h_rec[(size_t)c * kRecWords];
+        for (int a = 0; a < 3; a++) p.pos[a] = r[kRecPose + a];
+        for (int a = 0; a < 4; a++) p.quat[a] = r[kRecPose + 3 + a];
+        for (int k = 0; k < nt; k++) p.tors[k] = r[kRecPose + 7 + k];
+        p.e_total = r[kRecE];
+        p.e_inter = r[kRecE + 1];
+        p.e_intra = r[kRecE + 2];
+        p.e_wall = r[kRecE + 3];
+        p.score = p.e_inter / (1.0f + kWRot * (float)nt);
+        p.chain = c;
+    };
+    (void)nx;
+    int cnt = top_k > 0 ? h_sel[0] : 0;
+    for (int q = 0; q < cnt; q++) {
+        const int c = h_sel[1 + q];
+        fill_pose(c, out[q]);
+        if (out_xyz)
+            for (int a = 0; a < pl.h.n_atoms; a++) {
+                const float4 v = h_xyz[(size_t)c * pl.h.n_atoms + a];
+                float *o = out_xyz + ((size_t)q * pl.h.n_atoms + a) * 3;
+                o[0] = v.x; o[1] = v.y; o[2] = v.z;
+            }
+    }
+    if (n_out) *n_out = cnt;
+    if (chains_out)
+        for (int c = 0; c < n_chains; c++) fill_pose(c, chains_out[c]);
+    if (stats) {
+        std::memset(stats, 0, sizeof *stats);
+        for (int c = 0; c < n_chains; c++) {
+            const int *ri = reinterpret_cast<const int *>(&h_rec[(size_t)c * kRecWords]);
+            stats->pose_evals += ri[kRecEvals];
+            stats->accepted += ri[kRecAccepted];
+            stats->local_opts += ri[kRecLocalOpts];
+            if (!std::isfinite(h_rec[(size_t)c * kRecWords + kRecE])) stats->n_nonfinite++;
+        }
+        float ms = 0;
+        HIP_TRY(hipEventElapsedTime(&ms, ev0, ev1), "event");
+        stats->kernel_ms = ms;
+        (void)hipEventDestroy(ev0);
+        (void)hipEventDestroy(ev1);
+    }
+    return DSDP_OK;
+}
+
+}  // extern "C"

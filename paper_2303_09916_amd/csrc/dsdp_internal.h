@@ -1,0 +1,114 @@
+// Private layouts shared by the host side of libdsdp (dsdp_abi.cpp) and its HIP
+// kernels.  Nothing here is part of the public ABI (include/dsdp.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dsdp {
+
+constexpr int kMaxAtoms = 64;
+constexpr int kMaxFrags = 32;
+constexpr int kMaxTors = kMaxFrags - 1;
+constexpr int kMaxPairs = kMaxAtoms * (kMaxAtoms - 1) / 2;
+constexpr int kMaxD = 6 + kMaxTors;
+constexpr int kNXS = 17;
+constexpr float kCutoff = 8.0f;
+constexpr float kCutoff2 = 64.0f;
+
+// Vina's XS typing (ref. [6] of the paper): radius, hydrophobic, donor, acceptor.
+// Order: C_H C_P N_P N_D N_A N_DA O_P O_D O_A O_DA S_P P_P F_H Cl_H Br_H I_H Met_D
+__host__ __device__ constexpr float xs_radius(int t)
+{
+    constexpr float r[kNXS] = {1.9f, 1.9f, 1.8f, 1.8f, 1.8f, 1.8f, 1.7f, 1.7f, 1.7f,
+                               1.7f, 2.0f, 2.1f, 1.5f, 1.8f, 2.0f, 2.2f, 1.2f};
+    return r[t];
+}
+__host__ __device__ constexpr bool xs_hydrophobic(int t) { return t == 0 || (t >= 12 && t <= 15); }
+__host__ __device__ constexpr bool xs_donor(int t) { return t == 3 || t == 5 || t == 7 || t == 9 || t == 16; }
+__host__ __device__ constexpr bool xs_acceptor(int t) { return t == 4 || t == 5 || t == 8 || t == 9; }
+
+// Pair class flags packed next to a pair's radius sum.
+constexpr uint32_t kPairHydrophobic = 1u;
+constexpr uint32_t kPairHBond = 2u;
+__host__ __device__ inline uint32_t pair_flags(int a, int b)
+{
+    uint32_t f = 0;
+    if (xs_hydrophobic(a) && xs_hydrophobic(b)) f |= kPairHydrophobic;
+    if ((xs_donor(a) && xs_acceptor(b)) || (xs_donor(b) && xs_acceptor(a))) f |= kPairHBond;
+    return f;
+}
+
+// Vina weights (ref. [6]): gauss1, gauss2, repulsion, hydrophobic, hydrogen bond.
+constexpr float kWGauss1 = -0.0356f;
+constexpr float kWGauss2 = -0.00516f;
+constexpr float kWRepulsion = 0.840f;
+constexpr float kWHydrophobic = -0.0351f;
+constexpr float kWHBond = -0.587f;
+constexpr float kWRot = 0.0585f;
+
+// Device view of one set of maps.
+struct GridView {
+    const float4 *maps;      // [T][nz][ny][nx] (E, dE/dx, dE/dy, dE/dz)
+    int n[3];
+    float origin[3];
+    float h, inv_h;
+    int T;
+    int map_of_type[kNXS];   // XS type -> map index or -1
+};
+
+// Ligand blob: 32-bit words, built on the host per (ligand, grids), copied to the
+// device, then staged into LDS by every search workgroup.  Section offsets are in
+// words from the blob start; float4 sections are 4-word aligned.
+struct LigHeader {
+    int32_t n_atoms, n_frags, n_tors, n_pairs;
+    int32_t max_depth;
+    float rg;                // gyration radius about the root centre (rotation amplitude scale)
+    int32_t off_atom;        // float4[n_atoms]: local offset xyz from the fragment origin, w = map index bits
+    int32_t off_frag_u;      // float4[n_frags]: unit torsion axis in the parent frame, w = parent bits
+    int32_t off_frag_off;    // float4[n_frags]: fragment origin in the parent frame, w = subtree mask bits
+    int32_t off_atom_frag;   // int[n_atoms]
+    int32_t off_frag_start;  // int[n_frags + 1]
+    int32_t off_pair;        // uint32[n_pairs]: i | j << 8 | flags << 16
+    int32_t off_pair_rsum;   // float[n_pairs]: R_i + R_j
+    int32_t off_csr_start;   // int[n_atoms + 1]: pairs of atom i
+    int32_t off_csr;         // uint32[2 n_pairs]: partner | pair << 8
+    int32_t total_words;     // multiple of 4
+};
+constexpr int kHeaderWords = (int)(sizeof(LigHeader) / 4 + 3) / 4 * 4;
+
+// Per-chain result record in device memory (words).
+constexpr int kRecPose = 0;        // 40 floats: pose, stride 7 + n_tors used
+constexpr int kRecE = 40;          // e_total, e_inter, e_intra, wall
+constexpr int kRecEvals = 44;      // int32 pose evaluations
+constexpr int kRecAccepted = 45;   // int32 Metropolis acceptances
+constexpr int kRecLocalOpts = 46;  // int32 local optimisations
+constexpr int kRecWords = 48;
+
+// Random-number streams (Philox4x32-10 counter = chain, step, stream, block; key = seed).
+constexpr uint32_t kTagInit = 0, kTagMutate = 1, kTagMetropolis = 2;
+
+struct SearchParams {
+    float temperature, wall_slope, rmsd_cluster, trans_amp;
+    int bfgs_iters, ls_trials;
+    float ls_shrink, armijo_c1;
+};
+
+// Launchers (defined in the .hip files).
+hipError_t launch_grid_build(const float4 *atoms, const int *cell_start, const int *cn, const float *clo,
+                             float cell, const GridView &g, const int *map_types_host, float4 *maps,
+                             hipStream_t stream);
+size_t chain_lds_bytes(const LigHeader &h);
+hipError_t launch_eval(const uint32_t *blob, int blob_words, const LigHeader &h, const GridView &g,
+                       const SearchParams &p, const float *poses, int n, float *energy, float *grad, float *xyz,
+                       hipStream_t stream);
+hipError_t launch_local_opt(const uint32_t *blob, int blob_words, const LigHeader &h, const GridView &g,
+                            const SearchParams &p, const float *poses_in, int n, float *poses_out, float *energy,
+                            int *evals, hipStream_t stream);
+hipError_t launch_dock(const uint32_t *blob, int blob_words, const LigHeader &h, const GridView &g,
+                       const SearchParams &p, int n_chains, int n_steps, uint64_t seed, float *records,
+                       float4 *best_xyz, hipStream_t stream);
+hipError_t launch_rank(const float *records, const float4 *best_xyz, int n_chains, int n_atoms, int top_k,
+                       float rmsd_cut, int *sel, hipStream_t stream);
+
+}  // namespace dsdp

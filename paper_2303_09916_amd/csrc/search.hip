@@ -1,0 +1,880 @@
+// Pose evaluation, BFGS local optimisation, Monte Carlo chains and ranking on gfx950.
+//
+// Paper: Section 2, "Binding pose search" (Vina scoring kept; score-and-gradient
+// grids with trilinear interpolation, Appendix eqs. 2 and 4; Vina's BFGS local
+// optimiser, ref. [36]) and the parallelisation paragraph (many short,
+// independent Monte Carlo copies; results post-processed into ranked poses).
+//
+// Execution model: one 64-lane wavefront per chain (or per pose).  Lanes map to
+// ligand atoms for kinematics and grid gathers, to atom pairs (strided) for the
+// intra-ligand terms, to fragments for the torque tree and to tangent
+// coordinates for the BFGS vectors.  The ligand description lives in LDS (shared
+// by the waves of a workgroup); each wave owns an LDS region with its
+// coordinates, forces, frames, BFGS matrix and poses.  All cross-lane traffic
+// is LDS or butterfly shuffles in a fixed order, so a chain's arithmetic does not
+// depend on which wave, workgroup or launch runs it.
+#include "dsdp_internal.h"
+
+namespace dsdp {
+namespace {
+
+constexpr float kPi = 3.14159265358979323846f;
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
+__device__ __forceinline__ int wave_id() { return (int)(threadIdx.x >> 6); }
+
+// Make a wave's LDS writes visible to its other lanes.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Butterfly sum: every lane ends with the same bits (each step adds a pair of
+// operands in both lanes, and addition commutes).
+__device__ __forceinline__ float wave_sum(float v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+// ---------------------------------------------------------------- Philox4x32-10
+// Salmon et al., SC'11: ten rounds of two 32x32->64 multiplies, Weyl key bumps.
+__device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; r++) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    }
+    return c;
+}
+__device__ __forceinline__ uint4 draw(uint64_t seed, uint32_t chain, uint32_t step, uint32_t tag, uint32_t block)
+{
+    return philox(make_uint4(chain, step, tag, block), (uint32_t)seed, (uint32_t)(seed >> 32));
+}
+// top 24 bits -> [0, 1), exact in float
+__device__ __forceinline__ float unif(uint32_t x) { return (float)(x >> 8) * (1.0f / 16777216.0f); }
+
+// ---------------------------------------------------------------- small geometry
+struct M3 {
+    float a[9];
+};
+__device__ __forceinline__ M3 quat_to_mat(float w, float x, float y, float z)
+{
+    M3 R;
+    R.a[0] = 1 - 2 * (y * y + z * z); R.a[1] = 2 * (x * y - w * z);     R.a[2] = 2 * (x * z + w * y);
+    R.a[3] = 2 * (x * y + w * z);     R.a[4] = 1 - 2 * (x * x + z * z); R.a[5] = 2 * (y * z - w * x);
+    R.a[6] = 2 * (x * z - w * y);     R.a[7] = 2 * (y * z + w * x);     R.a[8] = 1 - 2 * (x * x + y * y);
+    return R;
+}
+__device__ __forceinline__ M3 axis_angle(float ux, float uy, float uz, float th)
+{
+    float s, c;
+    sincosf(th, &s, &c);
+    const float t = 1 - c;
+    M3 R;
+    R.a[0] = c + t * ux * ux;      R.a[1] = t * ux * uy - s * uz; R.a[2] = t * ux * uz + s * uy;
+    R.a[3] = t * uy * ux + s * uz; R.a[4] = c + t * uy * uy;      R.a[5] = t * uy * uz - s * ux;
+    R.a[6] = t * uz * ux - s * uy; R.a[7] = t * uz * uy + s * ux; R.a[8] = c + t * uz * uz;
+    return R;
+}
+__device__ __forceinline__ M3 mul(const M3 &A, const M3 &B)
+{
+    M3 C;
+#pragma unroll
+    for (int r = 0; r < 3; r++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) C.a[3 * r + c] = A.a[3 * r] * B.a[c] + A.a[3 * r + 1] * B.a[3 + c] + A.a[3 * r + 2] * B.a[6 + c];
+    return C;
+}
+__device__ __forceinline__ float3 mv(const M3 &A, float3 v)
+{
+    return make_float3(A.a[0] * v.x + A.a[1] * v.y + A.a[2] * v.z, A.a[3] * v.x + A.a[4] * v.y + A.a[5] * v.z,
+                       A.a[6] * v.x + A.a[7] * v.y + A.a[8] * v.z);
+}
+__device__ __forceinline__ float3 cross3(float3 a, float3 b)
+{
+    return make_float3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ float3 f3(float4 v) { return make_float3(v.x, v.y, v.z); }
+__device__ __forceinline__ float3 operator+(float3 a, float3 b) { return make_float3(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ __forceinline__ float3 operator-(float3 a, float3 b) { return make_float3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ float3 operator*(float s, float3 a) { return make_float3(s * a.x, s * a.y, s * a.z); }
+__device__ __forceinline__ float dot3(float3 a, float3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+
+// unit quaternion of rotation vector v (angle |v| about v/|v|)
+__device__ __forceinline__ float4 quat_of_rotvec(float vx, float vy, float vz)
+{
+    const float a = sqrtf(vx * vx + vy * vy + vz * vz);
+    if (a == 0.0f) return make_float4(1.f, 0.f, 0.f, 0.f);   // (w, x, y, z)
+    float s, c;
+    sincosf(0.5f * a, &s, &c);
+    const float k = s / a;
+    return make_float4(c, k * vx, k * vy, k * vz);
+}
+// Hamilton product a * b, (w, x, y, z) in (x, y, z, w) slots of float4 as w=x-slot
+__device__ __forceinline__ float4 quat_mul(float4 a, float4 b)
+{
+    return make_float4(a.x * b.x - a.y * b.y - a.z * b.z - a.w * b.w,
+                       a.x * b.y + a.y * b.x + a.z * b.w - a.w * b.z,
+                       a.x * b.z - a.y * b.w + a.z * b.x + a.w * b.y,
+                       a.x * b.w + a.y * b.z - a.z * b.y + a.w * b.x);
+}
+__device__ __forceinline__ float4 quat_normalize(float4 q)
+{
+    const float n = sqrtf(q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w);
+    return make_float4(q.x / n, q.y / n, q.z / n, q.w / n);
+}
+// into (-pi, pi]; non-finite values pass through, huge ones are reduced first
+__device__ __forceinline__ float wrap_angle(float t)
+{
+    if (!(fabsf(t) < 3.0e38f)) return t;
+    if (fabsf(t) > 1.0e4f) t = fmodf(t, 2 * kPi);
+    while (t > kPi) t -= 2 * kPi;
+    while (t <= -kPi) t += 2 * kPi;
+    return t;
+}
+// point in the unit ball: direction (z = 2u1 - 1, phi = 2 pi u2), radius u3^(1/3)
+__device__ __forceinline__ float3 ball(float u1, float u2, float u3)
+{
+    const float z = 2 * u1 - 1, r = cbrtf(u3);
+    float s, c;
+    sincosf(2 * kPi * u2, &s, &c);
+    const float q = sqrtf(fmaxf(0.0f, 1 - z * z));
+    return make_float3(r * q * c, r * q * s, r * z);
+}
+
+// Vina pair energy on the surface distance d and its derivative in d (returned as
+// (e, de)).  Piecewise terms in branch-free form; at a kink the left-hand slope
+// is taken.
+__device__ __forceinline__ float2 vina_pair(float d, uint32_t flags)
+{
+    const float g1 = __expf(-4.0f * d * d);
+    const float b = d - 3.0f;
+    const float g2 = __expf(-0.25f * b * b);
+    const float dn = fminf(d, 0.0f);
+    float e = kWGauss1 * g1 + kWGauss2 * g2 + kWRepulsion * dn * dn;
+    float de = kWGauss1 * g1 * (-8.0f * d) + kWGauss2 * g2 * (-0.5f * b) + kWRepulsion * 2.0f * dn;
+    if (flags & kPairHydrophobic) {
+        e += kWHydrophobic * fminf(fmaxf(1.5f - d, 0.0f), 1.0f);
+        de += (d > 0.5f && d <= 1.5f) ? -kWHydrophobic : 0.0f;
+    }
+    if (flags & kPairHBond) {
+        e += kWHBond * fminf(fmaxf(-d * (1.0f / 0.7f), 0.0f), 1.0f);
+        de += (d > -0.7f && d <= 0.0f) ? -kWHBond * (1.0f / 0.7f) : 0.0f;
+    }
+    return make_float2(e, de);
+}
+
+// ---------------------------------------------------------------- LDS layout
+struct LigL {
+    int na, nf, nt, np, D, nx;
+    float rg;
+    const float4 *atom;      // local offset, w = map index
+    const float4 *fu;        // torsion axis in parent frame, w = parent
+    const float4 *foff;      // origin in parent frame, w = subtree mask
+    const int *atom_frag;
+    const int *frag_start;
+    const uint32_t *pair;
+    const float *rsum;
+    const int *csr_start;
+    const uint32_t *csr;
+};
+
+struct ChainL {
+    float4 *xyz, *frc, *trq;
+    float4 *R;       // [nf][4]: rows of R_k, then origin o_k
+    float4 *Q;       // [nf][3]: rotation of fragment k relative to its parent (root: R(q))
+    float4 *FT;      // [nf][2]: force, torque (about o_k) summed over fragment k's atoms
+    float *spair;    // [np]: dE/dr / r of each pair
+    float *g, *p, *s, *y, *Hy, *gt, *tmp;
+    float *H;
+    int hs;
+    float *cur, *trial, *cand, *best;
+    float *misc;
+};
+
+__host__ __device__ inline int rup4(int v) { return (v + 3) & ~3; }
+
+struct ChainLayout {
+    int xyz, frc, trq, R, Q, FT, spair, vec, H, hs, pose, misc, words, Dp, NXp;
+};
+__host__ __device__ inline ChainLayout chain_layout(int na, int nf, int np, int D, int nx)
+{
+    ChainLayout c;
+    int w = 0;
+    c.xyz = w; w += 4 * na;
+    c.frc = w; w += 4 * na;
+    c.trq = w; w += 4 * na;
+    c.R = w; w += 16 * nf;
+    c.Q = w; w += 12 * nf;
+    c.FT = w; w += 8 * nf;
+    c.spair = w; w += rup4(np);
+    c.Dp = rup4(D);
+    c.vec = w; w += 7 * c.Dp;
+    c.hs = D + 1;
+    c.H = w; w += rup4(D * c.hs);
+    c.NXp = rup4(nx);
+    c.pose = w; w += 4 * c.NXp;
+    c.misc = w; w += 48;
+    c.words = w;
+    return c;
+}
+
+__device__ inline LigL make_lig(const uint32_t *blob)
+{
+    const LigHeader *h = reinterpret_cast<const LigHeader *>(blob);
+    LigL L;
+    L.na = h->n_atoms; L.nf = h->n_frags; L.nt = h->n_tors; L.np = h->n_pairs;
+    L.D = 6 + L.nt; L.nx = 7 + L.nt;
+    L.rg = h->rg;
+    L.atom = reinterpret_cast<const float4 *>(blob + h->off_atom);
+    L.fu = reinterpret_cast<const float4 *>(blob + h->off_frag_u);
+    L.foff = reinterpret_cast<const float4 *>(blob + h->off_frag_off);
+    L.atom_frag = reinterpret_cast<const int *>(blob + h->off_atom_frag);
+    L.frag_start = reinterpret_cast<const int *>(blob + h->off_frag_start);
+    L.pair = blob + h->off_pair;
+    L.rsum = reinterpret_cast<const float *>(blob + h->off_pair_rsum);
+    L.csr_start = reinterpret_cast<const int *>(blob + h->off_csr_start);
+    L.csr = blob + h->off_csr;
+    return L;
+}
+
+__device__ inline ChainL make_chain(float *base, const ChainLayout &c)
+{
+    ChainL S;
+    S.xyz = reinterpret_cast<float4 *>(base + c.xyz);
+    S.frc = reinterpret_cast<float4 *>(base + c.frc);
+    S.trq = reinterpret_cast<float4 *>(base + c.trq);
+    S.R = reinterpret_cast<float4 *>(base + c.R);
+    S.Q = reinterpret_cast<float4 *>(base + c.Q);
+    S.FT = reinterpret_cast<float4 *>(base + c.FT);
+    S.spair = base + c.spair;
+    float *v = base + c.vec;
+    S.g = v; S.p = v + c.Dp; S.s = v + 2 * c.Dp; S.y = v + 3 * c.Dp; S.Hy = v + 4 * c.Dp; S.gt = v + 5 * c.Dp;
+    S.tmp = v + 6 * c.Dp;
+    S.H = base + c.H;
+    S.hs = c.hs;
+    float *p = base + c.pose;
+    S.cur = p; S.trial = p + c.NXp; S.cand = p + 2 * c.NXp; S.best = p + 3 * c.NXp;
+    S.misc = base + c.misc;
+    return S;
+}
+
+// ---------------------------------------------------------------- evaluation
+struct Energy {
+    float total, inter, intra, wall;
+};
+
+// Energy of `pose` (LDS, wave-uniform) and, if grad != nullptr, its gradient in
+// the tangent coordinates written to grad[0..D) (LDS).  Coordinates are left in
+// S.xyz.  Every lane returns the same values.
+__device__ Energy eval_pose(const LigL &L, const ChainL &S, const GridView &G, const float *pose, float *grad,
+                            float wall_slope)
+{
+    const int lane = lane_id();
+
+    // (1) rotation of every fragment relative to its parent; the root's is R(q)
+    if (lane < L.nf) {
+        M3 Q;
+        if (lane == 0) {
+            const float4 q = quat_normalize(make_float4(pose[3], pose[4], pose[5], pose[6]));
+            Q = quat_to_mat(q.x, q.y, q.z, q.w);
+        } else {
+            const float4 u = L.fu[lane];
+            Q = axis_angle(u.x, u.y, u.z, pose[7 + lane - 1]);
+        }
+        S.Q[3 * lane + 0] = make_float4(Q.a[0], Q.a[1], Q.a[2], 0.f);
+        S.Q[3 * lane + 1] = make_float4(Q.a[3], Q.a[4], Q.a[5], 0.f);
+        S.Q[3 * lane + 2] = make_float4(Q.a[6], Q.a[7], Q.a[8], 0.f);
+    }
+    wave_sync();
+
+    // (2) world frame of fragment k: compose along its ancestry (bottom-up)
+    //     R_k = R_0 Q_a1 .. Q_k,  o_k = p + R_0 (off_a1 + Q_a1 (off_a2 + ... off_k))
+    if (lane < L.nf) {
+        M3 R0;
+        {
+            const float4 r0 = S.Q[0], r1 = S.Q[1], r2 = S.Q[2];
+            R0.a[0] = r0.x; R0.a[1] = r0.y; R0.a[2] = r0.z;
+            R0.a[3] = r1.x; R0.a[4] = r1.y; R0.a[5] = r1.z;
+            R0.a[6] = r2.x; R0.a[7] = r2.y; R0.a[8] = r2.z;
+        }
+        M3 R = R0;
+        float3 o = make_float3(pose[0], pose[1], pose[2]);
+        if (lane > 0) {
+            M3 M;
+            {
+                const float4 r0 = S.Q[3 * lane], r1 = S.Q[3 * lane + 1], r2 = S.Q[3 * lane + 2];
+                M.a[0] = r0.x; M.a[1] = r0.y; M.a[2] = r0.z;
+                M.a[3] = r1.x; M.a[4] = r1.y; M.a[5] = r1.z;
+                M.a[6] = r2.x; M.a[7] = r2.y; M.a[8] = r2.z;
+            }
+            float3 v = f3(L.foff[lane]);
+            int m = __float_as_int(L.fu[lane].w);
+            while (m > 0) {
+                M3 Qm;
+                const float4 r0 = S.Q[3 * m], r1 = S.Q[3 * m + 1], r2 = S.Q[3 * m + 2];
+                Qm.a[0] = r0.x; Qm.a[1] = r0.y; Qm.a[2] = r0.z;
+                Qm.a[3] = r1.x; Qm.a[4] = r1.y; Qm.a[5] = r1.z;
+                Qm.a[6] = r2.x; Qm.a[7] = r2.y; Qm.a[8] = r2.z;
+                v = f3(L.foff[m]) + mv(Qm, v);
+                M = mul(Qm, M);
+                m = __float_as_int(L.fu[m].w);
+            }
+            R = mul(R0, M);
+            o = o + mv(R0, v);
+        }
+        S.R[4 * lane + 0] = make_float4(R.a[0], R.a[1], R.a[2], 0.f);
+        S.R[4 * lane + 1] = make_float4(R.a[3], R.a[4], R.a[5], 0.f);
+        S.R[4 * lane + 2] = make_float4(R.a[6], R.a[7], R.a[8], 0.f);
+        S.R[4 * lane + 3] = make_float4(o.x, o.y, o.z, 0.f);
+    }
+    wave_sync();
+
+    // (3) atom coordinates and the inter-molecular term from the maps
+    float e_atom = 0.f, w_atom = 0.f;
+    float3 x = make_float3(0.f, 0.f, 0.f), f = make_float3(0.f, 0.f, 0.f);
+    int frag = 0;
+    if (lane < L.na) {
+        frag = L.atom_frag[lane];
+        const float4 loc = L.atom[lane];
+        const float4 r0 = S.R[4 * frag], r1 = S.R[4 * frag + 1], r2 = S.R[4 * frag + 2], o = S.R[4 * frag + 3];
+        x = make_float3(o.x + r0.x * loc.x + r0.y * loc.y + r0.z * loc.z,
+                        o.y + r1.x * loc.x + r1.y * loc.y + r1.z * loc.z,
+                        o.z + r2.x * loc.x + r2.y * loc.y + r2.z * loc.z);
+        S.xyz[lane] = make_float4(x.x, x.y, x.z, 0.f);
+
+        // wall and clamping (a coordinate outside the box is clamped onto the face;
+        // the atom pays wall_slope per Angstrom outside; the map gradient along a
+        // clamped axis is dropped)
+        const float xs[3] = {x.x, x.y, x.z};
+        float u[3], wg[3];
+        int ci[3];
+        bool cl[3];
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            const float lo = G.origin[a];
+            const float hi = G.origin[a] + (float)(G.n[a] - 1) * G.h;
+            float xa = xs[a];
+            wg[a] = 0.f;
+            cl[a] = false;
+            if (xa < lo) {
+                w_atom += wall_slope * (lo - xa);
+                wg[a] = -wall_slope;
+                xa = lo;
+                cl[a] = true;
+            } else if (xa > hi) {
+                w_atom += wall_slope * (xa - hi);
+                wg[a] = wall_slope;
+                xa = hi;
+                cl[a] = true;
+            }
+            u[a] = (xa - lo) * G.inv_h;
+            int i = (int)floorf(u[a]);
+            i = min(i, G.n[a] - 2);
+            i = max(i, 0);
+            ci[a] = i;
+            u[a] -= (float)i;
+        }
+        const int t = __float_as_int(loc.w);
+        const long sy = G.n[0], sz = (long)G.n[0] * G.n[1];
+        const float4 *m0 = G.maps + (long)t * sz * G.n[2] + ci[2] * sz + ci[1] * sy + ci[0];
+        const float4 c000 = m0[0], c100 = m0[1], c010 = m0[sy], c110 = m0[sy + 1];
+        const float4 c001 = m0[sz], c101 = m0[sz + 1], c011 = m0[sz + sy], c111 = m0[sz + sy + 1];
+        const float px = u[0], py = u[1], pz = u[2];
+        const float qx = 1.f - px, qy = 1.f - py, qz = 1.f - pz;
+        const float w000 = qx * qy * qz, w100 = px * qy * qz, w010 = qx * py * qz, w110 = px * py * qz;
+        const float w001 = qx * qy * pz, w101 = px * qy * pz, w011 = qx * py * pz, w111 = px * py * pz;
+        // eq. 2 (energy) and eq. 4 (gradient): the same weights on E and on stored gradients
+        const float E = w000 * c000.x + w100 * c100.x + w010 * c010.x + w110 * c110.x + w001 * c001.x +
+                        w101 * c101.x + w011 * c011.x + w111 * c111.x;
+        float gx = w000 * c000.y + w100 * c100.y + w010 * c010.y + w110 * c110.y + w001 * c001.y + w101 * c101.y +
+                   w011 * c011.y + w111 * c111.y;
+        float gy = w000 * c000.z + w100 * c100.z + w010 * c010.z + w110 * c110.z + w001 * c001.z + w101 * c101.z +
+                   w011 * c011.z + w111 * c111.z;
+        float gz = w000 * c000.w + w100 * c100.w + w010 * c010.w + w110 * c110.w + w001 * c001.w + w101 * c101.w +
+                   w011 * c011.w + w111 * c111.w;
+        if (cl[0]) gx = 0.f;
+        if (cl[1]) gy = 0.f;
+        if (cl[2]) gz = 0.f;
+        f = make_float3(gx + wg[0], gy + wg[1], gz + wg[2]);
+        e_atom = E + w_atom;
+    }
+    wave_sync();
+
+    // (4) intra-ligand pairs, strided over lanes; store dE/dr / r per pair
+    float e_pair = 0.f;
+    for (int p = lane; p < L.np; p += 64) {
+        const uint32_t pw = L.pair[p];
+        const int i = (int)(pw & 255u), j = (int)((pw >> 8) & 255u);
+        const float4 xi = S.xyz[i], xj = S.xyz[j];
+        const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        float sp = 0.f;
+        if (r2 < kCutoff2) {
+            const float r = sqrtf(r2);
+            const float2 ed = vina_pair(r - L.rsum[p], pw >> 16);
+            e_pair += ed.x;
+            sp = r > 1e-9f ? ed.y / r : 0.f;
+        }
+        S.spair[p] = sp;
+    }
+    wave_sync();
+
+    const float e_inter = wave_sum(e_atom);
+    const float e_intra = wave_sum(e_pair);
+    const float wall = wave_sum(w_atom);
+    Energy out;
+    out.inter = e_inter;
+    out.intra = e_intra;
+    out.wall = wall;
+    out.total = e_inter + e_intra;
+    if (grad == nullptr) return out;
+
+    // (5) pair forces gathered per atom (CSR, fixed order), then torque about the
+    //     atom's fragment origin
+    if (lane < L.na) {
+        const int e0 = L.csr_start[lane], e1 = L.csr_start[lane + 1];
+        for (int e = e0; e < e1; e++) {
+            const uint32_t w = L.csr[e];
+            const float4 xj = S.xyz[w & 255u];
+            const float sp = S.spair[w >> 8];
+            f = f + sp * (x - f3(xj));
+        }
+        const float3 o = f3(S.R[4 * frag + 3]);
+        const float3 tq = cross3(x - o, f);
+        S.frc[lane] = make_float4(f.x, f.y, f.z, 0.f);
+        S.trq[lane] = make_float4(tq.x, tq.y, tq.z, 0.f);
+    }
+    wave_sync();
+
+    // (6) per-fragment sums over the fragment's contiguous atom range
+    if (lane < L.nf) {
+        float3 F = make_float3(0.f, 0.f, 0.f), Tq = make_float3(0.f, 0.f, 0.f);
+        const int a0 = L.frag_start[lane], a1 = L.frag_start[lane + 1];
+        for (int a = a0; a < a1; a++) {
+            F = F + f3(S.frc[a]);
+            Tq = Tq + f3(S.trq[a]);
+        }
+        S.FT[2 * lane] = make_float4(F.x, F.y, F.z, 0.f);
+        S.FT[2 * lane + 1] = make_float4(Tq.x, Tq.y, Tq.z, 0.f);
+    }
+    wave_sync();
+
+    // (7) subtree sums: F_sub(k) = sum F_m, tau_sub(k) = sum T_m + (o_m - o_k) x F_m
+    //     over fragments m in k's subtree; dE/dtheta_k = u_k . tau_sub(k)
+    if (lane < L.nf) {
+        uint32_t mask = __float_as_uint(L.foff[lane].w);
+        const float3 ok = f3(S.R[4 * lane + 3]);
+        float3 F = make_float3(0.f, 0.f, 0.f), Tq = make_float3(0.f, 0.f, 0.f);
+        while (mask) {
+            const int m = __ffs(mask) - 1;
+            mask &= mask - 1;
+            const float3 Fm = f3(S.FT[2 * m]);
+            F = F + Fm;
+            Tq = Tq + f3(S.FT[2 * m + 1]) + cross3(f3(S.R[4 * m + 3]) - ok, Fm);
+        }
+        if (lane == 0) {
+            grad[0] = F.x; grad[1] = F.y; grad[2] = F.z;
+            grad[3] = Tq.x; grad[4] = Tq.y; grad[5] = Tq.z;
+        } else {
+            const float4 uref = L.fu[lane];
+            const float4 r0 = S.R[4 * lane], r1 = S.R[4 * lane + 1], r2 = S.R[4 * lane + 2];
+            const float3 u = make_float3(r0.x * uref.x + r0.y * uref.y + r0.z * uref.z,
+                                         r1.x * uref.x + r1.y * uref.y + r1.z * uref.z,
+                                         r2.x * uref.x + r2.y * uref.y + r2.z * uref.z);
+            grad[6 + lane - 1] = dot3(u, Tq);
+        }
+    }
+    wave_sync();
+    return out;
+}
+
+// trial = x (+) alpha * dir   (p += a dp; q <- normalise(quat(a w) q); theta <- wrap(theta + a dtheta))
+__device__ inline void pose_step(const LigL &L, const float *x, float alpha, const float *dir, float *out)
+{
+    const int lane = lane_id();
+    const float4 dq = quat_of_rotvec(alpha * dir[3], alpha * dir[4], alpha * dir[5]);
+    const float4 q = quat_normalize(quat_mul(dq, make_float4(x[3], x[4], x[5], x[6])));
+    if (lane < 3) out[lane] = x[lane] + alpha * dir[lane];
+    else if (lane < 7) out[lane] = lane == 3 ? q.x : (lane == 4 ? q.y : (lane == 5 ? q.z : q.w));
+    else if (lane < L.nx) out[lane] = wrap_angle(x[lane] + alpha * dir[lane - 1]);
+    wave_sync();
+}
+
+__device__ inline void copy_pose(const LigL &L, const float *src, float *dst)
+{
+    const int lane = lane_id();
+    if (lane < L.nx) dst[lane] = src[lane];
+    wave_sync();
+}
+
+// BFGS with Armijo backtracking on pose x (LDS, in place).  Returns the energy of
+// the final pose; *evals counts evaluations.  Gradient of the final pose in S.g.
+__device__ Energy local_opt(const LigL &L, const ChainL &S, const GridView &G, const SearchParams &P, float *x,
+                            int &evals)
+{
+    const int lane = lane_id();
+    const int D = L.D;
+    Energy Ex = eval_pose(L, S, G, x, S.g, P.wall_slope);
+    evals++;
+    if (lane < D)
+        for (int c = 0; c < D; c++) S.H[lane * S.hs + c] = (c == lane) ? 1.f : 0.f;
+    wave_sync();
+    for (int it = 0; it < P.bfgs_iters; it++) {
+        float pl = 0.f, gl = 0.f;
+        if (lane < D) {
+            float acc = 0.f;
+            for (int c = 0; c < D; c++) acc += S.H[lane * S.hs + c] * S.g[c];
+            pl = -acc;
+            gl = S.g[lane];
+            S.p[lane] = pl;
+        }
+        const float gp = wave_sum(pl * gl);
+        wave_sync();
+        float alpha = 1.f;
+        bool ok = false;
+        Energy Et;
+        for (int t = 0; t < P.ls_trials; t++) {
+            pose_step(L, x, alpha, S.p, S.trial);
+            Et = eval_pose(L, S, G, S.trial, S.gt, P.wall_slope);
+            evals++;
+            if (Et.total <= Ex.total + P.armijo_c1 * alpha * gp) {
+                ok = true;
+                break;
+            }
+            alpha *= P.ls_shrink;
+        }
+        if (!ok) break;
+        float sl = 0.f, yl = 0.f;
+        if (lane < D) {
+            sl = alpha * pl;
+            yl = S.gt[lane] - gl;
+            S.s[lane] = sl;
+            S.y[lane] = yl;
+            S.g[lane] = S.gt[lane];
+        }
+        if (lane < L.nx) x[lane] = S.trial[lane];
+        Ex = Et;
+        const float ys = wave_sum(sl * yl);
+        wave_sync();
+        if (ys > 0.f) {
+            const float rho = 1.f / ys;
+            float hy = 0.f;
+            if (lane < D) {
+                for (int c = 0; c < D; c++) hy += S.H[lane * S.hs + c] * S.y[c];
+                S.Hy[lane] = hy;
+            }
+            const float yHy = wave_sum(yl * hy);
+            wave_sync();
+            if (lane < D) {
+                for (int c = 0; c < D; c++)
+                    S.H[lane * S.hs + c] += rho * ((1.f + rho * yHy) * sl * S.s[c] - sl * S.Hy[c] - hy * S.s[c]);
+            }
+            wave_sync();
+        }
+    }
+    return Ex;
+}
+
+// Stage the ligand blob into LDS (whole workgroup) and return the chain region of this wave.
+__device__ inline void stage_blob(const uint32_t *blob, int words, uint32_t *lds)
+{
+    for (int w = threadIdx.x; w < words; w += blockDim.x) lds[w] = blob[w];
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------- kernels
+
+__global__ __launch_bounds__(256) void eval_kernel(const uint32_t *blob, int blob_words, GridView G, SearchParams P,
+                                                   const float *poses, int n, float *energy, float *grad, float *xyz)
+{
+    extern __shared__ float4 lds4[];
+    uint32_t *lds = reinterpret_cast<uint32_t *>(lds4);
+    stage_blob(blob, blob_words, lds);
+    const LigL L = make_lig(lds);
+    const ChainLayout cl = chain_layout(L.na, L.nf, L.np, L.D, L.nx);
+    const ChainL S = make_chain(reinterpret_cast<float *>(lds) + blob_words + wave_id() * cl.words, cl);
+    const int idx = blockIdx.x * (blockDim.x >> 6) + wave_id();
+    if (idx >= n) return;
+    const int lane = lane_id();
+    if (lane < L.nx) S.cur[lane] = poses[(long)idx * L.nx + lane];
+    wave_sync();
+    const Energy E = eval_pose(L, S, G, S.cur, S.g, P.wall_slope);
+    if (lane == 0) {
+        energy[4 * idx + 0] = E.total;
+        energy[4 * idx + 1] = E.inter;
+        energy[4 * idx + 2] = E.intra;
+        energy[4 * idx + 3] = E.wall;
+    }
+    if (lane < L.D) grad[(long)idx * L.D + lane] = S.g[lane];
+    if (xyz && lane < L.na) {
+        const float4 v = S.xyz[lane];
+        float *o = xyz + ((long)idx * L.na + lane) * 3;
+        o[0] = v.x; o[1] = v.y; o[2] = v.z;
+    }
+}
+
+__global__ __launch_bounds__(256) void local_opt_kernel(const uint32_t *blob, int blob_words, GridView G,
+                                                        SearchParams P, const float *poses_in, int n,
+                                                        float *poses_out, float *energy, int *evals_out)
+{
+    extern __shared__ float4 lds4[];
+    uint32_t *lds = reinterpret_cast<uint32_t *>(lds4);
+    stage_blob(blob, blob_words, lds);
+    const LigL L = make_lig(lds);
+    const ChainLayout cl = chain_layout(L.na, L.nf, L.np, L.D, L.nx);
+    const ChainL S = make_chain(reinterpret_cast<float *>(lds) + blob_words + wave_id() * cl.words, cl);
+    const int idx = blockIdx.x * (blockDim.x >> 6) + wave_id();
+    if (idx >= n) return;
+    const int lane = lane_id();
+    if (lane < L.nx) S.cur[lane] = poses_in[(long)idx * L.nx + lane];
+    wave_sync();
+    int evals = 0;
+    const Energy E = local_opt(L, S, G, P, S.cur, evals);
+    if (lane < L.nx) poses_out[(long)idx * L.nx + lane] = S.cur[lane];
+    if (lane == 0) {
+        energy[4 * idx + 0] = E.total;
+        energy[4 * idx + 1] = E.inter;
+        energy[4 * idx + 2] = E.intra;
+        energy[4 * idx + 3] = E.wall;
+        if (evals_out) evals_out[idx] = evals;
+    }
+}
+
+// One Monte Carlo chain per wave: initial pose, then n_steps of mutate -> BFGS ->
+// Metropolis, keeping the lowest accepted energy.  Results go to `records`
+// (kRecWords per chain) and the best pose's coordinates to best_xyz.
+__global__ __launch_bounds__(256) void dock_kernel(const uint32_t *blob, int blob_words, GridView G, SearchParams P,
+                                                   int n_chains, int n_steps, uint64_t seed, float *records,
+                                                   float4 *best_xyz)
+{
+    extern __shared__ float4 lds4[];
+    uint32_t *lds = reinterpret_cast<uint32_t *>(lds4);
+    stage_blob(blob, blob_words, lds);
+    const LigL L = make_lig(lds);
+    const ChainLayout cl = chain_layout(L.na, L.nf, L.np, L.D, L.nx);
+    const ChainL S = make_chain(reinterpret_cast<float *>(lds) + blob_words + wave_id() * cl.words, cl);
+    const int chain = blockIdx.x * (blockDim.x >> 6) + wave_id();
+    if (chain >= n_chains) return;
+    const int lane = lane_id();
+    const uint32_t c = (uint32_t)chain;
+
+    // initial pose: position uniform in the box, Shoemake orientation, uniform torsions
+    const int nw = 6 + L.nt;
+    if (lane < nw) {
+        const uint4 r = draw(seed, c, 0u, kTagInit, (uint32_t)(lane >> 2));
+        const uint32_t v = (lane & 3) == 0 ? r.x : ((lane & 3) == 1 ? r.y : ((lane & 3) == 2 ? r.z : r.w));
+        S.misc[lane] = unif(v);
+    }
+    wave_sync();
+    if (lane < 3) {
+        S.cur[lane] = G.origin[lane] + S.misc[lane] * ((float)(G.n[lane] - 1) * G.h);
+    } else if (lane < 7) {
+        const float u1 = S.misc[3], u2 = S.misc[4], u3 = S.misc[5];
+        const float s1 = sqrtf(1.f - u1), s2 = sqrtf(u1);
+        float sa, ca, sb, cb;
+        sincosf(2 * kPi * u2, &sa, &ca);
+        sincosf(2 * kPi * u3, &sb, &cb);
+        const float v = lane == 3 ? s2 * cb : (lane == 4 ? s1 * sa : (lane == 5 ? s1 * ca : s2 * sb));
+        S.cur[lane] = v;
+    } else if (lane < L.nx) {
+        S.cur[lane] = -kPi + 2 * kPi * S.misc[6 + lane - 7];
+    }
+    wave_sync();
+
+    Energy Ex;
+    Ex.total = 0.f; Ex.inter = 0.f; Ex.intra = 0.f; Ex.wall = 0.f;
+    Energy Eb;
+    Eb.total = __int_as_float(0x7f800000); Eb.inter = Eb.intra = Eb.wall = 0.f;
+    if (lane < L.nx) S.best[lane] = S.cur[lane];
+    int evals = 0, accepted = 0, lopts = 0;
+    const float rot_amp = L.rg > 0.f ? P.trans_amp / L.rg : 0.f;
+
+    for (int step = 0; step < n_steps; step++) {
+        copy_pose(L, S.cur, S.cand);
+        // mutation: one of 2 + n_tors moves, chosen in integer arithmetic
+        const uint4 r = draw(seed, c, (uint32_t)step, kTagMutate, 0u);
+        const int which = (int)(((uint64_t)r.x * (uint64_t)(2 + L.nt)) >> 32);
+        const float u1 = unif(r.y), u2 = unif(r.z), u3 = unif(r.w);
+        if (which == 0) {
+            const float3 v = ball(u1, u2, u3);
+            if (lane < 3) S.cand[lane] += P.trans_amp * (lane == 0 ? v.x : (lane == 1 ? v.y : v.z));
+        } else if (which == 1) {
+            const float3 v = ball(u1, u2, u3);
+            const float4 dq = quat_of_rotvec(rot_amp * v.x, rot_amp * v.y, rot_amp * v.z);
+            const float4 q = quat_normalize(quat_mul(dq, make_float4(S.cur[3], S.cur[4], S.cur[5], S.cur[6])));
+            if (lane >= 3 && lane < 7) S.cand[lane] = lane == 3 ? q.x : (lane == 4 ? q.y : (lane == 5 ? q.z : q.w));
+        } else {
+            if (lane == 7 + which - 2) S.cand[lane] = -kPi + 2 * kPi * u1;
+        }
+        wave_sync();
+        const Energy Ec = local_opt(L, S, G, P, S.cand, evals);
+        lopts++;
+        bool take = true;
+        if (step > 0) {
+            const float dE = Ec.total - Ex.total;
+            const float u = unif(draw(seed, c, (uint32_t)step, kTagMetropolis, 0u).x);
+            take = (dE < 0.f) || (u < expf(-dE / P.temperature));
+        }
+        if (take) {
+            copy_pose(L, S.cand, S.cur);
+            Ex = Ec;
+            accepted++;
+            if (Ex.total < Eb.total) {
+                copy_pose(L, S.cur, S.best);
+                Eb = Ex;
+            }
+        }
+    }
+
+    // coordinates of the best pose (for RMSD clustering)
+    eval_pose(L, S, G, S.best, nullptr, P.wall_slope);
+    float *rec = records + (long)chain * kRecWords;
+    if (lane < L.nx) rec[kRecPose + lane] = S.best[lane];
+    if (lane == 0) {
+        rec[kRecE + 0] = Eb.total;
+        rec[kRecE + 1] = Eb.inter;
+        rec[kRecE + 2] = Eb.intra;
+        rec[kRecE + 3] = Eb.wall;
+        reinterpret_cast<int *>(rec)[kRecEvals] = evals;
+        reinterpret_cast<int *>(rec)[kRecAccepted] = accepted;
+        reinterpret_cast<int *>(rec)[kRecLocalOpts] = lopts;
+    }
+    if (lane < L.na) best_xyz[(long)chain * L.na + lane] = S.xyz[lane];
+}
+
+// Ranking (post-processing): repeatedly take the lowest (energy, chain) candidate
+// still alive, then drop every candidate within rmsd_cut of it.  This selects the
+// same poses as a greedy pass over the sorted list that keeps a pose when its
+// RMSD to every kept pose exceeds the cut.
+__global__ __launch_bounds__(1024) void rank_kernel(const float *records, const float4 *best_xyz, int n_chains,
+                                                    int n_atoms, int top_k, float rmsd_cut, int *sel)
+{
+    extern __shared__ unsigned char rank_lds[];
+    unsigned char *alive = rank_lds;
+    __shared__ unsigned long long s_red[16];
+    __shared__ int s_pick;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int c = tid; c < n_chains; c += nt) {
+        const float e = records[(long)c * kRecWords + kRecE];
+        alive[c] = (e == e && fabsf(e) != __int_as_float(0x7f800000)) ? 1 : 0;
+    }
+    __syncthreads();
+    const float cut2n = rmsd_cut * rmsd_cut * (float)n_atoms;
+    int count = 0;
+    for (int r = 0; r < top_k; r++) {
+        unsigned long long best = ~0ull;
+        for (int c = tid; c < n_chains; c += nt) {
+            if (!alive[c]) continue;
+            const uint32_t b = __float_as_uint(records[(long)c * kRecWords + kRecE]);
+            const uint32_t key = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+            const unsigned long long k = ((unsigned long long)key << 32) | (uint32_t)c;
+            best = k < best ? k : best;
+        }
+        for (int m = 32; m >= 1; m >>= 1) {
+            const unsigned long long o = __shfl_xor(best, m, 64);
+            best = o < best ? o : best;
+        }
+        if ((tid & 63) == 0) s_red[tid >> 6] = best;
+        __syncthreads();
+        if (tid == 0) {
+            unsigned long long b = ~0ull;
+            for (int w = 0; w < (nt >> 6); w++) b = s_red[w] < b ? s_red[w] : b;
+            s_pick = b == ~0ull ? -1 : (int)(uint32_t)(b & 0xffffffffu);
+        }
+        __syncthreads();
+        const int pick = s_pick;
+        if (pick < 0) break;
+        if (tid == 0) sel[1 + count] = pick;
+        count++;
+        const float4 *xp = best_xyz + (long)pick * n_atoms;
+        for (int c = tid; c < n_chains; c += nt) {
+            if (!alive[c]) continue;
+            const float4 *xc = best_xyz + (long)c * n_atoms;
+            float s = 0.f;
+            for (int a = 0; a < n_atoms; a++) {
+                const float4 p = xp[a], q = xc[a];
+                const float dx = p.x - q.x, dy = p.y - q.y, dz = p.z - q.z;
+                s += dx * dx + dy * dy + dz * dz;
+            }
+            if (s <= cut2n || c == pick) alive[c] = 0;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) sel[0] = count;
+}
+
+inline int pick_waves(size_t blob_bytes, size_t chain_bytes)
+{
+    // up to 4 waves per workgroup while the LDS stays within 64 KB
+    int w = 4;
+    while (w > 1 && blob_bytes + w * chain_bytes > 65536) w--;
+    return w;
+}
+
+}  // namespace
+
+size_t chain_lds_bytes(const LigHeader &h)
+{
+    const ChainLayout c = chain_layout(h.n_atoms, h.n_frags, h.n_pairs, 6 + h.n_tors, 7 + h.n_tors);
+    return (size_t)c.words * 4;
+}
+
+hipError_t launch_eval(const uint32_t *blob, int blob_words, const LigHeader &h, const GridView &g,
+                       const SearchParams &p, const float *poses, int n, float *energy, float *grad, float *xyz,
+                       hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    const size_t cb = chain_lds_bytes(h), bb = (size_t)blob_words * 4;
+    const int w = pick_waves(bb, cb);
+    const int blocks = (n + w - 1) / w;
+    eval_kernel<<<blocks, 64 * w, bb + w * cb, stream>>>(blob, blob_words, g, p, poses, n, energy, grad, xyz);
+    return hipGetLastError();
+}
+
+hipError_t launch_local_opt(const uint32_t *blob, int blob_words, const LigHeader &h, const GridView &g,
+                            const SearchParams &p, const float *poses_in, int n, float *poses_out, float *energy,
+                            int *evals, hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    const size_t cb = chain_lds_bytes(h), bb = (size_t)blob_words * 4;
+    const int w = pick_waves(bb, cb);
+    const int blocks = (n + w - 1) / w;
+    local_opt_kernel<<<blocks, 64 * w, bb + w * cb, stream>>>(blob, blob_words, g, p, poses_in, n, poses_out, energy,
+                                                               evals);
+    return hipGetLastError();
+}
+
+hipError_t launch_dock(const uint32_t *blob, int blob_words, const LigHeader &h, const GridView &g,
+                       const SearchParams &p, int n_chains, int n_steps, uint64_t seed, float *records,
+                       float4 *best_xyz, hipStream_t stream)
+{
+    if (n_chains <= 0) return hipSuccess;
+    const size_t cb = chain_lds_bytes(h), bb = (size_t)blob_words * 4;
+    const int w = 1;
+    const int blocks = (n_chains + w - 1) / w;
+    dock_kernel<<<blocks, 64 * w, bb + w * cb, stream>>>(blob, blob_words, g, p, n_chains, n_steps, seed, records,
+                                                          best_xyz);
+    return hipGetLastError();
+}
+
+hipError_t launch_rank(const float *records, const float4 *best_xyz, int n_chains, int n_atoms, int top_k,
+                       float rmsd_cut, int *sel, hipStream_t stream)
+{
+    const int threads = n_chains >= 1024 ? 1024 : ((n_chains + 63) / 64) * 64;
+    rank_kernel<<<1, threads < 64 ? 64 : threads, (size_t)n_chains, stream>>>(records, best_xyz, n_chains, n_atoms,
+                                                                              top_k, rmsd_cut, sel);
+    return hipGetLastError();
+}
+
+}  // namespace dsdp

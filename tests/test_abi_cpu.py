@@ -1,0 +1,105 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point include/dsdp.h declares, and rejects malformed input with the
+documented status codes before touching the device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2303_09916_amd as D
+from synth import make_config, make_ligand, PALETTE_T9
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    src = open(os.path.join(ROOT, "include", "dsdp.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dsdp_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = C.CDLL(D.LIB_PATH)
+    names = declared()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(D.EXPORTED)
+
+
+def test_version_and_defaults():
+    assert "gfx950" in D.dsdp_version()
+    p = D.dsdp_params_default()
+    assert p.struct_size == C.sizeof(D.dsdp_params)
+    assert (p.temperature, p.bfgs_iters, p.ls_trials) == (pytest.approx(1.2), 20, 10)
+
+
+def test_geometry_queries():
+    box = {"centre": (1.0, 2.0, 3.0), "size": 30.0, "spacing": 0.375}
+    n, origin = D.dsdp_grid_dims(box)
+    assert n == (81, 81, 81)
+    np.testing.assert_allclose(origin, np.array([1.0, 2.0, 3.0]) - 15.0, atol=1e-5)
+    assert D.dsdp_grids_bytes(box, 8) == 81 ** 3 * 8 * 16
+    assert D.dsdp_grids_bytes(box, 0) == 0
+    assert D.dsdp_grids_bytes({"centre": (0, 0, 0), "size": 0.1, "spacing": 0.375}, 4) == 0
+    with pytest.raises(D.DsdpError) as e:
+        D.dsdp_grid_dims({"centre": (0, 0, 0), "size": 10.0, "spacing": -1.0})
+    assert e.value.status == D.DSDP_ERR_INVALID_ARG
+
+
+class FakeDev:
+    """Stands in for a device tensor in calls that must fail before any device access."""
+
+    def __init__(self, n):
+        self.n = n
+
+    def data_ptr(self):
+        return 4096
+
+    def numel(self):
+        return self.n
+
+    def element_size(self):
+        return 1
+
+
+def test_build_grids_rejects_bad_input():
+    cfg = make_config(1)
+    rec, box = cfg["receptor"], cfg["box"]
+    need = D.dsdp_grids_bytes(box, 4)
+    wneed = D.dsdp_build_grids_workspace_bytes(rec.n, box)
+    cases = [
+        (dict(types=[0, 0]), D.DSDP_ERR_INVALID_ARG),
+        (dict(types=[0, 99]), D.DSDP_ERR_INVALID_ARG),
+        (dict(maps=FakeDev(need - 16)), D.DSDP_ERR_WORKSPACE_TOO_SMALL),
+        (dict(ws=FakeDev(wneed - 1)), D.DSDP_ERR_WORKSPACE_TOO_SMALL),
+        (dict(rtypes=np.full(rec.n, 40)), D.DSDP_ERR_INVALID_ARG),
+    ]
+    for over, code in cases:
+        with pytest.raises(D.DsdpError) as e:
+            D.dsdp_build_grids(rec.xyz, over.get("rtypes", rec.types), box, over.get("types", cfg["map_types"]),
+                               over.get("maps", FakeDev(need)), over.get("ws", FakeDev(wneed)))
+        assert e.value.status == code, (over, e.value)
+
+
+def test_ligand_validation():
+    lig = make_ligand(20, 4, seed=1, palette=PALETTE_T9)
+    ok = D.Ligand.from_synth(lig)
+    assert D.dsdp_dock_workspace_bytes(ok, 32) > 0
+    bad_parent = lig.frag_parent.copy()
+    bad_parent[2] = 3
+    bad_axis = lig.axis.copy()
+    bad_axis[1] = bad_axis[1][::-1]
+    big = make_ligand(64, 3, seed=2, palette=PALETTE_T9)
+    for L in (D.Ligand(lig.xyz, lig.types, lig.frag_start, bad_parent, lig.axis, lig.bonds),
+              D.Ligand(lig.xyz, lig.types, lig.frag_start, lig.frag_parent, bad_axis, lig.bonds),
+              D.Ligand(lig.xyz, lig.types, lig.frag_start, lig.frag_parent, lig.axis, lig.bonds[:3]),
+              D.Ligand(lig.xyz, np.full(20, 17), lig.frag_start, lig.frag_parent, lig.axis, lig.bonds)):
+        assert D.dsdp_dock_workspace_bytes(L, 32) == 0
+    assert D.dsdp_dock_workspace_bytes(D.Ligand.from_synth(big), 32) > 0
+    xyz = np.concatenate([big.xyz, big.xyz[:1] + 5])
+    too_big = D.Ligand(xyz, np.concatenate([big.types, big.types[:1]]), np.array([0, 65]), np.array([-1]),
+                       np.array([[-1, -1]]), big.bonds)
+    assert D.dsdp_dock_workspace_bytes(too_big, 32) == 0
