@@ -121,6 +121,7 @@ typedef struct {
     int64_t accepted;                /* Metropolis acceptances */
     int32_t n_nonfinite;             /* chains whose best energy is not finite (excluded from ranking) */
     float kernel_ms;                 /* device time of the search and ranking kernels */
+    float search_ms;                 /* device time of the search kernel alone (HIP events on the call's stream) */
 } dsdp_dock_stats;
 
 /* Message of the calling thread's last error ("" if none).  Never NULL. */
@@ -170,6 +171,13 @@ dsdp_status dsdp_build_grids(const dsdp_atom *rec, int32_t n_rec, const dsdp_box
 
 /* Free a grid handle (not the device maps).  NULL is ignored. */
 void dsdp_grids_release(dsdp_grids g);
+
+/*
+ * Derived sizes of a ligand: the number of intra-ligand pairs the energy sums
+ * (atoms in different rigid fragments, more than three bonds apart) and the
+ * depth of its torsion tree.  Either output may be NULL.
+ */
+dsdp_status dsdp_ligand_info(const dsdp_ligand *lig, int32_t *n_pairs, int32_t *tree_depth);
 
 /*
  * Device workspace bytes for dsdp_dock / dsdp_eval_poses / dsdp_local_opt on

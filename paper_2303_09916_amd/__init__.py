@@ -61,7 +61,7 @@ class dsdp_pose(C.Structure):
 
 class dsdp_dock_stats(C.Structure):
     _fields_ = [("pose_evals", C.c_int64), ("local_opts", C.c_int64), ("accepted", C.c_int64),
-                ("n_nonfinite", C.c_int32), ("kernel_ms", C.c_float)]
+                ("n_nonfinite", C.c_int32), ("kernel_ms", C.c_float), ("search_ms", C.c_float)]
 
 
 _vp = C.c_void_p
@@ -75,6 +75,7 @@ _SIGS = {
     "dsdp_build_grids": (C.c_int32, [C.POINTER(dsdp_atom), C.c_int32, C.POINTER(dsdp_box), C.POINTER(C.c_int32),
                                      C.c_int32, _vp, C.c_size_t, _vp, C.c_size_t, _vp, C.POINTER(_vp)]),
     "dsdp_grids_release": (None, [_vp]),
+    "dsdp_ligand_info": (C.c_int32, [C.POINTER(dsdp_ligand), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "dsdp_dock_workspace_bytes": (C.c_size_t, [C.POINTER(dsdp_ligand), C.c_int32]),
     "dsdp_eval_poses": (C.c_int32, [_vp, C.POINTER(dsdp_ligand), _vp, C.c_int32, C.POINTER(dsdp_params), _vp, _vp,
                                     _vp, _vp, C.c_size_t, _vp]),
@@ -226,6 +227,13 @@ def dsdp_build_grids(rec_xyz, rec_types, box, types, d_maps, d_ws, stream=None):
 
 def dsdp_grids_release(h):
     lib().dsdp_grids_release(h)
+
+
+def dsdp_ligand_info(lig):
+    """(n_pairs, tree_depth) of a marshalled ligand."""
+    n, d = C.c_int32(0), C.c_int32(0)
+    _check(lib().dsdp_ligand_info(C.byref(lig.c), C.byref(n), C.byref(d)))
+    return n.value, d.value
 
 
 def dsdp_dock_workspace_bytes(lig, n_chains):

@@ -359,6 +359,24 @@ dsdp_status upload_blob(const Prepared &pl, char *d_ws, hipStream_t stream)
 
 bool aligned256(const void *p) { return ((uintptr_t)p & 255u) == 0; }
 
+// HIP events released on every return path
+struct Events {
+    hipEvent_t e[3] = {nullptr, nullptr, nullptr};
+    hipError_t create()
+    {
+        for (auto &x : e) {
+            hipError_t r = hipEventCreate(&x);
+            if (r != hipSuccess) return r;
+        }
+        return hipSuccess;
+    }
+    ~Events()
+    {
+        for (auto &x : e)
+            if (x) (void)hipEventDestroy(x);
+    }
+};
+
 }  // namespace
 
 extern "C" {
@@ -514,6 +532,16 @@ dsdp_status dsdp_build_grids(const dsdp_atom *rec, int32_t n_rec, const dsdp_box
 
 void dsdp_grids_release(dsdp_grids g) { delete g; }
 
+dsdp_status dsdp_ligand_info(const dsdp_ligand *lig, int32_t *n_pairs, int32_t *tree_depth)
+{
+    Prepared pl;
+    dsdp_status st = prepare_ligand(lig, nullptr, pl);
+    if (st) return st;
+    if (n_pairs) *n_pairs = pl.h.n_pairs;
+    if (tree_depth) *tree_depth = pl.h.max_depth;
+    return DSDP_OK;
+}
+
 size_t dsdp_dock_workspace_bytes(const dsdp_ligand *lig, int32_t n_chains)
 {
     Prepared pl;
@@ -599,11 +627,10 @@ dsdp_status dsdp_dock(dsdp_grids g, const dsdp_ligand *lig, int32_t n_chains, in
     char *ws = (char *)d_ws;
     st = upload_blob(pl, ws + w.blob, s);
     if (st) return st;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    Events ev;
     if (stats) {
-        HIP_TRY(hipEventCreate(&ev0), "event");
-        HIP_TRY(hipEventCreate(&ev1), "event");
-        HIP_TRY(hipEventRecord(ev0, s), "event");
+        HIP_TRY(ev.create(), "event");
+        HIP_TRY(hipEventRecord(ev.e[0], s), "event");
     }
     float *rec = (float *)(ws + w.records);
     float4 *bxyz = (float4 *)(ws + w.xyz);
@@ -611,8 +638,9 @@ dsdp_status dsdp_dock(dsdp_grids g, const dsdp_ligand *lig, int32_t n_chains, in
     HIP_TRY(launch_dock((const uint32_t *)(ws + w.blob), pl.h.total_words, pl.h, g->view, sp, n_chains, n_steps, seed,
                         rec, bxyz, s),
             "dock launch");
+    if (stats) HIP_TRY(hipEventRecord(ev.e[1], s), "event");
     HIP_TRY(launch_rank(rec, bxyz, n_chains, pl.h.n_atoms, top_k, sp.rmsd_cluster, sel, s), "rank launch");
-    if (stats) HIP_TRY(hipEventRecord(ev1, s), "event");
+    if (stats) HIP_TRY(hipEventRecord(ev.e[2], s), "event");
     std::vector<float> h_rec((size_t)n_chains * kRecWords);
     std::vector<int> h_sel((size_t)top_k + 1);
     HIP_TRY(hipMemcpyAsync(h_rec.data(), rec, h_rec.size() * 4, hipMemcpyDeviceToHost, s), "result copy");
@@ -661,11 +689,11 @@ dsdp_status dsdp_dock(dsdp_grids g, const dsdp_ligand *lig, int32_t n_chains, in
             stats->local_opts += ri[kRecLocalOpts];
             if (!std::isfinite(h_rec[(size_t)c * kRecWords + kRecE])) stats->n_nonfinite++;
         }
-        float ms = 0;
-        HIP_TRY(hipEventElapsedTime(&ms, ev0, ev1), "event");
+        float ms = 0, ms_search = 0;
+        HIP_TRY(hipEventElapsedTime(&ms, ev.e[0], ev.e[2]), "event");
+        HIP_TRY(hipEventElapsedTime(&ms_search, ev.e[0], ev.e[1]), "event");
         stats->kernel_ms = ms;
-        (void)hipEventDestroy(ev0);
-        (void)hipEventDestroy(ev1);
+        stats->search_ms = ms_search;
     }
     return DSDP_OK;
 }
