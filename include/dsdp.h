@@ -99,6 +99,9 @@ typedef struct {
     int32_t ls_trials;       /* Armijo trials per iteration (10) */
     float ls_shrink;         /* step shrink factor per failed trial (0.1) */
     float armijo_c1;         /* sufficient-decrease constant (1e-4) */
+    int32_t waves_per_chain; /* wavefronts per chain, 1..4: that many line-search trials are
+                                evaluated at once; results do not depend on it.  0 = chosen
+                                by the library from the chain count and the device (0) */
 } dsdp_params;
 
 /* One ranked output pose. */

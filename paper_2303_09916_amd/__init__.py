@@ -50,7 +50,8 @@ class dsdp_ligand(C.Structure):
 class dsdp_params(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("temperature", C.c_float), ("wall_slope", C.c_float),
                 ("rmsd_cluster", C.c_float), ("trans_amp", C.c_float), ("bfgs_iters", C.c_int32),
-                ("ls_trials", C.c_int32), ("ls_shrink", C.c_float), ("armijo_c1", C.c_float)]
+                ("ls_trials", C.c_int32), ("ls_shrink", C.c_float), ("armijo_c1", C.c_float),
+                ("waves_per_chain", C.c_int32)]
 
 
 class dsdp_pose(C.Structure):

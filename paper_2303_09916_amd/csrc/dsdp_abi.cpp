@@ -189,8 +189,9 @@ dsdp_status prepare_ligand(const dsdp_ligand *lig, const int *map_of_type, Prepa
         adj[lig->bonds[2 * b]].push_back(lig->bonds[2 * b + 1]);
         adj[lig->bonds[2 * b + 1]].push_back(lig->bonds[2 * b]);
     }
-    std::vector<uint32_t> pairs;
-    std::vector<float> rsum;
+    // pairs ordered by (j - i, i): 64 consecutive pairs (one wave-wide step of the
+    // kernel) then touch distinct atoms, so their force updates do not collide
+    std::vector<std::pair<int, int>> plist;
     for (int i = 0; i < na; i++) {
         std::vector<int> dist(na, 1 << 20), queue;
         dist[i] = 0;
@@ -202,20 +203,20 @@ dsdp_status prepare_ligand(const dsdp_ligand *lig, const int *map_of_type, Prepa
                     queue.push_back(v);
                 }
         for (int j = i + 1; j < na; j++)
-            if (frag_of[i] != frag_of[j] && dist[j] > 3) {
-                const int ti = lig->atoms[i].xs_type, tj = lig->atoms[j].xs_type;
-                pairs.push_back((uint32_t)i | ((uint32_t)j << 8) | (pair_flags(ti, tj) << 16));
-                rsum.push_back(xs_radius(ti) + xs_radius(tj));
-            }
+            if (frag_of[i] != frag_of[j] && dist[j] > 3) plist.emplace_back(i, j);
+    }
+    std::stable_sort(plist.begin(), plist.end(), [](const std::pair<int, int> &a, const std::pair<int, int> &b) {
+        return (a.second - a.first) < (b.second - b.first);
+    });
+    std::vector<uint32_t> pairs;
+    std::vector<float> rsum;
+    for (const auto &ij : plist) {
+        const int i = ij.first, j = ij.second;
+        const int ti = lig->atoms[i].xs_type, tj = lig->atoms[j].xs_type;
+        pairs.push_back((uint32_t)i | ((uint32_t)j << 8) | (pair_flags(ti, tj) << 16));
+        rsum.push_back(xs_radius(ti) + xs_radius(tj));
     }
     const int np = (int)pairs.size();
-    // per-atom pair lists (pair order)
-    std::vector<std::vector<uint32_t>> lists(na);
-    for (int p = 0; p < np; p++) {
-        const int i = pairs[p] & 255u, j = (pairs[p] >> 8) & 255u;
-        lists[i].push_back((uint32_t)j | ((uint32_t)p << 8));
-        lists[j].push_back((uint32_t)i | ((uint32_t)p << 8));
-    }
     // depth and subtree masks
     int max_depth = 0;
     std::vector<int> depth(nf, 0);
@@ -249,8 +250,6 @@ dsdp_status prepare_ligand(const dsdp_ligand *lig, const int *map_of_type, Prepa
     h.off_frag_start = take(nf + 1, 1);
     h.off_pair = take(np, 1);
     h.off_pair_rsum = take(np, 1);
-    h.off_csr_start = take(na + 1, 1);
-    h.off_csr = take(2 * np, 1);
     h.total_words = (w + 3) / 4 * 4;
 
     std::vector<uint32_t> blob((size_t)h.total_words, 0u);
@@ -295,12 +294,6 @@ dsdp_status prepare_ligand(const dsdp_ligand *lig, const int *map_of_type, Prepa
         blob[(size_t)h.off_pair + p] = pairs[p];
         fput(h.off_pair_rsum + p, rsum[p]);
     }
-    int e = 0;
-    for (int i = 0; i < na; i++) {
-        blob[(size_t)h.off_csr_start + i] = (uint32_t)e;
-        for (uint32_t v : lists[i]) blob[(size_t)h.off_csr + e++] = v;
-    }
-    blob[(size_t)h.off_csr_start + na] = (uint32_t)e;
     out.h = h;
     out.blob.swap(blob);
     return DSDP_OK;
@@ -328,7 +321,8 @@ dsdp_status check_params(const dsdp_params *p)
     if (!p) return DSDP_OK;
     if (p->struct_size != sizeof(dsdp_params)) return fail(DSDP_ERR_INVALID_ARG, "params.struct_size mismatch");
     if (!(p->temperature > 0) || !(p->wall_slope >= 0) || !(p->rmsd_cluster >= 0) || !(p->trans_amp >= 0) ||
-        p->bfgs_iters < 0 || p->ls_trials < 1 || !(p->ls_shrink > 0 && p->ls_shrink < 1) || !(p->armijo_c1 >= 0))
+        p->bfgs_iters < 0 || p->ls_trials < 1 || !(p->ls_shrink > 0 && p->ls_shrink < 1) || !(p->armijo_c1 >= 0) ||
+        p->waves_per_chain < 0 || p->waves_per_chain > 4)
         return fail(DSDP_ERR_INVALID_ARG, "search parameter out of range");
     return DSDP_OK;
 }
@@ -358,6 +352,38 @@ dsdp_status upload_blob(const Prepared &pl, char *d_ws, hipStream_t stream)
 }
 
 bool aligned256(const void *p) { return ((uintptr_t)p & 255u) == 0; }
+
+// Compute units of the current device (cached per device).
+int device_cus()
+{
+    static thread_local int dev_cached = -1, cus = 0;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (dev != dev_cached) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+        cus = v;
+        dev_cached = dev;
+    }
+    return cus;
+}
+
+// Waves per chain: the caller's choice, else enough to put about one wave on
+// each SIMD (four per compute unit) when chains are few; every choice gives the
+// same results.  Reduced until the workgroup's LDS fits in 64 KB.
+dsdp_status pick_waves(const dsdp_params *prm, const LigHeader &h, int n_chains, int &waves)
+{
+    int w = (prm && prm->waves_per_chain > 0) ? prm->waves_per_chain : 0;
+    if (w == 0) {
+        const long simds = 4L * device_cus();
+        w = (int)std::max(1L, std::min(4L, simds / std::max(1, n_chains)));
+    }
+    while (w > 1 && search_lds_bytes(h, w) > 65536) w--;
+    if (search_lds_bytes(h, w) > 65536)
+        return fail(DSDP_ERR_UNSUPPORTED, "ligand needs %zu bytes of LDS per chain", search_lds_bytes(h, 1));
+    waves = w;
+    return DSDP_OK;
+}
 
 // HIP events released on every return path
 struct Events {
@@ -397,6 +423,7 @@ void dsdp_params_default(dsdp_params *p)
     p->ls_trials = 10;
     p->ls_shrink = 0.1f;
     p->armijo_c1 = 1e-4f;
+    p->waves_per_chain = 0;
 }
 
 dsdp_status dsdp_grid_dims(const dsdp_box *box, int32_t *n, float *origin)
@@ -596,7 +623,10 @@ dsdp_status dsdp_local_opt(dsdp_grids g, const dsdp_ligand *lig, const float *d_
     char *ws = (char *)d_ws;
     st = upload_blob(pl, ws + w.blob, s);
     if (st) return st;
-    HIP_TRY(launch_local_opt((const uint32_t *)(ws + w.blob), pl.h.total_words, pl.h, g->view, to_search(prm),
+    int waves = 1;
+    st = pick_waves(prm, pl.h, n_poses, waves);
+    if (st) return st;
+    HIP_TRY(launch_local_opt((const uint32_t *)(ws + w.blob), pl.h.total_words, pl.h, g->view, to_search(prm), waves,
                              d_poses_in, n_poses, d_poses_out, d_energy, d_evals, s),
             "local-opt launch");
     return DSDP_OK;
@@ -623,6 +653,9 @@ dsdp_status dsdp_dock(dsdp_grids g, const dsdp_ligand *lig, int32_t n_chains, in
     if (!d_ws || ws_bytes < w.total) return fail(DSDP_ERR_WORKSPACE_TOO_SMALL, "workspace needs %zu bytes", w.total);
     if (!aligned256(d_ws)) return fail(DSDP_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
     const SearchParams sp = to_search(prm);
+    int waves = 1;
+    st = pick_waves(prm, pl.h, n_chains, waves);
+    if (st) return st;
     hipStream_t s = (hipStream_t)stream;
     char *ws = (char *)d_ws;
     st = upload_blob(pl, ws + w.blob, s);
@@ -635,8 +668,8 @@ dsdp_status dsdp_dock(dsdp_grids g, const dsdp_ligand *lig, int32_t n_chains, in
     float *rec = (float *)(ws + w.records);
     float4 *bxyz = (float4 *)(ws + w.xyz);
     int *sel = (int *)(ws + w.sel);
-    HIP_TRY(launch_dock((const uint32_t *)(ws + w.blob), pl.h.total_words, pl.h, g->view, sp, n_chains, n_steps, seed,
-                        rec, bxyz, s),
+    HIP_TRY(launch_dock((const uint32_t *)(ws + w.blob), pl.h.total_words, pl.h, g->view, sp, waves, n_chains, n_steps,
+                        seed, rec, bxyz, s),
             "dock launch");
     if (stats) HIP_TRY(hipEventRecord(ev.e[1], s), "event");
     HIP_TRY(launch_rank(rec, bxyz, n_chains, pl.h.n_atoms, top_k, sp.rmsd_cluster, sel, s), "rank launch");

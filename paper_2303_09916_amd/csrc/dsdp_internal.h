@@ -71,8 +71,6 @@ struct LigHeader {
     int32_t off_frag_start;  // int[n_frags + 1]
     int32_t off_pair;        // uint32[n_pairs]: i | j << 8 | flags << 16
     int32_t off_pair_rsum;   // float[n_pairs]: R_i + R_j
-    int32_t off_csr_start;   // int[n_atoms + 1]: pairs of atom i
-    int32_t off_csr;         // uint32[2 n_pairs]: partner | pair << 8
     int32_t total_words;     // multiple of 4
 };
 constexpr int kHeaderWords = (int)(sizeof(LigHeader) / 4 + 3) / 4 * 4;
@@ -98,15 +96,15 @@ struct SearchParams {
 hipError_t launch_grid_build(const float4 *atoms, const int *cell_start, const int *cn, const float *clo,
                              float cell, const GridView &g, const int *map_types_host, float4 *maps,
                              hipStream_t stream);
-size_t chain_lds_bytes(const LigHeader &h);
+size_t search_lds_bytes(const LigHeader &h, int waves);
 hipError_t launch_eval(const uint32_t *blob, int blob_words, const LigHeader &h, const GridView &g,
                        const SearchParams &p, const float *poses, int n, float *energy, float *grad, float *xyz,
                        hipStream_t stream);
 hipError_t launch_local_opt(const uint32_t *blob, int blob_words, const LigHeader &h, const GridView &g,
-                            const SearchParams &p, const float *poses_in, int n, float *poses_out, float *energy,
-                            int *evals, hipStream_t stream);
+                            const SearchParams &p, int waves, const float *poses_in, int n, float *poses_out,
+                            float *energy, int *evals, hipStream_t stream);
 hipError_t launch_dock(const uint32_t *blob, int blob_words, const LigHeader &h, const GridView &g,
-                       const SearchParams &p, int n_chains, int n_steps, uint64_t seed, float *records,
+                       const SearchParams &p, int waves, int n_chains, int n_steps, uint64_t seed, float *records,
                        float4 *best_xyz, hipStream_t stream);
 hipError_t launch_rank(const float *records, const float4 *best_xyz, int n_chains, int n_atoms, int top_k,
                        float rmsd_cut, int *sel, hipStream_t stream);

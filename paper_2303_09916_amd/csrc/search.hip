@@ -31,13 +31,27 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Butterfly sum: every lane ends with the same bits (each step adds a pair of
-// operands in both lanes, and addition commutes).
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float read_lane(float v, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+// Sum over the 64 lanes; every lane gets the same bits.  Within each row of 16
+// lanes, four DPP steps pair lanes symmetrically (quad swaps, half-row mirror,
+// row mirror), so both members of a pair add the same two operands; the four
+// row sums are then read out and added in a fixed order.
 __device__ __forceinline__ float wave_sum(float v)
 {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-    return v;
+    v += dpp<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp<0x141>(v);   // row_half_mirror
+    v += dpp<0x140>(v);   // row_mirror
+    return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
 }
 
 // ---------------------------------------------------------------- Philox4x32-10
@@ -77,8 +91,7 @@ __device__ __forceinline__ M3 quat_to_mat(float w, float x, float y, float z)
 }
 __device__ __forceinline__ M3 axis_angle(float ux, float uy, float uz, float th)
 {
-    float s, c;
-    sincosf(th, &s, &c);
+    const float s = __sinf(th), c = __cosf(th);
     const float t = 1 - c;
     M3 R;
     R.a[0] = c + t * ux * ux;      R.a[1] = t * ux * uy - s * uz; R.a[2] = t * ux * uz + s * uy;
@@ -105,6 +118,15 @@ __device__ __forceinline__ float3 cross3(float3 a, float3 b)
     return make_float3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
 }
 __device__ __forceinline__ float3 f3(float4 v) { return make_float3(v.x, v.y, v.z); }
+__device__ __forceinline__ M3 load_m3(const float4 *rows)
+{
+    const float4 r0 = rows[0], r1 = rows[1], r2 = rows[2];
+    M3 M;
+    M.a[0] = r0.x; M.a[1] = r0.y; M.a[2] = r0.z;
+    M.a[3] = r1.x; M.a[4] = r1.y; M.a[5] = r1.z;
+    M.a[6] = r2.x; M.a[7] = r2.y; M.a[8] = r2.z;
+    return M;
+}
 __device__ __forceinline__ float3 operator+(float3 a, float3 b) { return make_float3(a.x + b.x, a.y + b.y, a.z + b.z); }
 __device__ __forceinline__ float3 operator-(float3 a, float3 b) { return make_float3(a.x - b.x, a.y - b.y, a.z - b.z); }
 __device__ __forceinline__ float3 operator*(float s, float3 a) { return make_float3(s * a.x, s * a.y, s * a.z); }
@@ -115,8 +137,7 @@ __device__ __forceinline__ float4 quat_of_rotvec(float vx, float vy, float vz)
 {
     const float a = sqrtf(vx * vx + vy * vy + vz * vz);
     if (a == 0.0f) return make_float4(1.f, 0.f, 0.f, 0.f);   // (w, x, y, z)
-    float s, c;
-    sincosf(0.5f * a, &s, &c);
+    const float s = __sinf(0.5f * a), c = __cosf(0.5f * a);
     const float k = s / a;
     return make_float4(c, k * vx, k * vy, k * vz);
 }
@@ -130,8 +151,8 @@ __device__ __forceinline__ float4 quat_mul(float4 a, float4 b)
 }
 __device__ __forceinline__ float4 quat_normalize(float4 q)
 {
-    const float n = sqrtf(q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w);
-    return make_float4(q.x / n, q.y / n, q.z / n, q.w / n);
+    const float k = rsqrtf(q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w);
+    return make_float4(q.x * k, q.y * k, q.z * k, q.w * k);
 }
 // into (-pi, pi]; non-finite values pass through, huge ones are reduced first
 __device__ __forceinline__ float wrap_angle(float t)
@@ -146,8 +167,7 @@ __device__ __forceinline__ float wrap_angle(float t)
 __device__ __forceinline__ float3 ball(float u1, float u2, float u3)
 {
     const float z = 2 * u1 - 1, r = cbrtf(u3);
-    float s, c;
-    sincosf(2 * kPi * u2, &s, &c);
+    const float s = __sinf(2 * kPi * u2), c = __cosf(2 * kPi * u2);
     const float q = sqrtf(fmaxf(0.0f, 1 - z * z));
     return make_float3(r * q * c, r * q * s, r * z);
 }
@@ -185,48 +205,94 @@ struct LigL {
     const int *frag_start;
     const uint32_t *pair;
     const float *rsum;
-    const int *csr_start;
-    const uint32_t *csr;
 };
 
-struct ChainL {
-    float4 *xyz, *frc, *trq;
+// Scratch of one pose evaluation (one per wave).
+struct WaveL {
+    float4 *xyz;
+    float *fx, *fy, *fz;   // [na4] per-atom pair-force accumulators (planes, one bank per atom)
+    float *ft;             // [6][nf4] per-fragment force and torque accumulators (planes)
+    int nf4;
     float4 *R;       // [nf][4]: rows of R_k, then origin o_k
     float4 *Q;       // [nf][3]: rotation of fragment k relative to its parent (root: R(q))
-    float4 *FT;      // [nf][2]: force, torque (about o_k) summed over fragment k's atoms
-    float *spair;    // [np]: dE/dr / r of each pair
-    float *g, *p, *s, *y, *Hy, *gt, *tmp;
-    float *H;
-    int hs;
-    float *cur, *trial, *cand, *best;
-    float *misc;
+    float *trial;    // [NXp]: this wave's trial pose
+    float *gt;       // [Dp]: gradient at the trial pose
 };
+
+// State of one chain, shared by the waves that work on it.
+struct ChainL {
+    float *g, *p, *s, *y, *Hy;   // [Dp] BFGS vectors (tangent coordinates)
+    float *H;                    // [D][hs] inverse-Hessian estimate, row j owned by lane j
+    int hs;
+    float *cur, *cand, *best;    // [NXp] poses
+    float *et;                   // [4 * kMaxWaves]: energies (total, inter, intra, wall) per trial slot
+    float *misc;                 // [48]: initial draws and scalars
+};
+
+constexpr int kMaxWaves = 4;     // waves per chain (concurrent line-search trials)
+constexpr int kMiscGp = 40;      // slot of g.p in misc
 
 __host__ __device__ inline int rup4(int v) { return (v + 3) & ~3; }
 
-struct ChainLayout {
-    int xyz, frc, trq, R, Q, FT, spair, vec, H, hs, pose, misc, words, Dp, NXp;
+struct Layout {
+    int xyz, frc, na4, R, Q, FT, nf4, trial, gt, wave_words;  // per-wave offsets
+    int vec, H, hs, pose, et, misc, chain_words, Dp, NXp;     // per-chain offsets
 };
-__host__ __device__ inline ChainLayout chain_layout(int na, int nf, int np, int D, int nx)
+__host__ __device__ inline Layout make_layout(int na, int nf, int D, int nx)
 {
-    ChainLayout c;
+    Layout c;
+    c.Dp = rup4(D);
+    c.NXp = rup4(nx);
     int w = 0;
     c.xyz = w; w += 4 * na;
-    c.frc = w; w += 4 * na;
-    c.trq = w; w += 4 * na;
+    c.na4 = rup4(na);
+    c.frc = w; w += 3 * c.na4;
     c.R = w; w += 16 * nf;
     c.Q = w; w += 12 * nf;
-    c.FT = w; w += 8 * nf;
-    c.spair = w; w += rup4(np);
-    c.Dp = rup4(D);
-    c.vec = w; w += 7 * c.Dp;
+    c.nf4 = rup4(nf);
+    c.FT = w; w += 6 * c.nf4;
+    c.trial = w; w += c.NXp;
+    c.gt = w; w += c.Dp;
+    c.wave_words = w;
+    w = 0;
+    c.vec = w; w += 5 * c.Dp;
     c.hs = D + 1;
     c.H = w; w += rup4(D * c.hs);
-    c.NXp = rup4(nx);
-    c.pose = w; w += 4 * c.NXp;
+    c.pose = w; w += 3 * c.NXp;
+    c.et = w; w += 4 * kMaxWaves;
     c.misc = w; w += 48;
-    c.words = w;
+    c.chain_words = w;
     return c;
+}
+
+__device__ inline WaveL make_wave(float *base, const Layout &c)
+{
+    WaveL S;
+    S.xyz = reinterpret_cast<float4 *>(base + c.xyz);
+    S.fx = base + c.frc;
+    S.fy = S.fx + c.na4;
+    S.fz = S.fy + c.na4;
+    S.R = reinterpret_cast<float4 *>(base + c.R);
+    S.Q = reinterpret_cast<float4 *>(base + c.Q);
+    S.ft = base + c.FT;
+    S.nf4 = c.nf4;
+    S.trial = base + c.trial;
+    S.gt = base + c.gt;
+    return S;
+}
+
+__device__ inline ChainL make_chain(float *base, const Layout &c)
+{
+    ChainL C;
+    float *v = base + c.vec;
+    C.g = v; C.p = v + c.Dp; C.s = v + 2 * c.Dp; C.y = v + 3 * c.Dp; C.Hy = v + 4 * c.Dp;
+    C.H = base + c.H;
+    C.hs = c.hs;
+    float *p = base + c.pose;
+    C.cur = p; C.cand = p + c.NXp; C.best = p + 2 * c.NXp;
+    C.et = base + c.et;
+    C.misc = base + c.misc;
+    return C;
 }
 
 __device__ inline LigL make_lig(const uint32_t *blob)
@@ -243,30 +309,29 @@ __device__ inline LigL make_lig(const uint32_t *blob)
     L.frag_start = reinterpret_cast<const int *>(blob + h->off_frag_start);
     L.pair = blob + h->off_pair;
     L.rsum = reinterpret_cast<const float *>(blob + h->off_pair_rsum);
-    L.csr_start = reinterpret_cast<const int *>(blob + h->off_csr_start);
-    L.csr = blob + h->off_csr;
     return L;
 }
 
-__device__ inline ChainL make_chain(float *base, const ChainLayout &c)
+// A lane's share of the intra-ligand pair list (pairs lane, lane + 64, ...),
+// loaded once per chain; unused slots carry kPairNone.
+constexpr uint32_t kPairNone = 0x80000000u;
+template <int PPL>
+struct PairRegs {
+    uint32_t w[PPL];
+    float rs[PPL];
+};
+template <int PPL>
+__device__ inline PairRegs<PPL> load_pairs(const LigL &L)
 {
-    ChainL S;
-    S.xyz = reinterpret_cast<float4 *>(base + c.xyz);
-    S.frc = reinterpret_cast<float4 *>(base + c.frc);
-    S.trq = reinterpret_cast<float4 *>(base + c.trq);
-    S.R = reinterpret_cast<float4 *>(base + c.R);
-    S.Q = reinterpret_cast<float4 *>(base + c.Q);
-    S.FT = reinterpret_cast<float4 *>(base + c.FT);
-    S.spair = base + c.spair;
-    float *v = base + c.vec;
-    S.g = v; S.p = v + c.Dp; S.s = v + 2 * c.Dp; S.y = v + 3 * c.Dp; S.Hy = v + 4 * c.Dp; S.gt = v + 5 * c.Dp;
-    S.tmp = v + 6 * c.Dp;
-    S.H = base + c.H;
-    S.hs = c.hs;
-    float *p = base + c.pose;
-    S.cur = p; S.trial = p + c.NXp; S.cand = p + 2 * c.NXp; S.best = p + 3 * c.NXp;
-    S.misc = base + c.misc;
-    return S;
+    PairRegs<PPL> pr;
+    const int lane = lane_id();
+#pragma unroll
+    for (int k = 0; k < PPL; k++) {
+        const int p = lane + 64 * k;
+        pr.w[k] = p < L.np ? L.pair[p] : kPairNone;
+        pr.rs[k] = p < L.np ? L.rsum[p] : 0.f;
+    }
+    return pr;
 }
 
 // ---------------------------------------------------------------- evaluation
@@ -277,12 +342,14 @@ struct Energy {
 // Energy of `pose` (LDS, wave-uniform) and, if grad != nullptr, its gradient in
 // the tangent coordinates written to grad[0..D) (LDS).  Coordinates are left in
 // S.xyz.  Every lane returns the same values.
-__device__ Energy eval_pose(const LigL &L, const ChainL &S, const GridView &G, const float *pose, float *grad,
-                            float wall_slope)
+template <int PPL>
+__device__ Energy eval_pose(const LigL &L, const WaveL &S, const PairRegs<PPL> &pr, const GridView &G,
+                            const float *pose, float *grad, float wall_slope)
 {
     const int lane = lane_id();
 
-    // (1) rotation of every fragment relative to its parent; the root's is R(q)
+    // (1) rotation of every fragment relative to its parent (root: R(q)); clear
+    //     the fragment force/torque accumulators
     if (lane < L.nf) {
         M3 Q;
         if (lane == 0) {
@@ -295,37 +362,23 @@ __device__ Energy eval_pose(const LigL &L, const ChainL &S, const GridView &G, c
         S.Q[3 * lane + 0] = make_float4(Q.a[0], Q.a[1], Q.a[2], 0.f);
         S.Q[3 * lane + 1] = make_float4(Q.a[3], Q.a[4], Q.a[5], 0.f);
         S.Q[3 * lane + 2] = make_float4(Q.a[6], Q.a[7], Q.a[8], 0.f);
+#pragma unroll
+        for (int q = 0; q < 6; q++) S.ft[q * S.nf4 + lane] = 0.f;
     }
     wave_sync();
 
     // (2) world frame of fragment k: compose along its ancestry (bottom-up)
     //     R_k = R_0 Q_a1 .. Q_k,  o_k = p + R_0 (off_a1 + Q_a1 (off_a2 + ... off_k))
     if (lane < L.nf) {
-        M3 R0;
-        {
-            const float4 r0 = S.Q[0], r1 = S.Q[1], r2 = S.Q[2];
-            R0.a[0] = r0.x; R0.a[1] = r0.y; R0.a[2] = r0.z;
-            R0.a[3] = r1.x; R0.a[4] = r1.y; R0.a[5] = r1.z;
-            R0.a[6] = r2.x; R0.a[7] = r2.y; R0.a[8] = r2.z;
-        }
+        const M3 R0 = load_m3(S.Q);
         M3 R = R0;
         float3 o = make_float3(pose[0], pose[1], pose[2]);
         if (lane > 0) {
-            M3 M;
-            {
-                const float4 r0 = S.Q[3 * lane], r1 = S.Q[3 * lane + 1], r2 = S.Q[3 * lane + 2];
-                M.a[0] = r0.x; M.a[1] = r0.y; M.a[2] = r0.z;
-                M.a[3] = r1.x; M.a[4] = r1.y; M.a[5] = r1.z;
-                M.a[6] = r2.x; M.a[7] = r2.y; M.a[8] = r2.z;
-            }
+            M3 M = load_m3(S.Q + 3 * lane);
             float3 v = f3(L.foff[lane]);
             int m = __float_as_int(L.fu[lane].w);
             while (m > 0) {
-                M3 Qm;
-                const float4 r0 = S.Q[3 * m], r1 = S.Q[3 * m + 1], r2 = S.Q[3 * m + 2];
-                Qm.a[0] = r0.x; Qm.a[1] = r0.y; Qm.a[2] = r0.z;
-                Qm.a[3] = r1.x; Qm.a[4] = r1.y; Qm.a[5] = r1.z;
-                Qm.a[6] = r2.x; Qm.a[7] = r2.y; Qm.a[8] = r2.z;
+                const M3 Qm = load_m3(S.Q + 3 * m);
                 v = f3(L.foff[m]) + mv(Qm, v);
                 M = mul(Qm, M);
                 m = __float_as_int(L.fu[m].w);
@@ -340,9 +393,13 @@ __device__ Energy eval_pose(const LigL &L, const ChainL &S, const GridView &G, c
     }
     wave_sync();
 
-    // (3) atom coordinates and the inter-molecular term from the maps
-    float e_atom = 0.f, w_atom = 0.f;
-    float3 x = make_float3(0.f, 0.f, 0.f), f = make_float3(0.f, 0.f, 0.f);
+    // (3) atom coordinates; issue the eight corner gathers of the inter-molecular
+    //     term now and consume them after the intra-ligand pairs
+    float w_atom = 0.f;
+    float3 x = make_float3(0.f, 0.f, 0.f), wg = make_float3(0.f, 0.f, 0.f);
+    float px = 0.f, py = 0.f, pz = 0.f;
+    bool clx = false, cly = false, clz = false;
+    float4 c000, c100, c010, c110, c001, c101, c011, c111;
     int frag = 0;
     if (lane < L.na) {
         frag = L.atom_frag[lane];
@@ -352,31 +409,35 @@ __device__ Energy eval_pose(const LigL &L, const ChainL &S, const GridView &G, c
                         o.y + r1.x * loc.x + r1.y * loc.y + r1.z * loc.z,
                         o.z + r2.x * loc.x + r2.y * loc.y + r2.z * loc.z);
         S.xyz[lane] = make_float4(x.x, x.y, x.z, 0.f);
+        S.fx[lane] = 0.f;
+        S.fy[lane] = 0.f;
+        S.fz[lane] = 0.f;
 
-        // wall and clamping (a coordinate outside the box is clamped onto the face;
-        // the atom pays wall_slope per Angstrom outside; the map gradient along a
-        // clamped axis is dropped)
-        const float xs[3] = {x.x, x.y, x.z};
-        float u[3], wg[3];
+        // wall and clamping: a coordinate outside the box is clamped onto the face;
+        // the atom pays wall_slope per Angstrom outside and the map gradient along
+        // a clamped axis is dropped
         int ci[3];
-        bool cl[3];
+        float u[3];
+        const float xs[3] = {x.x, x.y, x.z};
+        float wgs[3];
+        bool cls[3];
 #pragma unroll
         for (int a = 0; a < 3; a++) {
             const float lo = G.origin[a];
             const float hi = G.origin[a] + (float)(G.n[a] - 1) * G.h;
             float xa = xs[a];
-            wg[a] = 0.f;
-            cl[a] = false;
+            wgs[a] = 0.f;
+            cls[a] = false;
             if (xa < lo) {
                 w_atom += wall_slope * (lo - xa);
-                wg[a] = -wall_slope;
+                wgs[a] = -wall_slope;
                 xa = lo;
-                cl[a] = true;
+                cls[a] = true;
             } else if (xa > hi) {
                 w_atom += wall_slope * (xa - hi);
-                wg[a] = wall_slope;
+                wgs[a] = wall_slope;
                 xa = hi;
-                cl[a] = true;
+                cls[a] = true;
             }
             u[a] = (xa - lo) * G.inv_h;
             int i = (int)floorf(u[a]);
@@ -385,16 +446,51 @@ __device__ Energy eval_pose(const LigL &L, const ChainL &S, const GridView &G, c
             ci[a] = i;
             u[a] -= (float)i;
         }
+        wg = make_float3(wgs[0], wgs[1], wgs[2]);
+        clx = cls[0]; cly = cls[1]; clz = cls[2];
+        px = u[0]; py = u[1]; pz = u[2];
         const int t = __float_as_int(loc.w);
         const long sy = G.n[0], sz = (long)G.n[0] * G.n[1];
         const float4 *m0 = G.maps + (long)t * sz * G.n[2] + ci[2] * sz + ci[1] * sy + ci[0];
-        const float4 c000 = m0[0], c100 = m0[1], c010 = m0[sy], c110 = m0[sy + 1];
-        const float4 c001 = m0[sz], c101 = m0[sz + 1], c011 = m0[sz + sy], c111 = m0[sz + sy + 1];
-        const float px = u[0], py = u[1], pz = u[2];
+        c000 = m0[0]; c100 = m0[1]; c010 = m0[sy]; c110 = m0[sy + 1];
+        c001 = m0[sz]; c101 = m0[sz + 1]; c011 = m0[sz + sy]; c111 = m0[sz + sy + 1];
+    }
+    wave_sync();
+
+    // (4) intra-ligand pairs, PPL per lane held in registers (pair lane + 64 k);
+    //     forces accumulate per atom in LDS
+    float e_pair = 0.f;
+#pragma unroll
+    for (int k = 0; k < PPL; k++) {
+        const uint32_t pw = pr.w[k];
+        const int i = (int)(pw & 255u), j = (int)((pw >> 8) & 255u);
+        const float4 xi = S.xyz[i], xj = S.xyz[j];
+        const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        if (!(pw & kPairNone) && r2 < kCutoff2) {
+            const float inv_r = r2 > 1e-18f ? rsqrtf(r2) : 0.f;
+            const float2 ed = vina_pair(r2 * inv_r - pr.rs[k], pw >> 16);
+            e_pair += ed.x;
+            if (grad != nullptr) {
+                const float sp = ed.y * inv_r;
+                atomicAdd(S.fx + i, sp * dx);
+                atomicAdd(S.fy + i, sp * dy);
+                atomicAdd(S.fz + i, sp * dz);
+                atomicAdd(S.fx + j, -sp * dx);
+                atomicAdd(S.fy + j, -sp * dy);
+                atomicAdd(S.fz + j, -sp * dz);
+            }
+        }
+    }
+
+    // (5) inter-molecular energy and force from the gathered corners: eq. 2 for
+    //     the energy and eq. 4 (the same weights on the stored gradients)
+    float e_atom = 0.f;
+    float3 f = make_float3(0.f, 0.f, 0.f);
+    if (lane < L.na) {
         const float qx = 1.f - px, qy = 1.f - py, qz = 1.f - pz;
         const float w000 = qx * qy * qz, w100 = px * qy * qz, w010 = qx * py * qz, w110 = px * py * qz;
         const float w001 = qx * qy * pz, w101 = px * qy * pz, w011 = qx * py * pz, w111 = px * py * pz;
-        // eq. 2 (energy) and eq. 4 (gradient): the same weights on E and on stored gradients
         const float E = w000 * c000.x + w100 * c100.x + w010 * c010.x + w110 * c110.x + w001 * c001.x +
                         w101 * c101.x + w011 * c011.x + w111 * c111.x;
         float gx = w000 * c000.y + w100 * c100.y + w010 * c010.y + w110 * c110.y + w001 * c001.y + w101 * c101.y +
@@ -403,33 +499,12 @@ __device__ Energy eval_pose(const LigL &L, const ChainL &S, const GridView &G, c
                    w011 * c011.z + w111 * c111.z;
         float gz = w000 * c000.w + w100 * c100.w + w010 * c010.w + w110 * c110.w + w001 * c001.w + w101 * c101.w +
                    w011 * c011.w + w111 * c111.w;
-        if (cl[0]) gx = 0.f;
-        if (cl[1]) gy = 0.f;
-        if (cl[2]) gz = 0.f;
-        f = make_float3(gx + wg[0], gy + wg[1], gz + wg[2]);
+        if (clx) gx = 0.f;
+        if (cly) gy = 0.f;
+        if (clz) gz = 0.f;
+        f = make_float3(gx + wg.x, gy + wg.y, gz + wg.z);
         e_atom = E + w_atom;
     }
-    wave_sync();
-
-    // (4) intra-ligand pairs, strided over lanes; store dE/dr / r per pair
-    float e_pair = 0.f;
-    for (int p = lane; p < L.np; p += 64) {
-        const uint32_t pw = L.pair[p];
-        const int i = (int)(pw & 255u), j = (int)((pw >> 8) & 255u);
-        const float4 xi = S.xyz[i], xj = S.xyz[j];
-        const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
-        const float r2 = dx * dx + dy * dy + dz * dz;
-        float sp = 0.f;
-        if (r2 < kCutoff2) {
-            const float r = sqrtf(r2);
-            const float2 ed = vina_pair(r - L.rsum[p], pw >> 16);
-            e_pair += ed.x;
-            sp = r > 1e-9f ? ed.y / r : 0.f;
-        }
-        S.spair[p] = sp;
-    }
-    wave_sync();
-
     const float e_inter = wave_sum(e_atom);
     const float e_intra = wave_sum(e_pair);
     const float wall = wave_sum(w_atom);
@@ -439,54 +514,43 @@ __device__ Energy eval_pose(const LigL &L, const ChainL &S, const GridView &G, c
     out.wall = wall;
     out.total = e_inter + e_intra;
     if (grad == nullptr) return out;
-
-    // (5) pair forces gathered per atom (CSR, fixed order), then torque about the
-    //     atom's fragment origin
-    if (lane < L.na) {
-        const int e0 = L.csr_start[lane], e1 = L.csr_start[lane + 1];
-        for (int e = e0; e < e1; e++) {
-            const uint32_t w = L.csr[e];
-            const float4 xj = S.xyz[w & 255u];
-            const float sp = S.spair[w >> 8];
-            f = f + sp * (x - f3(xj));
-        }
-        const float3 o = f3(S.R[4 * frag + 3]);
-        const float3 tq = cross3(x - o, f);
-        S.frc[lane] = make_float4(f.x, f.y, f.z, 0.f);
-        S.trq[lane] = make_float4(tq.x, tq.y, tq.z, 0.f);
-    }
     wave_sync();
 
-    // (6) per-fragment sums over the fragment's contiguous atom range
-    if (lane < L.nf) {
-        float3 F = make_float3(0.f, 0.f, 0.f), Tq = make_float3(0.f, 0.f, 0.f);
-        const int a0 = L.frag_start[lane], a1 = L.frag_start[lane + 1];
-        for (int a = a0; a < a1; a++) {
-            F = F + f3(S.frc[a]);
-            Tq = Tq + f3(S.trq[a]);
-        }
-        S.FT[2 * lane] = make_float4(F.x, F.y, F.z, 0.f);
-        S.FT[2 * lane + 1] = make_float4(Tq.x, Tq.y, Tq.z, 0.f);
+    // (6) total atom force; force and torque (about the fragment origin) summed per fragment
+    if (lane < L.na) {
+        f = f + make_float3(S.fx[lane], S.fy[lane], S.fz[lane]);
+        const float3 o = f3(S.R[4 * frag + 3]);
+        const float3 tq = cross3(x - o, f);
+        float *ft = S.ft + frag;
+        atomicAdd(ft, f.x);
+        atomicAdd(ft + S.nf4, f.y);
+        atomicAdd(ft + 2 * S.nf4, f.z);
+        atomicAdd(ft + 3 * S.nf4, tq.x);
+        atomicAdd(ft + 4 * S.nf4, tq.y);
+        atomicAdd(ft + 5 * S.nf4, tq.z);
     }
     wave_sync();
 
     // (7) subtree sums: F_sub(k) = sum F_m, tau_sub(k) = sum T_m + (o_m - o_k) x F_m
     //     over fragments m in k's subtree; dE/dtheta_k = u_k . tau_sub(k)
-    if (lane < L.nf) {
-        uint32_t mask = __float_as_uint(L.foff[lane].w);
-        const float3 ok = f3(S.R[4 * lane + 3]);
+    {
+        const uint32_t mask = lane < L.nf ? __float_as_uint(L.foff[lane].w) : 0u;
+        const float3 ok = lane < L.nf ? f3(S.R[4 * lane + 3]) : make_float3(0.f, 0.f, 0.f);
         float3 F = make_float3(0.f, 0.f, 0.f), Tq = make_float3(0.f, 0.f, 0.f);
-        while (mask) {
-            const int m = __ffs(mask) - 1;
-            mask &= mask - 1;
-            const float3 Fm = f3(S.FT[2 * m]);
-            F = F + Fm;
-            Tq = Tq + f3(S.FT[2 * m + 1]) + cross3(f3(S.R[4 * m + 3]) - ok, Fm);
+#pragma unroll 4
+        for (int m = 0; m < L.nf; m++) {
+            const float3 Fm = make_float3(S.ft[m], S.ft[S.nf4 + m], S.ft[2 * S.nf4 + m]);
+            const float3 Tm = make_float3(S.ft[3 * S.nf4 + m], S.ft[4 * S.nf4 + m], S.ft[5 * S.nf4 + m]);
+            const float3 om = f3(S.R[4 * m + 3]);
+            if ((mask >> m) & 1u) {
+                F = F + Fm;
+                Tq = Tq + Tm + cross3(om - ok, Fm);
+            }
         }
         if (lane == 0) {
             grad[0] = F.x; grad[1] = F.y; grad[2] = F.z;
             grad[3] = Tq.x; grad[4] = Tq.y; grad[5] = Tq.z;
-        } else {
+        } else if (lane < L.nf) {
             const float4 uref = L.fu[lane];
             const float4 r0 = S.R[4 * lane], r1 = S.R[4 * lane + 1], r2 = S.R[4 * lane + 2];
             const float3 u = make_float3(r0.x * uref.x + r0.y * uref.y + r0.z * uref.z,
@@ -518,75 +582,135 @@ __device__ inline void copy_pose(const LigL &L, const float *src, float *dst)
     wave_sync();
 }
 
-// BFGS with Armijo backtracking on pose x (LDS, in place).  Returns the energy of
-// the final pose; *evals counts evaluations.  Gradient of the final pose in S.g.
-__device__ Energy local_opt(const LigL &L, const ChainL &S, const GridView &G, const SearchParams &P, float *x,
-                            int &evals)
+__device__ inline void put_energy(float *slot, const Energy &e)
 {
-    const int lane = lane_id();
-    const int D = L.D;
-    Energy Ex = eval_pose(L, S, G, x, S.g, P.wall_slope);
+    if (lane_id() == 0) {
+        slot[0] = e.total;
+        slot[1] = e.inter;
+        slot[2] = e.intra;
+        slot[3] = e.wall;
+    }
+}
+__device__ inline Energy get_energy(const float *slot)
+{
+    Energy e;
+    e.total = slot[0];
+    e.inter = slot[1];
+    e.intra = slot[2];
+    e.wall = slot[3];
+    return e;
+}
+
+// BFGS with Armijo backtracking on the chain's pose x (LDS, in place), run by all
+// W waves of the workgroup together.  The line search evaluates W consecutive
+// trials at once (alpha_t = shrink^t, one per wave) and accepts the first that
+// passes the Armijo test, which is the trial the one-at-a-time search accepts:
+// the result does not depend on W.  `evals` counts the evaluations the
+// one-at-a-time search makes (speculative trials past the accepted one are not
+// counted).  Wave 0 owns the direction and the inverse-Hessian update.  The
+// final gradient is left in C.g.
+template <int PPL>
+__device__ Energy local_opt_group(const LigL &L, const Layout &lay, float *wave_base, const ChainL &C,
+                                  const PairRegs<PPL> &pr, const GridView &G, const SearchParams &P, float *x,
+                                  int &evals, int W)
+{
+    const int lane = lane_id(), w = wave_id(), D = L.D;
+    const WaveL S = make_wave(wave_base + w * lay.wave_words, lay);
+    if (w == 0) {
+        const Energy e = eval_pose(L, S, pr, G, x, C.g, P.wall_slope);
+        put_energy(C.et, e);
+        if (lane < D)
+            for (int c = 0; c < D; c++) C.H[lane * C.hs + c] = (c == lane) ? 1.f : 0.f;
+    }
+    __syncthreads();
+    Energy Ex = get_energy(C.et);
     evals++;
-    if (lane < D)
-        for (int c = 0; c < D; c++) S.H[lane * S.hs + c] = (c == lane) ? 1.f : 0.f;
-    wave_sync();
     for (int it = 0; it < P.bfgs_iters; it++) {
-        float pl = 0.f, gl = 0.f;
-        if (lane < D) {
-            float acc = 0.f;
-            for (int c = 0; c < D; c++) acc += S.H[lane * S.hs + c] * S.g[c];
-            pl = -acc;
-            gl = S.g[lane];
-            S.p[lane] = pl;
-        }
-        const float gp = wave_sum(pl * gl);
-        wave_sync();
-        float alpha = 1.f;
-        bool ok = false;
-        Energy Et;
-        for (int t = 0; t < P.ls_trials; t++) {
-            pose_step(L, x, alpha, S.p, S.trial);
-            Et = eval_pose(L, S, G, S.trial, S.gt, P.wall_slope);
-            evals++;
-            if (Et.total <= Ex.total + P.armijo_c1 * alpha * gp) {
-                ok = true;
-                break;
+        if (w == 0) {
+            float pl = 0.f, gl = 0.f;
+            if (lane < D) {
+                float acc = 0.f;
+#pragma unroll 4
+                for (int c = 0; c < D; c++) acc += C.H[lane * C.hs + c] * C.g[c];
+                pl = -acc;
+                gl = C.g[lane];
+                C.p[lane] = pl;
             }
-            alpha *= P.ls_shrink;
+            const float gp = wave_sum(pl * gl);
+            if (lane == 0) C.misc[kMiscGp] = gp;
         }
-        if (!ok) break;
-        float sl = 0.f, yl = 0.f;
-        if (lane < D) {
-            sl = alpha * pl;
-            yl = S.gt[lane] - gl;
-            S.s[lane] = sl;
-            S.y[lane] = yl;
-            S.g[lane] = S.gt[lane];
+        __syncthreads();
+        const float gp = C.misc[kMiscGp];
+        int acc_slot = -1;
+        float alpha_acc = 0.f;
+        float alpha0 = 1.f;   // alpha of the round's first trial
+        for (int t0 = 0; t0 < P.ls_trials; t0 += W) {
+            const int t = t0 + w;
+            if (t < P.ls_trials) {
+                float alpha = alpha0;
+                for (int q = 0; q < w; q++) alpha *= P.ls_shrink;
+                pose_step(L, x, alpha, C.p, S.trial);
+                put_energy(C.et + 4 * w, eval_pose(L, S, pr, G, S.trial, S.gt, P.wall_slope));
+            }
+            __syncthreads();
+            float a = alpha0;
+            int v = 0;
+            for (; v < W && t0 + v < P.ls_trials; v++) {
+                if (C.et[4 * v] <= Ex.total + P.armijo_c1 * a * gp) {
+                    acc_slot = v;
+                    alpha_acc = a;
+                    break;
+                }
+                a *= P.ls_shrink;
+            }
+            evals += acc_slot >= 0 ? acc_slot + 1 : v;
+            alpha0 = a;
+            if (acc_slot >= 0) break;
+            __syncthreads();   // this round's energies are read before the next round writes
         }
-        if (lane < L.nx) x[lane] = S.trial[lane];
+        if (acc_slot < 0) break;
+        const Energy Et = get_energy(C.et + 4 * acc_slot);
+        if (w == 0) {
+            const WaveL A = make_wave(wave_base + acc_slot * lay.wave_words, lay);
+            float sl = 0.f, yl = 0.f;
+            if (lane < D) {
+                const float gl = C.g[lane];
+                sl = alpha_acc * C.p[lane];
+                yl = A.gt[lane] - gl;
+                C.s[lane] = sl;
+                C.y[lane] = yl;
+                C.g[lane] = A.gt[lane];
+            }
+            if (lane < L.nx) x[lane] = A.trial[lane];
+            const float ys = wave_sum(sl * yl);
+            wave_sync();
+            if (ys > 0.f) {
+                const float rho = 1.f / ys;
+                float hy = 0.f;
+                if (lane < D) {
+#pragma unroll 4
+                    for (int c = 0; c < D; c++) hy += C.H[lane * C.hs + c] * C.y[c];
+                    C.Hy[lane] = hy;
+                }
+                const float yHy = wave_sum(yl * hy);
+                wave_sync();
+                if (lane < D) {
+                    const float a = rho * (1.f + rho * yHy) * sl, b = rho * sl, cc = rho * hy;
+#pragma unroll 4
+                    for (int c = 0; c < D; c++) {
+                        const float sc = C.s[c], hc = C.Hy[c];
+                        C.H[lane * C.hs + c] += a * sc - b * hc - cc * sc;
+                    }
+                }
+            }
+        }
         Ex = Et;
-        const float ys = wave_sum(sl * yl);
-        wave_sync();
-        if (ys > 0.f) {
-            const float rho = 1.f / ys;
-            float hy = 0.f;
-            if (lane < D) {
-                for (int c = 0; c < D; c++) hy += S.H[lane * S.hs + c] * S.y[c];
-                S.Hy[lane] = hy;
-            }
-            const float yHy = wave_sum(yl * hy);
-            wave_sync();
-            if (lane < D) {
-                for (int c = 0; c < D; c++)
-                    S.H[lane * S.hs + c] += rho * ((1.f + rho * yHy) * sl * S.s[c] - sl * S.Hy[c] - hy * S.s[c]);
-            }
-            wave_sync();
-        }
+        __syncthreads();
     }
     return Ex;
 }
 
-// Stage the ligand blob into LDS (whole workgroup) and return the chain region of this wave.
+// Stage the ligand blob into LDS (whole workgroup).
 __device__ inline void stage_blob(const uint32_t *blob, int words, uint32_t *lds)
 {
     for (int w = threadIdx.x; w < words; w += blockDim.x) lds[w] = blob[w];
@@ -595,6 +719,8 @@ __device__ inline void stage_blob(const uint32_t *blob, int words, uint32_t *lds
 
 // ---------------------------------------------------------------- kernels
 
+// One pose per wave (independent waves).
+template <int PPL>
 __global__ __launch_bounds__(256) void eval_kernel(const uint32_t *blob, int blob_words, GridView G, SearchParams P,
                                                    const float *poses, int n, float *energy, float *grad, float *xyz)
 {
@@ -602,21 +728,22 @@ __global__ __launch_bounds__(256) void eval_kernel(const uint32_t *blob, int blo
     uint32_t *lds = reinterpret_cast<uint32_t *>(lds4);
     stage_blob(blob, blob_words, lds);
     const LigL L = make_lig(lds);
-    const ChainLayout cl = chain_layout(L.na, L.nf, L.np, L.D, L.nx);
-    const ChainL S = make_chain(reinterpret_cast<float *>(lds) + blob_words + wave_id() * cl.words, cl);
+    const Layout lay = make_layout(L.na, L.nf, L.D, L.nx);
+    const WaveL S = make_wave(reinterpret_cast<float *>(lds) + blob_words + wave_id() * lay.wave_words, lay);
     const int idx = blockIdx.x * (blockDim.x >> 6) + wave_id();
     if (idx >= n) return;
     const int lane = lane_id();
-    if (lane < L.nx) S.cur[lane] = poses[(long)idx * L.nx + lane];
+    if (lane < L.nx) S.trial[lane] = poses[(long)idx * L.nx + lane];
     wave_sync();
-    const Energy E = eval_pose(L, S, G, S.cur, S.g, P.wall_slope);
+    const PairRegs<PPL> pr = load_pairs<PPL>(L);
+    const Energy E = eval_pose(L, S, pr, G, S.trial, S.gt, P.wall_slope);
     if (lane == 0) {
         energy[4 * idx + 0] = E.total;
         energy[4 * idx + 1] = E.inter;
         energy[4 * idx + 2] = E.intra;
         energy[4 * idx + 3] = E.wall;
     }
-    if (lane < L.D) grad[(long)idx * L.D + lane] = S.g[lane];
+    if (lane < L.D) grad[(long)idx * L.D + lane] = S.gt[lane];
     if (xyz && lane < L.na) {
         const float4 v = S.xyz[lane];
         float *o = xyz + ((long)idx * L.na + lane) * 3;
@@ -624,6 +751,8 @@ __global__ __launch_bounds__(256) void eval_kernel(const uint32_t *blob, int blo
     }
 }
 
+// One pose per workgroup of W waves.
+template <int PPL>
 __global__ __launch_bounds__(256) void local_opt_kernel(const uint32_t *blob, int blob_words, GridView G,
                                                         SearchParams P, const float *poses_in, int n,
                                                         float *poses_out, float *energy, int *evals_out)
@@ -632,28 +761,34 @@ __global__ __launch_bounds__(256) void local_opt_kernel(const uint32_t *blob, in
     uint32_t *lds = reinterpret_cast<uint32_t *>(lds4);
     stage_blob(blob, blob_words, lds);
     const LigL L = make_lig(lds);
-    const ChainLayout cl = chain_layout(L.na, L.nf, L.np, L.D, L.nx);
-    const ChainL S = make_chain(reinterpret_cast<float *>(lds) + blob_words + wave_id() * cl.words, cl);
-    const int idx = blockIdx.x * (blockDim.x >> 6) + wave_id();
-    if (idx >= n) return;
-    const int lane = lane_id();
-    if (lane < L.nx) S.cur[lane] = poses_in[(long)idx * L.nx + lane];
-    wave_sync();
+    const Layout lay = make_layout(L.na, L.nf, L.D, L.nx);
+    float *cbase = reinterpret_cast<float *>(lds) + blob_words;
+    const ChainL C = make_chain(cbase, lay);
+    float *wbase = cbase + lay.chain_words;
+    const int W = (int)(blockDim.x >> 6);
+    const int idx = blockIdx.x;
+    const int lane = lane_id(), w = wave_id();
+    if (w == 0 && lane < L.nx) C.cur[lane] = poses_in[(long)idx * L.nx + lane];
+    __syncthreads();
     int evals = 0;
-    const Energy E = local_opt(L, S, G, P, S.cur, evals);
-    if (lane < L.nx) poses_out[(long)idx * L.nx + lane] = S.cur[lane];
-    if (lane == 0) {
-        energy[4 * idx + 0] = E.total;
-        energy[4 * idx + 1] = E.inter;
-        energy[4 * idx + 2] = E.intra;
-        energy[4 * idx + 3] = E.wall;
-        if (evals_out) evals_out[idx] = evals;
+    const PairRegs<PPL> pr = load_pairs<PPL>(L);
+    const Energy E = local_opt_group(L, lay, wbase, C, pr, G, P, C.cur, evals, W);
+    if (w == 0) {
+        if (lane < L.nx) poses_out[(long)idx * L.nx + lane] = C.cur[lane];
+        if (lane == 0) {
+            energy[4 * idx + 0] = E.total;
+            energy[4 * idx + 1] = E.inter;
+            energy[4 * idx + 2] = E.intra;
+            energy[4 * idx + 3] = E.wall;
+            if (evals_out) evals_out[idx] = evals;
+        }
     }
 }
 
-// One Monte Carlo chain per wave: initial pose, then n_steps of mutate -> BFGS ->
-// Metropolis, keeping the lowest accepted energy.  Results go to `records`
-// (kRecWords per chain) and the best pose's coordinates to best_xyz.
+// One Monte Carlo chain per workgroup of W waves: initial pose, then n_steps of
+// mutate -> BFGS -> Metropolis, keeping the lowest accepted energy.  Results go
+// to `records` (kRecWords per chain) and the best pose's coordinates to best_xyz.
+template <int PPL>
 __global__ __launch_bounds__(256) void dock_kernel(const uint32_t *blob, int blob_words, GridView G, SearchParams P,
                                                    int n_chains, int n_steps, uint64_t seed, float *records,
                                                    float4 *best_xyz)
@@ -662,95 +797,105 @@ __global__ __launch_bounds__(256) void dock_kernel(const uint32_t *blob, int blo
     uint32_t *lds = reinterpret_cast<uint32_t *>(lds4);
     stage_blob(blob, blob_words, lds);
     const LigL L = make_lig(lds);
-    const ChainLayout cl = chain_layout(L.na, L.nf, L.np, L.D, L.nx);
-    const ChainL S = make_chain(reinterpret_cast<float *>(lds) + blob_words + wave_id() * cl.words, cl);
-    const int chain = blockIdx.x * (blockDim.x >> 6) + wave_id();
-    if (chain >= n_chains) return;
-    const int lane = lane_id();
+    const Layout lay = make_layout(L.na, L.nf, L.D, L.nx);
+    float *cbase = reinterpret_cast<float *>(lds) + blob_words;
+    const ChainL C = make_chain(cbase, lay);
+    float *wbase = cbase + lay.chain_words;
+    const int W = (int)(blockDim.x >> 6);
+    const int chain = blockIdx.x;
+    const PairRegs<PPL> pr = load_pairs<PPL>(L);
+    const int lane = lane_id(), w = wave_id();
     const uint32_t c = (uint32_t)chain;
 
     // initial pose: position uniform in the box, Shoemake orientation, uniform torsions
-    const int nw = 6 + L.nt;
-    if (lane < nw) {
-        const uint4 r = draw(seed, c, 0u, kTagInit, (uint32_t)(lane >> 2));
-        const uint32_t v = (lane & 3) == 0 ? r.x : ((lane & 3) == 1 ? r.y : ((lane & 3) == 2 ? r.z : r.w));
-        S.misc[lane] = unif(v);
+    if (w == 0) {
+        const int nw = 6 + L.nt;
+        if (lane < nw) {
+            const uint4 r = draw(seed, c, 0u, kTagInit, (uint32_t)(lane >> 2));
+            const uint32_t v = (lane & 3) == 0 ? r.x : ((lane & 3) == 1 ? r.y : ((lane & 3) == 2 ? r.z : r.w));
+            C.misc[lane] = unif(v);
+        }
+        wave_sync();
+        if (lane < 3) {
+            C.cur[lane] = G.origin[lane] + C.misc[lane] * ((float)(G.n[lane] - 1) * G.h);
+        } else if (lane < 7) {
+            const float u1 = C.misc[3], u2 = C.misc[4], u3 = C.misc[5];
+            const float s1 = sqrtf(1.f - u1), s2 = sqrtf(u1);
+            const float sa = __sinf(2 * kPi * u2), ca = __cosf(2 * kPi * u2);
+            const float sb = __sinf(2 * kPi * u3), cb = __cosf(2 * kPi * u3);
+            const float v = lane == 3 ? s2 * cb : (lane == 4 ? s1 * sa : (lane == 5 ? s1 * ca : s2 * sb));
+            C.cur[lane] = v;
+        } else if (lane < L.nx) {
+            C.cur[lane] = -kPi + 2 * kPi * C.misc[6 + lane - 7];
+        }
+        wave_sync();
+        copy_pose(L, C.cur, C.best);
     }
-    wave_sync();
-    if (lane < 3) {
-        S.cur[lane] = G.origin[lane] + S.misc[lane] * ((float)(G.n[lane] - 1) * G.h);
-    } else if (lane < 7) {
-        const float u1 = S.misc[3], u2 = S.misc[4], u3 = S.misc[5];
-        const float s1 = sqrtf(1.f - u1), s2 = sqrtf(u1);
-        float sa, ca, sb, cb;
-        sincosf(2 * kPi * u2, &sa, &ca);
-        sincosf(2 * kPi * u3, &sb, &cb);
-        const float v = lane == 3 ? s2 * cb : (lane == 4 ? s1 * sa : (lane == 5 ? s1 * ca : s2 * sb));
-        S.cur[lane] = v;
-    } else if (lane < L.nx) {
-        S.cur[lane] = -kPi + 2 * kPi * S.misc[6 + lane - 7];
-    }
-    wave_sync();
+    __syncthreads();
 
     Energy Ex;
     Ex.total = 0.f; Ex.inter = 0.f; Ex.intra = 0.f; Ex.wall = 0.f;
     Energy Eb;
     Eb.total = __int_as_float(0x7f800000); Eb.inter = Eb.intra = Eb.wall = 0.f;
-    if (lane < L.nx) S.best[lane] = S.cur[lane];
     int evals = 0, accepted = 0, lopts = 0;
     const float rot_amp = L.rg > 0.f ? P.trans_amp / L.rg : 0.f;
 
     for (int step = 0; step < n_steps; step++) {
-        copy_pose(L, S.cur, S.cand);
-        // mutation: one of 2 + n_tors moves, chosen in integer arithmetic
-        const uint4 r = draw(seed, c, (uint32_t)step, kTagMutate, 0u);
-        const int which = (int)(((uint64_t)r.x * (uint64_t)(2 + L.nt)) >> 32);
-        const float u1 = unif(r.y), u2 = unif(r.z), u3 = unif(r.w);
-        if (which == 0) {
-            const float3 v = ball(u1, u2, u3);
-            if (lane < 3) S.cand[lane] += P.trans_amp * (lane == 0 ? v.x : (lane == 1 ? v.y : v.z));
-        } else if (which == 1) {
-            const float3 v = ball(u1, u2, u3);
-            const float4 dq = quat_of_rotvec(rot_amp * v.x, rot_amp * v.y, rot_amp * v.z);
-            const float4 q = quat_normalize(quat_mul(dq, make_float4(S.cur[3], S.cur[4], S.cur[5], S.cur[6])));
-            if (lane >= 3 && lane < 7) S.cand[lane] = lane == 3 ? q.x : (lane == 4 ? q.y : (lane == 5 ? q.z : q.w));
-        } else {
-            if (lane == 7 + which - 2) S.cand[lane] = -kPi + 2 * kPi * u1;
+        if (w == 0) {
+            copy_pose(L, C.cur, C.cand);
+            // mutation: one of 2 + n_tors moves, chosen in integer arithmetic
+            const uint4 r = draw(seed, c, (uint32_t)step, kTagMutate, 0u);
+            const int which = (int)(((uint64_t)r.x * (uint64_t)(2 + L.nt)) >> 32);
+            const float u1 = unif(r.y), u2 = unif(r.z), u3 = unif(r.w);
+            if (which == 0) {
+                const float3 v = ball(u1, u2, u3);
+                if (lane < 3) C.cand[lane] += P.trans_amp * (lane == 0 ? v.x : (lane == 1 ? v.y : v.z));
+            } else if (which == 1) {
+                const float3 v = ball(u1, u2, u3);
+                const float4 dq = quat_of_rotvec(rot_amp * v.x, rot_amp * v.y, rot_amp * v.z);
+                const float4 q = quat_normalize(quat_mul(dq, make_float4(C.cur[3], C.cur[4], C.cur[5], C.cur[6])));
+                if (lane >= 3 && lane < 7) C.cand[lane] = lane == 3 ? q.x : (lane == 4 ? q.y : (lane == 5 ? q.z : q.w));
+            } else {
+                if (lane == 7 + which - 2) C.cand[lane] = -kPi + 2 * kPi * u1;
+            }
         }
-        wave_sync();
-        const Energy Ec = local_opt(L, S, G, P, S.cand, evals);
+        __syncthreads();
+        const Energy Ec = local_opt_group(L, lay, wbase, C, pr, G, P, C.cand, evals, W);
         lopts++;
         bool take = true;
         if (step > 0) {
             const float dE = Ec.total - Ex.total;
             const float u = unif(draw(seed, c, (uint32_t)step, kTagMetropolis, 0u).x);
-            take = (dE < 0.f) || (u < expf(-dE / P.temperature));
+            take = (dE < 0.f) || (u < __expf(-dE / P.temperature));
         }
         if (take) {
-            copy_pose(L, S.cand, S.cur);
+            if (w == 0) copy_pose(L, C.cand, C.cur);
             Ex = Ec;
             accepted++;
             if (Ex.total < Eb.total) {
-                copy_pose(L, S.cur, S.best);
+                if (w == 0) copy_pose(L, C.cur, C.best);
                 Eb = Ex;
             }
         }
     }
 
     // coordinates of the best pose (for RMSD clustering)
-    eval_pose(L, S, G, S.best, nullptr, P.wall_slope);
-    float *rec = records + (long)chain * kRecWords;
-    if (lane < L.nx) rec[kRecPose + lane] = S.best[lane];
-    if (lane == 0) {
-        rec[kRecE + 0] = Eb.total;
-        rec[kRecE + 1] = Eb.inter;
-        rec[kRecE + 2] = Eb.intra;
-        rec[kRecE + 3] = Eb.wall;
-        reinterpret_cast<int *>(rec)[kRecEvals] = evals;
-        reinterpret_cast<int *>(rec)[kRecAccepted] = accepted;
-        reinterpret_cast<int *>(rec)[kRecLocalOpts] = lopts;
+    if (w == 0) {
+        const WaveL S = make_wave(wbase, lay);
+        eval_pose(L, S, pr, G, C.best, nullptr, P.wall_slope);
+        float *rec = records + (long)chain * kRecWords;
+        if (lane < L.nx) rec[kRecPose + lane] = C.best[lane];
+        if (lane == 0) {
+            rec[kRecE + 0] = Eb.total;
+            rec[kRecE + 1] = Eb.inter;
+            rec[kRecE + 2] = Eb.intra;
+            rec[kRecE + 3] = Eb.wall;
+            reinterpret_cast<int *>(rec)[kRecEvals] = evals;
+            reinterpret_cast<int *>(rec)[kRecAccepted] = accepted;
+            reinterpret_cast<int *>(rec)[kRecLocalOpts] = lopts;
+        }
+        if (lane < L.na) best_xyz[(long)chain * L.na + lane] = S.xyz[lane];
     }
-    if (lane < L.na) best_xyz[(long)chain * L.na + lane] = S.xyz[lane];
 }
 
 // Ranking (post-processing): repeatedly take the lowest (energy, chain) candidate
@@ -814,20 +959,20 @@ __global__ __launch_bounds__(1024) void rank_kernel(const float *records, const 
     if (tid == 0) sel[0] = count;
 }
 
-inline int pick_waves(size_t blob_bytes, size_t chain_bytes)
+inline int pick_eval_waves(size_t blob_bytes, size_t wave_bytes)
 {
-    // up to 4 waves per workgroup while the LDS stays within 64 KB
+    // up to 4 independent waves per workgroup while the LDS stays within 64 KB
     int w = 4;
-    while (w > 1 && blob_bytes + w * chain_bytes > 65536) w--;
+    while (w > 1 && blob_bytes + w * wave_bytes > 65536) w--;
     return w;
 }
 
 }  // namespace
 
-size_t chain_lds_bytes(const LigHeader &h)
+size_t search_lds_bytes(const LigHeader &h, int waves)
 {
-    const ChainLayout c = chain_layout(h.n_atoms, h.n_frags, h.n_pairs, 6 + h.n_tors, 7 + h.n_tors);
-    return (size_t)c.words * 4;
+    const Layout c = make_layout(h.n_atoms, h.n_frags, 6 + h.n_tors, 7 + h.n_tors);
+    return (size_t)h.total_words * 4 + (size_t)c.chain_words * 4 + (size_t)waves * c.wave_words * 4;
 }
 
 hipError_t launch_eval(const uint32_t *blob, int blob_words, const LigHeader &h, const GridView &g,
@@ -835,36 +980,54 @@ hipError_t launch_eval(const uint32_t *blob, int blob_words, const LigHeader &h,
                        hipStream_t stream)
 {
     if (n <= 0) return hipSuccess;
-    const size_t cb = chain_lds_bytes(h), bb = (size_t)blob_words * 4;
-    const int w = pick_waves(bb, cb);
+    const Layout c = make_layout(h.n_atoms, h.n_frags, 6 + h.n_tors, 7 + h.n_tors);
+    const size_t wb = (size_t)c.wave_words * 4, bb = (size_t)blob_words * 4;
+    const int w = pick_eval_waves(bb, wb);
     const int blocks = (n + w - 1) / w;
-    eval_kernel<<<blocks, 64 * w, bb + w * cb, stream>>>(blob, blob_words, g, p, poses, n, energy, grad, xyz);
+    const size_t lds = bb + w * wb;
+    if (h.n_pairs <= 512)
+        eval_kernel<8><<<blocks, 64 * w, lds, stream>>>(blob, blob_words, g, p, poses, n, energy, grad, xyz);
+    else if (h.n_pairs <= 1024)
+        eval_kernel<16><<<blocks, 64 * w, lds, stream>>>(blob, blob_words, g, p, poses, n, energy, grad, xyz);
+    else
+        eval_kernel<32><<<blocks, 64 * w, lds, stream>>>(blob, blob_words, g, p, poses, n, energy, grad, xyz);
     return hipGetLastError();
 }
 
 hipError_t launch_local_opt(const uint32_t *blob, int blob_words, const LigHeader &h, const GridView &g,
-                            const SearchParams &p, const float *poses_in, int n, float *poses_out, float *energy,
-                            int *evals, hipStream_t stream)
+                            const SearchParams &p, int waves, const float *poses_in, int n, float *poses_out,
+                            float *energy, int *evals, hipStream_t stream)
 {
     if (n <= 0) return hipSuccess;
-    const size_t cb = chain_lds_bytes(h), bb = (size_t)blob_words * 4;
-    const int w = pick_waves(bb, cb);
-    const int blocks = (n + w - 1) / w;
-    local_opt_kernel<<<blocks, 64 * w, bb + w * cb, stream>>>(blob, blob_words, g, p, poses_in, n, poses_out, energy,
-                                                               evals);
+    if (waves < 1 || waves > kMaxWaves) return hipErrorInvalidValue;
+    const size_t lds = search_lds_bytes(h, waves);
+    if (h.n_pairs <= 512)
+        local_opt_kernel<8><<<n, 64 * waves, lds, stream>>>(blob, blob_words, g, p, poses_in, n, poses_out, energy, evals);
+    else if (h.n_pairs <= 1024)
+        local_opt_kernel<16><<<n, 64 * waves, lds, stream>>>(blob, blob_words, g, p, poses_in, n, poses_out, energy,
+                                                             evals);
+    else
+        local_opt_kernel<32><<<n, 64 * waves, lds, stream>>>(blob, blob_words, g, p, poses_in, n, poses_out, energy,
+                                                             evals);
     return hipGetLastError();
 }
 
 hipError_t launch_dock(const uint32_t *blob, int blob_words, const LigHeader &h, const GridView &g,
-                       const SearchParams &p, int n_chains, int n_steps, uint64_t seed, float *records,
+                       const SearchParams &p, int waves, int n_chains, int n_steps, uint64_t seed, float *records,
                        float4 *best_xyz, hipStream_t stream)
 {
     if (n_chains <= 0) return hipSuccess;
-    const size_t cb = chain_lds_bytes(h), bb = (size_t)blob_words * 4;
-    const int w = 1;
-    const int blocks = (n_chains + w - 1) / w;
-    dock_kernel<<<blocks, 64 * w, bb + w * cb, stream>>>(blob, blob_words, g, p, n_chains, n_steps, seed, records,
-                                                          best_xyz);
+    if (waves < 1 || waves > kMaxWaves) return hipErrorInvalidValue;
+    const size_t lds = search_lds_bytes(h, waves);
+    if (h.n_pairs <= 512)
+        dock_kernel<8><<<n_chains, 64 * waves, lds, stream>>>(blob, blob_words, g, p, n_chains, n_steps, seed, records,
+                                                              best_xyz);
+    else if (h.n_pairs <= 1024)
+        dock_kernel<16><<<n_chains, 64 * waves, lds, stream>>>(blob, blob_words, g, p, n_chains, n_steps, seed, records,
+                                                               best_xyz);
+    else
+        dock_kernel<32><<<n_chains, 64 * waves, lds, stream>>>(blob, blob_words, g, p, n_chains, n_steps, seed, records,
+                                                               best_xyz);
     return hipGetLastError();
 }
 

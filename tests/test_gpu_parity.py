@@ -213,8 +213,11 @@ def test_local_opt_endpoint_spread_default(cfg1):
 
 
 def test_dock_deterministic_and_chain_independent(cfg1):
+    """A chain's result is bitwise the same across runs, chain counts and the
+    number of waves per chain (concurrent line-search trials)."""
     cfg, ref, g = cfg1
     gc = _gc()
+    import paper_2303_09916_amd as D
     lig = cfg["ligands"][0]
     a = gc.gpu_dock(g, lig, 32, 20, 3, 5)
     b = gc.gpu_dock(g, lig, 32, 20, 3, 5)
@@ -223,6 +226,11 @@ def test_dock_deterministic_and_chain_independent(cfg1):
         assert bytes(a[2][k]) == bytes(b[2][k])
         assert bytes(a[2][k]) == bytes(c[2][k])
     assert [bytes(p) for p in a[0]] == [bytes(p) for p in b[0]]
+    for w in (1, 2, 3, 4):
+        d = gc.gpu_dock(g, lig, 32, 20, 3, 5, D.dsdp_params_default(waves_per_chain=w))
+        for k in range(32):
+            assert bytes(a[2][k]) == bytes(d[2][k]), (w, k)
+        assert d[3].pose_evals == a[3].pose_evals
 
 
 def test_dock_topk_properties(cfg1):
