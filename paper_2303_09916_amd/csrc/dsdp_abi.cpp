@@ -250,6 +250,30 @@ dsdp_status prepare_ligand(const dsdp_ligand *lig, const int *map_of_type, Prepa
     h.off_frag_start = take(nf + 1, 1);
     h.off_pair = take(np, 1);
     h.off_pair_rsum = take(np, 1);
+    // per-atom pair lists for the force gather: lane l serves atom l % 32 (half
+    // l / 32) when there are at most 32 atoms, else atom l; entries are pair
+    // indices with a sign bit (set when the atom is the pair's second atom), padded
+    // with the zero slot n_pairs
+    const int lpa = na <= 32 ? 2 : 1;
+    std::vector<std::vector<uint16_t>> lane_list(64);
+    {
+        std::vector<std::vector<uint16_t>> atom_list(na);
+        for (int p = 0; p < np; p++) {
+            const int i = pairs[p] & 255u, j = (pairs[p] >> 8) & 255u;
+            atom_list[i].push_back((uint16_t)p);
+            atom_list[j].push_back((uint16_t)(p | 0x8000));
+        }
+        for (int l = 0; l < 64; l++) {
+            const int a = lpa == 2 ? (l & 31) : l, half = lpa == 2 ? (l >> 5) : 0;
+            if (a >= na) continue;
+            for (size_t e = half; e < atom_list[a].size(); e += lpa) lane_list[l].push_back(atom_list[a][e]);
+        }
+    }
+    size_t maxlen = 0;
+    for (const auto &v : lane_list) maxlen = std::max(maxlen, v.size());
+    h.n_chunks = (int)((maxlen + 7) / 8);
+    h.lanes_per_atom = lpa;
+    h.off_plist = take(h.n_chunks * 64 * 4, 4);
     h.total_words = (w + 3) / 4 * 4;
 
     std::vector<uint32_t> blob((size_t)h.total_words, 0u);
@@ -271,7 +295,7 @@ dsdp_status prepare_ligand(const dsdp_ligand *lig, const int *map_of_type, Prepa
         if (k == 0) {
             for (int a = 0; a < 3; a++) fput(h.off_frag_u + a, 0.f);
             for (int a = 0; a < 3; a++) fput(h.off_frag_off + a, 0.f);
-            blob[(size_t)h.off_frag_u + 3] = (uint32_t)-1;
+            blob[(size_t)h.off_frag_u + 3] = 0u;   // no parent, depth 0
         } else {
             const int ia = lig->axis[2 * k], ib = lig->axis[2 * k + 1];
             double u[3], nrm = 0, op[3];
@@ -285,7 +309,7 @@ dsdp_status prepare_ligand(const dsdp_ligand *lig, const int *map_of_type, Prepa
                 fput(h.off_frag_u + 4 * k + a, (float)(u[a] / nrm));
                 fput(h.off_frag_off + 4 * k + a, (float)(ref[3 * ib + a] - op[a]));
             }
-            blob[(size_t)h.off_frag_u + 4 * k + 3] = (uint32_t)lig->frag_parent[k];
+            blob[(size_t)h.off_frag_u + 4 * k + 3] = (uint32_t)(lig->frag_parent[k] + 1) | ((uint32_t)depth[k] << 16);
         }
         blob[(size_t)h.off_frag_off + 4 * k + 3] = sub[k];
     }
@@ -294,6 +318,14 @@ dsdp_status prepare_ligand(const dsdp_ligand *lig, const int *map_of_type, Prepa
         blob[(size_t)h.off_pair + p] = pairs[p];
         fput(h.off_pair_rsum + p, rsum[p]);
     }
+    for (int c = 0; c < h.n_chunks; c++)
+        for (int l = 0; l < 64; l++)
+            for (int q = 0; q < 8; q++) {
+                const size_t e = (size_t)c * 8 + q;
+                const uint32_t v = e < lane_list[l].size() ? lane_list[l][e] : (uint32_t)np;
+                uint32_t &word = blob[(size_t)h.off_plist + ((size_t)c * 64 + l) * 4 + q / 2];
+                word |= (q & 1) ? (v << 16) : v;
+            }
     out.h = h;
     out.blob.swap(blob);
     return DSDP_OK;
@@ -368,18 +400,37 @@ int device_cus()
     return cus;
 }
 
-// Waves per chain: the caller's choice, else enough to put about one wave on
-// each SIMD (four per compute unit) when chains are few; every choice gives the
-// same results.  Reduced until the workgroup's LDS fits in 64 KB.
+// LDS bytes a workgroup may use on the current device.
+size_t device_max_lds()
+{
+    static thread_local int dev_cached = -1;
+    static thread_local size_t bytes = 65536;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 65536;
+    if (dev != dev_cached) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+            v = 65536;
+        bytes = (size_t)v;
+        dev_cached = dev;
+    }
+    return bytes;
+}
+
+// Waves per chain: the caller's choice, else about 8 waves per compute unit
+// (measured on MI355X with a 32-atom ligand: 4 waves per chain at 384 chains,
+// 2 at 1024, 1 at 4096 chains); every choice gives the same results.  Reduced
+// until the workgroup's LDS fits the device's limit.
 dsdp_status pick_waves(const dsdp_params *prm, const LigHeader &h, int n_chains, int &waves)
 {
     int w = (prm && prm->waves_per_chain > 0) ? prm->waves_per_chain : 0;
     if (w == 0) {
-        const long simds = 4L * device_cus();
-        w = (int)std::max(1L, std::min(4L, simds / std::max(1, n_chains)));
+        const long slots = 8L * device_cus();
+        w = (int)std::max(1L, std::min(4L, slots / std::max(1, n_chains)));
     }
-    while (w > 1 && search_lds_bytes(h, w) > 65536) w--;
-    if (search_lds_bytes(h, w) > 65536)
+    const size_t cap = device_max_lds();
+    while (w > 1 && search_lds_bytes(h, w) > cap) w--;
+    if (search_lds_bytes(h, w) > cap)
         return fail(DSDP_ERR_UNSUPPORTED, "ligand needs %zu bytes of LDS per chain", search_lds_bytes(h, 1));
     waves = w;
     return DSDP_OK;

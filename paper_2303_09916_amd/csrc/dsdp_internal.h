@@ -65,12 +65,15 @@ struct LigHeader {
     int32_t max_depth;
     float rg;                // gyration radius about the root centre (rotation amplitude scale)
     int32_t off_atom;        // float4[n_atoms]: local offset xyz from the fragment origin, w = map index bits
-    int32_t off_frag_u;      // float4[n_frags]: unit torsion axis in the parent frame, w = parent bits
+    int32_t off_frag_u;      // float4[n_frags]: unit torsion axis, w = (parent + 1) | depth << 16
     int32_t off_frag_off;    // float4[n_frags]: fragment origin in the parent frame, w = subtree mask bits
     int32_t off_atom_frag;   // int[n_atoms]
     int32_t off_frag_start;  // int[n_frags + 1]
     int32_t off_pair;        // uint32[n_pairs]: i | j << 8 | flags << 16
     int32_t off_pair_rsum;   // float[n_pairs]: R_i + R_j
+    int32_t off_plist;       // uint4[n_chunks][64]: per gather lane, 8 u16 entries (pair | sign << 15) per chunk
+    int32_t n_chunks;        // chunks of 8 entries per gather lane
+    int32_t lanes_per_atom;  // 2 when n_atoms <= 32 (lanes a and a + 32 split atom a's list), else 1
     int32_t total_words;     // multiple of 4
 };
 constexpr int kHeaderWords = (int)(sizeof(LigHeader) / 4 + 3) / 4 * 4;

@@ -30,14 +30,14 @@ struct BuildArgs {
     float clo[3];
     float cell;
     GridView g;
-    float2 tparam[kNXS * kNXS];   // [map t][receptor type]: (R_t + R_a, flag bits)
+    float4 tparam[kNXS * kNXS];   // [map t][receptor type]: (R_t + R_a, hydrophobic w, h-bond w, 0)
     float4 *maps;
 };
 
-// Vina pair energy on the surface distance d and its derivative in d (returned as
-// (e, de)).  Piecewise terms in branch-free form; at a kink the left-hand slope
-// is taken.
-__device__ __forceinline__ float2 vina_pair(float d, uint32_t flags)
+// Vina pair energy on the surface distance d and its derivative in d, returned
+// as (e, de); wh and wb are the pair's hydrophobic and hydrogen-bond weights
+// (0 when the pair is not of that class).  At a kink the left-hand slope is taken.
+__device__ __forceinline__ float2 vina_pair(float d, float wh, float wb)
 {
     const float g1 = __expf(-4.0f * d * d);
     const float b = d - 3.0f;
@@ -45,14 +45,8 @@ __device__ __forceinline__ float2 vina_pair(float d, uint32_t flags)
     const float dn = fminf(d, 0.0f);
     float e = kWGauss1 * g1 + kWGauss2 * g2 + kWRepulsion * dn * dn;
     float de = kWGauss1 * g1 * (-8.0f * d) + kWGauss2 * g2 * (-0.5f * b) + kWRepulsion * 2.0f * dn;
-    if (flags & kPairHydrophobic) {
-        e += kWHydrophobic * fminf(fmaxf(1.5f - d, 0.0f), 1.0f);
-        de += (d > 0.5f && d <= 1.5f) ? -kWHydrophobic : 0.0f;
-    }
-    if (flags & kPairHBond) {
-        e += kWHBond * fminf(fmaxf(-d * (1.0f / 0.7f), 0.0f), 1.0f);
-        de += (d > -0.7f && d <= 0.0f) ? -kWHBond * (1.0f / 0.7f) : 0.0f;
-    }
+    e += wh * fminf(fmaxf(1.5f - d, 0.0f), 1.0f) + wb * fminf(fmaxf(-d * (1.0f / 0.7f), 0.0f), 1.0f);
+    de += ((d > 0.5f && d <= 1.5f) ? -wh : 0.0f) + ((d > -0.7f && d <= 0.0f) ? -wb * (1.0f / 0.7f) : 0.0f);
     return make_float2(e, de);
 }
 
@@ -60,7 +54,7 @@ template <int TMAX>
 __global__ __launch_bounds__(kThreads) void grid_build_kernel(const BuildArgs a)
 {
     __shared__ float4 s_atoms[kStageCap];
-    __shared__ float2 s_tp[TMAX * kNXS];
+    __shared__ float4 s_tp[TMAX * kNXS];
     __shared__ int s_row_begin[kMaxRows], s_row_end[kMaxRows], s_row_pre[kMaxRows + 1];
     __shared__ int s_nrows, s_total;
 
@@ -74,7 +68,7 @@ __global__ __launch_bounds__(kThreads) void grid_build_kernel(const BuildArgs a)
     const float my = g.origin[1] + g.h * (float)j;
     const float mz = g.origin[2] + g.h * (float)k;
 
-    for (int q = tid; q < TMAX * kNXS; q += kThreads) s_tp[q] = (q < T * kNXS) ? a.tparam[q] : make_float2(0.f, 0.f);
+    for (int q = tid; q < TMAX * kNXS; q += kThreads) s_tp[q] = (q < T * kNXS) ? a.tparam[q] : make_float4(0.f, 0.f, 0.f, 0.f);
 
     // cell rows covering the tile expanded by the cutoff
     if (tid == 0) {
@@ -132,8 +126,8 @@ __global__ __launch_bounds__(kThreads) void grid_build_kernel(const BuildArgs a)
 #pragma unroll
                 for (int t = 0; t < TMAX; t++) {
                     if (t < T) {
-                        const float2 tp = s_tp[t * kNXS + ta];
-                        const float2 ed = vina_pair(r - tp.x, __float_as_uint(tp.y));
+                        const float4 tp = s_tp[t * kNXS + ta];
+                        const float2 ed = vina_pair(r - tp.x, tp.y, tp.z);
                         const float gs = ed.y * inv_r;
                         E[t] += ed.x;
                         Gx[t] += gs * dx;
@@ -174,11 +168,11 @@ hipError_t launch_grid_build(const float4 *atoms, const int *cell_start, const i
             if (t < g.T) {
                 const int mt = map_types_host[t];
                 const uint32_t fl = pair_flags(mt, r);
-                float flf;
-                memcpy(&flf, &fl, 4);
-                a.tparam[t * kNXS + r] = make_float2(xs_radius(mt) + xs_radius(r), flf);
+                a.tparam[t * kNXS + r] = make_float4(xs_radius(mt) + xs_radius(r),
+                                                     (fl & kPairHydrophobic) ? kWHydrophobic : 0.f,
+                                                     (fl & kPairHBond) ? kWHBond : 0.f, 0.f);
             } else {
-                a.tparam[t * kNXS + r] = make_float2(0.f, 0.f);
+                a.tparam[t * kNXS + r] = make_float4(0.f, 0.f, 0.f, 0.f);
             }
         }
     a.maps = maps;

@@ -172,10 +172,11 @@ __device__ __forceinline__ float3 ball(float u1, float u2, float u3)
     return make_float3(r * q * c, r * q * s, r * z);
 }
 
-// Vina pair energy on the surface distance d and its derivative in d (returned as
-// (e, de)).  Piecewise terms in branch-free form; at a kink the left-hand slope
-// is taken.
-__device__ __forceinline__ float2 vina_pair(float d, uint32_t flags)
+// Vina pair energy on the surface distance d and its derivative in d, returned
+// as (e, de).  wh and wb are the pair's hydrophobic and hydrogen-bond weights
+// (0 when the pair is not of that class).  Piecewise terms in branch-free form;
+// at a kink the left-hand slope is taken.
+__device__ __forceinline__ float2 vina_pair(float d, float wh, float wb)
 {
     const float g1 = __expf(-4.0f * d * d);
     const float b = d - 3.0f;
@@ -183,35 +184,34 @@ __device__ __forceinline__ float2 vina_pair(float d, uint32_t flags)
     const float dn = fminf(d, 0.0f);
     float e = kWGauss1 * g1 + kWGauss2 * g2 + kWRepulsion * dn * dn;
     float de = kWGauss1 * g1 * (-8.0f * d) + kWGauss2 * g2 * (-0.5f * b) + kWRepulsion * 2.0f * dn;
-    if (flags & kPairHydrophobic) {
-        e += kWHydrophobic * fminf(fmaxf(1.5f - d, 0.0f), 1.0f);
-        de += (d > 0.5f && d <= 1.5f) ? -kWHydrophobic : 0.0f;
-    }
-    if (flags & kPairHBond) {
-        e += kWHBond * fminf(fmaxf(-d * (1.0f / 0.7f), 0.0f), 1.0f);
-        de += (d > -0.7f && d <= 0.0f) ? -kWHBond * (1.0f / 0.7f) : 0.0f;
-    }
+    e += wh * fminf(fmaxf(1.5f - d, 0.0f), 1.0f) + wb * fminf(fmaxf(-d * (1.0f / 0.7f), 0.0f), 1.0f);
+    de += ((d > 0.5f && d <= 1.5f) ? -wh : 0.0f) + ((d > -0.7f && d <= 0.0f) ? -wb * (1.0f / 0.7f) : 0.0f);
     return make_float2(e, de);
 }
+__device__ __forceinline__ float pair_wh(uint32_t flags) { return (flags & kPairHydrophobic) ? kWHydrophobic : 0.0f; }
+__device__ __forceinline__ float pair_wb(uint32_t flags) { return (flags & kPairHBond) ? kWHBond : 0.0f; }
 
 // ---------------------------------------------------------------- LDS layout
 struct LigL {
-    int na, nf, nt, np, D, nx;
+    int na, nf, nt, np, D, nx, maxdepth;
     float rg;
     const float4 *atom;      // local offset, w = map index
-    const float4 *fu;        // torsion axis in parent frame, w = parent
+    const float4 *fu;        // torsion axis in parent frame, w = (parent + 1) | depth << 16
     const float4 *foff;      // origin in parent frame, w = subtree mask
     const int *atom_frag;
     const int *frag_start;
     const uint32_t *pair;
     const float *rsum;
+    const uint4 *plist;      // [n_chunks][64] gather lists
+    int n_chunks, lanes_per_atom;
 };
 
 // Scratch of one pose evaluation (one per wave).
 struct WaveL {
     float4 *xyz;
-    float *fx, *fy, *fz;   // [na4] per-atom pair-force accumulators (planes, one bank per atom)
-    float *ft;             // [6][nf4] per-fragment force and torque accumulators (planes)
+    float4 *pf;            // [np + 1] force of each pair on its first atom; slot np stays 0
+    float4 *af, *at;       // [na] total force and torque (about the fragment origin) per atom
+    float *ft;             // [6][nf4] per-fragment force and torque (planes)
     int nf4;
     float4 *R;       // [nf][4]: rows of R_k, then origin o_k
     float4 *Q;       // [nf][3]: rotation of fragment k relative to its parent (root: R(q))
@@ -235,18 +235,19 @@ constexpr int kMiscGp = 40;      // slot of g.p in misc
 __host__ __device__ inline int rup4(int v) { return (v + 3) & ~3; }
 
 struct Layout {
-    int xyz, frc, na4, R, Q, FT, nf4, trial, gt, wave_words;  // per-wave offsets
+    int xyz, pf, af, at, R, Q, FT, nf4, trial, gt, wave_words;  // per-wave offsets
     int vec, H, hs, pose, et, misc, chain_words, Dp, NXp;     // per-chain offsets
 };
-__host__ __device__ inline Layout make_layout(int na, int nf, int D, int nx)
+__host__ __device__ inline Layout make_layout(int na, int nf, int np, int D, int nx)
 {
     Layout c;
     c.Dp = rup4(D);
     c.NXp = rup4(nx);
     int w = 0;
     c.xyz = w; w += 4 * na;
-    c.na4 = rup4(na);
-    c.frc = w; w += 3 * c.na4;
+    c.pf = w; w += 4 * (np + 1);
+    c.af = w; w += 4 * na;
+    c.at = w; w += 4 * na;
     c.R = w; w += 16 * nf;
     c.Q = w; w += 12 * nf;
     c.nf4 = rup4(nf);
@@ -269,9 +270,9 @@ __device__ inline WaveL make_wave(float *base, const Layout &c)
 {
     WaveL S;
     S.xyz = reinterpret_cast<float4 *>(base + c.xyz);
-    S.fx = base + c.frc;
-    S.fy = S.fx + c.na4;
-    S.fz = S.fy + c.na4;
+    S.pf = reinterpret_cast<float4 *>(base + c.pf);
+    S.af = reinterpret_cast<float4 *>(base + c.af);
+    S.at = reinterpret_cast<float4 *>(base + c.at);
     S.R = reinterpret_cast<float4 *>(base + c.R);
     S.Q = reinterpret_cast<float4 *>(base + c.Q);
     S.ft = base + c.FT;
@@ -301,6 +302,7 @@ __device__ inline LigL make_lig(const uint32_t *blob)
     LigL L;
     L.na = h->n_atoms; L.nf = h->n_frags; L.nt = h->n_tors; L.np = h->n_pairs;
     L.D = 6 + L.nt; L.nx = 7 + L.nt;
+    L.maxdepth = h->max_depth;
     L.rg = h->rg;
     L.atom = reinterpret_cast<const float4 *>(blob + h->off_atom);
     L.fu = reinterpret_cast<const float4 *>(blob + h->off_frag_u);
@@ -309,6 +311,9 @@ __device__ inline LigL make_lig(const uint32_t *blob)
     L.frag_start = reinterpret_cast<const int *>(blob + h->off_frag_start);
     L.pair = blob + h->off_pair;
     L.rsum = reinterpret_cast<const float *>(blob + h->off_pair_rsum);
+    L.plist = reinterpret_cast<const uint4 *>(blob + h->off_plist);
+    L.n_chunks = h->n_chunks;
+    L.lanes_per_atom = h->lanes_per_atom;
     return L;
 }
 
@@ -362,8 +367,6 @@ __device__ Energy eval_pose(const LigL &L, const WaveL &S, const PairRegs<PPL> &
         S.Q[3 * lane + 0] = make_float4(Q.a[0], Q.a[1], Q.a[2], 0.f);
         S.Q[3 * lane + 1] = make_float4(Q.a[3], Q.a[4], Q.a[5], 0.f);
         S.Q[3 * lane + 2] = make_float4(Q.a[6], Q.a[7], Q.a[8], 0.f);
-#pragma unroll
-        for (int q = 0; q < 6; q++) S.ft[q * S.nf4 + lane] = 0.f;
     }
     wave_sync();
 
@@ -376,12 +379,12 @@ __device__ Energy eval_pose(const LigL &L, const WaveL &S, const PairRegs<PPL> &
         if (lane > 0) {
             M3 M = load_m3(S.Q + 3 * lane);
             float3 v = f3(L.foff[lane]);
-            int m = __float_as_int(L.fu[lane].w);
+            int m = (int)(__float_as_uint(L.fu[lane].w) & 0xffffu) - 1;
             while (m > 0) {
                 const M3 Qm = load_m3(S.Q + 3 * m);
                 v = f3(L.foff[m]) + mv(Qm, v);
                 M = mul(Qm, M);
-                m = __float_as_int(L.fu[m].w);
+                m = (int)(__float_as_uint(L.fu[m].w) & 0xffffu) - 1;
             }
             R = mul(R0, M);
             o = o + mv(R0, v);
@@ -409,9 +412,6 @@ __device__ Energy eval_pose(const LigL &L, const WaveL &S, const PairRegs<PPL> &
                         o.y + r1.x * loc.x + r1.y * loc.y + r1.z * loc.z,
                         o.z + r2.x * loc.x + r2.y * loc.y + r2.z * loc.z);
         S.xyz[lane] = make_float4(x.x, x.y, x.z, 0.f);
-        S.fx[lane] = 0.f;
-        S.fy[lane] = 0.f;
-        S.fz[lane] = 0.f;
 
         // wall and clamping: a coordinate outside the box is clamped onto the face;
         // the atom pays wall_slope per Angstrom outside and the map gradient along
@@ -460,26 +460,24 @@ __device__ Energy eval_pose(const LigL &L, const WaveL &S, const PairRegs<PPL> &
     // (4) intra-ligand pairs, PPL per lane held in registers (pair lane + 64 k);
     //     forces accumulate per atom in LDS
     float e_pair = 0.f;
+    const int slots = (L.np + 63) >> 6;
 #pragma unroll
     for (int k = 0; k < PPL; k++) {
+        if (k < slots) {
         const uint32_t pw = pr.w[k];
         const int i = (int)(pw & 255u), j = (int)((pw >> 8) & 255u);
         const float4 xi = S.xyz[i], xj = S.xyz[j];
         const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
         const float r2 = dx * dx + dy * dy + dz * dz;
+        float sp = 0.f;
         if (!(pw & kPairNone) && r2 < kCutoff2) {
             const float inv_r = r2 > 1e-18f ? rsqrtf(r2) : 0.f;
-            const float2 ed = vina_pair(r2 * inv_r - pr.rs[k], pw >> 16);
+            const uint32_t fl = pw >> 16;
+            const float2 ed = vina_pair(r2 * inv_r - pr.rs[k], pair_wh(fl), pair_wb(fl));
             e_pair += ed.x;
-            if (grad != nullptr) {
-                const float sp = ed.y * inv_r;
-                atomicAdd(S.fx + i, sp * dx);
-                atomicAdd(S.fy + i, sp * dy);
-                atomicAdd(S.fz + i, sp * dz);
-                atomicAdd(S.fx + j, -sp * dx);
-                atomicAdd(S.fy + j, -sp * dy);
-                atomicAdd(S.fz + j, -sp * dz);
-            }
+            sp = ed.y * inv_r;
+        }
+        if (grad != nullptr && !(pw & kPairNone)) S.pf[lane + 64 * k] = make_float4(sp * dx, sp * dy, sp * dz, 0.f);
         }
     }
 
@@ -516,47 +514,96 @@ __device__ Energy eval_pose(const LigL &L, const WaveL &S, const PairRegs<PPL> &
     if (grad == nullptr) return out;
     wave_sync();
 
-    // (6) total atom force; force and torque (about the fragment origin) summed per fragment
-    if (lane < L.na) {
-        f = f + make_float3(S.fx[lane], S.fy[lane], S.fz[lane]);
-        const float3 o = f3(S.R[4 * frag + 3]);
-        const float3 tq = cross3(x - o, f);
-        float *ft = S.ft + frag;
-        atomicAdd(ft, f.x);
-        atomicAdd(ft + S.nf4, f.y);
-        atomicAdd(ft + 2 * S.nf4, f.z);
-        atomicAdd(ft + 3 * S.nf4, tq.x);
-        atomicAdd(ft + 4 * S.nf4, tq.y);
-        atomicAdd(ft + 5 * S.nf4, tq.z);
+    // (6) pair forces gathered per atom from its list (8 entries per 16-byte chunk;
+    //     two lanes per atom when there are at most 32 atoms), then the atom's total
+    //     force and its torque about the fragment origin; per-fragment sums over
+    //     the fragment's contiguous atom range
+    {
+        float3 fp = make_float3(0.f, 0.f, 0.f);
+        for (int c = 0; c < L.n_chunks; c++) {
+            const uint4 q = L.plist[c * 64 + lane];
+            const uint32_t e[8] = {q.x & 0xffffu, q.x >> 16, q.y & 0xffffu, q.y >> 16,
+                                   q.z & 0xffffu, q.z >> 16, q.w & 0xffffu, q.w >> 16};
+            float4 v[8];
+#pragma unroll
+            for (int t = 0; t < 8; t++) v[t] = S.pf[e[t] & 0x7fffu];
+#pragma unroll
+            for (int t = 0; t < 8; t++) {
+                const float sg = (e[t] & 0x8000u) ? -1.f : 1.f;
+                fp = fp + sg * f3(v[t]);
+            }
+        }
+        if (L.lanes_per_atom == 2) {
+            fp.x += __shfl_xor(fp.x, 32, 64);
+            fp.y += __shfl_xor(fp.y, 32, 64);
+            fp.z += __shfl_xor(fp.z, 32, 64);
+        }
+        if (lane < L.na) {
+            f = f + fp;
+            const float3 o = f3(S.R[4 * frag + 3]);
+            const float3 tq = cross3(x - o, f);
+            S.af[lane] = make_float4(f.x, f.y, f.z, 0.f);
+            S.at[lane] = make_float4(tq.x, tq.y, tq.z, 0.f);
+        }
+    }
+    wave_sync();
+    if (lane < L.nf) {
+        float3 F = make_float3(0.f, 0.f, 0.f), Tq = make_float3(0.f, 0.f, 0.f);
+        const int a0 = L.frag_start[lane], a1 = L.frag_start[lane + 1];
+        for (int a = a0; a < a1; a++) {
+            F = F + f3(S.af[a]);
+            Tq = Tq + f3(S.at[a]);
+        }
+        S.ft[lane] = F.x;
+        S.ft[S.nf4 + lane] = F.y;
+        S.ft[2 * S.nf4 + lane] = F.z;
+        S.ft[3 * S.nf4 + lane] = Tq.x;
+        S.ft[4 * S.nf4 + lane] = Tq.y;
+        S.ft[5 * S.nf4 + lane] = Tq.z;
     }
     wave_sync();
 
-    // (7) subtree sums: F_sub(k) = sum F_m, tau_sub(k) = sum T_m + (o_m - o_k) x F_m
-    //     over fragments m in k's subtree; dE/dtheta_k = u_k . tau_sub(k)
+    // (7) subtree sums, deepest level first: each fragment adds its force and its
+    //     torque moved to the parent's origin, tau + (o_k - o_parent) x F, into
+    //     its parent; afterwards fragment k holds F_sub(k) and tau_sub(k) about o_k.
+    //     dE/dp = F_sub(0), dE/dw = tau_sub(0) (o_0 = p), dE/dtheta_k = u_k . tau_sub(k)
     {
-        const uint32_t mask = lane < L.nf ? __float_as_uint(L.foff[lane].w) : 0u;
-        const float3 ok = lane < L.nf ? f3(S.R[4 * lane + 3]) : make_float3(0.f, 0.f, 0.f);
-        float3 F = make_float3(0.f, 0.f, 0.f), Tq = make_float3(0.f, 0.f, 0.f);
-#pragma unroll 4
-        for (int m = 0; m < L.nf; m++) {
-            const float3 Fm = make_float3(S.ft[m], S.ft[S.nf4 + m], S.ft[2 * S.nf4 + m]);
-            const float3 Tm = make_float3(S.ft[3 * S.nf4 + m], S.ft[4 * S.nf4 + m], S.ft[5 * S.nf4 + m]);
-            const float3 om = f3(S.R[4 * m + 3]);
-            if ((mask >> m) & 1u) {
-                F = F + Fm;
-                Tq = Tq + Tm + cross3(om - ok, Fm);
-            }
+        int my_depth = -1, my_parent = -1;
+        if (lane < L.nf) {
+            const uint32_t pw = __float_as_uint(L.fu[lane].w);
+            my_parent = (int)(pw & 0xffffu) - 1;
+            my_depth = (int)(pw >> 16);
         }
-        if (lane == 0) {
-            grad[0] = F.x; grad[1] = F.y; grad[2] = F.z;
-            grad[3] = Tq.x; grad[4] = Tq.y; grad[5] = Tq.z;
-        } else if (lane < L.nf) {
-            const float4 uref = L.fu[lane];
-            const float4 r0 = S.R[4 * lane], r1 = S.R[4 * lane + 1], r2 = S.R[4 * lane + 2];
-            const float3 u = make_float3(r0.x * uref.x + r0.y * uref.y + r0.z * uref.z,
-                                         r1.x * uref.x + r1.y * uref.y + r1.z * uref.z,
-                                         r2.x * uref.x + r2.y * uref.y + r2.z * uref.z);
-            grad[6 + lane - 1] = dot3(u, Tq);
+        for (int d = L.maxdepth; d >= 1; d--) {
+            if (my_depth == d) {
+                const float3 Fk = make_float3(S.ft[lane], S.ft[S.nf4 + lane], S.ft[2 * S.nf4 + lane]);
+                const float3 Tk = make_float3(S.ft[3 * S.nf4 + lane], S.ft[4 * S.nf4 + lane], S.ft[5 * S.nf4 + lane]);
+                const float3 lever = f3(S.R[4 * lane + 3]) - f3(S.R[4 * my_parent + 3]);
+                const float3 Tp = Tk + cross3(lever, Fk);
+                float *fp = S.ft + my_parent;
+                atomicAdd(fp, Fk.x);
+                atomicAdd(fp + S.nf4, Fk.y);
+                atomicAdd(fp + 2 * S.nf4, Fk.z);
+                atomicAdd(fp + 3 * S.nf4, Tp.x);
+                atomicAdd(fp + 4 * S.nf4, Tp.y);
+                atomicAdd(fp + 5 * S.nf4, Tp.z);
+            }
+            wave_sync();
+        }
+        if (lane < L.nf) {
+            const float3 F = make_float3(S.ft[lane], S.ft[S.nf4 + lane], S.ft[2 * S.nf4 + lane]);
+            const float3 Tq = make_float3(S.ft[3 * S.nf4 + lane], S.ft[4 * S.nf4 + lane], S.ft[5 * S.nf4 + lane]);
+            if (lane == 0) {
+                grad[0] = F.x; grad[1] = F.y; grad[2] = F.z;
+                grad[3] = Tq.x; grad[4] = Tq.y; grad[5] = Tq.z;
+            } else {
+                const float4 uref = L.fu[lane];
+                const float4 r0 = S.R[4 * lane], r1 = S.R[4 * lane + 1], r2 = S.R[4 * lane + 2];
+                const float3 u = make_float3(r0.x * uref.x + r0.y * uref.y + r0.z * uref.z,
+                                             r1.x * uref.x + r1.y * uref.y + r1.z * uref.z,
+                                             r2.x * uref.x + r2.y * uref.y + r2.z * uref.z);
+                grad[6 + lane - 1] = dot3(u, Tq);
+            }
         }
     }
     wave_sync();
@@ -728,11 +775,12 @@ __global__ __launch_bounds__(256) void eval_kernel(const uint32_t *blob, int blo
     uint32_t *lds = reinterpret_cast<uint32_t *>(lds4);
     stage_blob(blob, blob_words, lds);
     const LigL L = make_lig(lds);
-    const Layout lay = make_layout(L.na, L.nf, L.D, L.nx);
+    const Layout lay = make_layout(L.na, L.nf, L.np, L.D, L.nx);
     const WaveL S = make_wave(reinterpret_cast<float *>(lds) + blob_words + wave_id() * lay.wave_words, lay);
     const int idx = blockIdx.x * (blockDim.x >> 6) + wave_id();
     if (idx >= n) return;
     const int lane = lane_id();
+    if (lane == 0) S.pf[L.np] = make_float4(0.f, 0.f, 0.f, 0.f);
     if (lane < L.nx) S.trial[lane] = poses[(long)idx * L.nx + lane];
     wave_sync();
     const PairRegs<PPL> pr = load_pairs<PPL>(L);
@@ -761,13 +809,14 @@ __global__ __launch_bounds__(256) void local_opt_kernel(const uint32_t *blob, in
     uint32_t *lds = reinterpret_cast<uint32_t *>(lds4);
     stage_blob(blob, blob_words, lds);
     const LigL L = make_lig(lds);
-    const Layout lay = make_layout(L.na, L.nf, L.D, L.nx);
+    const Layout lay = make_layout(L.na, L.nf, L.np, L.D, L.nx);
     float *cbase = reinterpret_cast<float *>(lds) + blob_words;
     const ChainL C = make_chain(cbase, lay);
     float *wbase = cbase + lay.chain_words;
     const int W = (int)(blockDim.x >> 6);
     const int idx = blockIdx.x;
     const int lane = lane_id(), w = wave_id();
+    if (lane == 0) make_wave(wbase + w * lay.wave_words, lay).pf[L.np] = make_float4(0.f, 0.f, 0.f, 0.f);
     if (w == 0 && lane < L.nx) C.cur[lane] = poses_in[(long)idx * L.nx + lane];
     __syncthreads();
     int evals = 0;
@@ -797,7 +846,7 @@ __global__ __launch_bounds__(256) void dock_kernel(const uint32_t *blob, int blo
     uint32_t *lds = reinterpret_cast<uint32_t *>(lds4);
     stage_blob(blob, blob_words, lds);
     const LigL L = make_lig(lds);
-    const Layout lay = make_layout(L.na, L.nf, L.D, L.nx);
+    const Layout lay = make_layout(L.na, L.nf, L.np, L.D, L.nx);
     float *cbase = reinterpret_cast<float *>(lds) + blob_words;
     const ChainL C = make_chain(cbase, lay);
     float *wbase = cbase + lay.chain_words;
@@ -806,6 +855,7 @@ __global__ __launch_bounds__(256) void dock_kernel(const uint32_t *blob, int blo
     const PairRegs<PPL> pr = load_pairs<PPL>(L);
     const int lane = lane_id(), w = wave_id();
     const uint32_t c = (uint32_t)chain;
+    if (lane == 0) make_wave(wbase + w * lay.wave_words, lay).pf[L.np] = make_float4(0.f, 0.f, 0.f, 0.f);
 
     // initial pose: position uniform in the box, Shoemake orientation, uniform torsions
     if (w == 0) {
@@ -971,7 +1021,7 @@ inline int pick_eval_waves(size_t blob_bytes, size_t wave_bytes)
 
 size_t search_lds_bytes(const LigHeader &h, int waves)
 {
-    const Layout c = make_layout(h.n_atoms, h.n_frags, 6 + h.n_tors, 7 + h.n_tors);
+    const Layout c = make_layout(h.n_atoms, h.n_frags, h.n_pairs, 6 + h.n_tors, 7 + h.n_tors);
     return (size_t)h.total_words * 4 + (size_t)c.chain_words * 4 + (size_t)waves * c.wave_words * 4;
 }
 
@@ -980,7 +1030,7 @@ hipError_t launch_eval(const uint32_t *blob, int blob_words, const LigHeader &h,
                        hipStream_t stream)
 {
     if (n <= 0) return hipSuccess;
-    const Layout c = make_layout(h.n_atoms, h.n_frags, 6 + h.n_tors, 7 + h.n_tors);
+    const Layout c = make_layout(h.n_atoms, h.n_frags, h.n_pairs, 6 + h.n_tors, 7 + h.n_tors);
     const size_t wb = (size_t)c.wave_words * 4, bb = (size_t)blob_words * 4;
     const int w = pick_eval_waves(bb, wb);
     const int blocks = (n + w - 1) / w;
