@@ -235,6 +235,29 @@ dsdp_status dsdp_dock(dsdp_grids g, const dsdp_ligand *lig, int32_t n_chains, in
                       dsdp_pose *out, float *out_xyz, int32_t *n_out, dsdp_pose *chains_out,
                       dsdp_dock_stats *stats);
 
+/* Device workspace bytes for dsdp_dock_batch over these ligands (0 on invalid input). */
+size_t dsdp_dock_batch_workspace_bytes(const dsdp_ligand *ligs, int32_t n_ligs, int32_t n_chains);
+
+/*
+ * Dock many ligands against one set of grids in one submission: every ligand
+ * gets n_chains chains of n_steps steps seeded by seeds[l], exactly as dsdp_dock
+ * would run them alone (a chain's result depends only on its seed, its index,
+ * its ligand, the grids and the parameters), then its own ranking.  Ligands of
+ * uneven size share the launches: chains are grouped by the ligand's pair-list
+ * size class, each group launched with the wave count the library's tuner picks
+ * for the group's chain count; the MC steps run in ticks of steps_per_tick steps
+ * (0 = about eight ticks) that continue from saved chain state, and the ticks
+ * and the ranking are captured once into a HIP graph and launched as one unit.
+ *   ligs, seeds  host [n_ligs];
+ *   out          host [n_ligs][top_k];  n_out host [n_ligs];
+ *   stats        nullable: totals over the batch (kernel_ms = graph device time).
+ * Synchronous: returns after the results are on the host.
+ */
+dsdp_status dsdp_dock_batch(dsdp_grids g, const dsdp_ligand *ligs, int32_t n_ligs, int32_t n_chains, int32_t n_steps,
+                            const uint64_t *seeds, const dsdp_params *prm, int32_t top_k, int32_t steps_per_tick,
+                            void *d_ws, size_t ws_bytes, void *stream, dsdp_pose *out, int32_t *n_out,
+                            dsdp_dock_stats *stats);
+
 #ifdef __cplusplus
 }
 #endif

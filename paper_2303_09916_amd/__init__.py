@@ -86,6 +86,11 @@ _SIGS = {
                               C.POINTER(dsdp_params), C.c_int32, _vp, C.c_size_t, _vp, C.POINTER(dsdp_pose),
                               C.POINTER(C.c_float), C.POINTER(C.c_int32), C.POINTER(dsdp_pose),
                               C.POINTER(dsdp_dock_stats)]),
+    "dsdp_dock_batch_workspace_bytes": (C.c_size_t, [C.POINTER(dsdp_ligand), C.c_int32, C.c_int32]),
+    "dsdp_dock_batch": (C.c_int32, [_vp, C.POINTER(dsdp_ligand), C.c_int32, C.c_int32, C.c_int32,
+                                    C.POINTER(C.c_uint64), C.POINTER(dsdp_params), C.c_int32, C.c_int32, _vp,
+                                    C.c_size_t, _vp, C.POINTER(dsdp_pose), C.POINTER(C.c_int32),
+                                    C.POINTER(dsdp_dock_stats)]),
 }
 EXPORTED = tuple(_SIGS)
 
@@ -273,3 +278,29 @@ def dsdp_dock(grids, lig, n_chains, n_steps, seed, top_k, d_ws, params=None, str
 def pose_array(p, n_tors):
     """dsdp_pose -> pose vector [p(3), q(4), theta(n_tors)] (float64)."""
     return np.array(list(p.pos) + list(p.quat) + list(p.tors)[:n_tors], dtype=np.float64)
+
+
+def _lig_array(ligs):
+    arr = (dsdp_ligand * len(ligs))()
+    for i, l in enumerate(ligs):
+        arr[i] = l.c
+    return arr
+
+
+def dsdp_dock_batch_workspace_bytes(ligs, n_chains):
+    return int(lib().dsdp_dock_batch_workspace_bytes(_lig_array(ligs), len(ligs), int(n_chains)))
+
+
+def dsdp_dock_batch(grids, ligs, n_chains, n_steps, seeds, top_k, d_ws, params=None, steps_per_tick=0, stream=None):
+    """Returns (list per ligand of list[dsdp_pose], stats)."""
+    n = len(ligs)
+    arr = _lig_array(ligs)
+    sd = (C.c_uint64 * n)(*[int(x) for x in seeds])
+    out = (dsdp_pose * max(n * top_k, 1))()
+    n_out = (C.c_int32 * n)()
+    stats = dsdp_dock_stats()
+    _check(lib().dsdp_dock_batch(grids, arr, n, int(n_chains), int(n_steps), sd,
+                                 C.byref(params) if params is not None else None, int(top_k), int(steps_per_tick),
+                                 _ptr(d_ws), _nbytes(d_ws), _stream(stream), out, n_out, C.byref(stats)))
+    res = [[out[l * top_k + q] for q in range(n_out[l])] for l in range(n)]
+    return res, stats

@@ -359,21 +359,28 @@ dsdp_status check_params(const dsdp_params *p)
     return DSDP_OK;
 }
 
-// workspace layout of the search calls
+// Workspace layout of the search calls.  The host-written sections (blob arena,
+// tasks, grid views, ranking segments) come first and are uploaded in one copy.
 struct SearchWs {
-    size_t blob, records, xyz, sel, total;
+    size_t arena, tasks, grids, segs, host_end, state, records, xyz, sel, total;
 };
-SearchWs search_ws(const LigHeader &h, int n)
+SearchWs search_ws(size_t arena_words, long n_slots, int n_grids, int n_segs)
 {
     SearchWs w;
     size_t o = 0;
-    w.blob = o; o += align256((size_t)h.total_words * 4);
-    w.records = o; o += align256((size_t)n * kRecWords * 4);
-    w.xyz = o; o += align256((size_t)n * h.n_atoms * 16);
-    w.sel = o; o += align256((size_t)(n + 1) * 4);
+    w.arena = o; o += align256(arena_words * 4);
+    w.tasks = o; o += align256((size_t)n_slots * sizeof(ChainTask));
+    w.grids = o; o += align256((size_t)n_grids * sizeof(GridView));
+    w.segs = o; o += align256((size_t)n_segs * sizeof(RankSeg));
+    w.host_end = o;
+    w.state = o; o += align256((size_t)n_slots * kStWords * 4);
+    w.records = o; o += align256((size_t)n_slots * kRecWords * 4);
+    w.xyz = o; o += align256((size_t)n_slots * kXyzStride * 16);
+    w.sel = o; o += align256((size_t)(n_slots + n_segs) * 4);
     w.total = o;
     return w;
 }
+SearchWs search_ws(const LigHeader &h, int n) { return search_ws((size_t)h.total_words, n, 1, 1); }
 
 dsdp_status upload_blob(const Prepared &pl, char *d_ws, hipStream_t stream)
 {
@@ -382,6 +389,13 @@ dsdp_status upload_blob(const Prepared &pl, char *d_ws, hipStream_t stream)
     HIP_TRY(hipStreamSynchronize(stream), "ligand upload");
     return DSDP_OK;
 }
+
+// Host image of the first workspace sections, uploaded in one copy.
+struct HostImage {
+    std::vector<unsigned char> bytes;
+    explicit HostImage(size_t n) : bytes(n, 0) {}
+    template <typename T> T *at(size_t off) { return reinterpret_cast<T *>(bytes.data() + off); }
+};
 
 bool aligned256(const void *p) { return ((uintptr_t)p & 255u) == 0; }
 
@@ -453,6 +467,31 @@ struct Events {
             if (x) (void)hipEventDestroy(x);
     }
 };
+
+void fill_pose(const float *r, int nt, int chain, dsdp_pose &p)
+{
+    std::memset(&p, 0, sizeof p);
+    for (int a = 0; a < 3; a++) p.pos[a] = r[kRecPose + a];
+    for (int a = 0; a < 4; a++) p.quat[a] = r[kRecPose + 3 + a];
+    for (int k = 0; k < nt; k++) p.tors[k] = r[kRecPose + 7 + k];
+    p.e_total = r[kRecE];
+    p.e_inter = r[kRecE + 1];
+    p.e_intra = r[kRecE + 2];
+    p.e_wall = r[kRecE + 3];
+    p.score = p.e_inter / (1.0f + kWRot * (float)nt);
+    p.chain = chain;
+}
+
+void add_stats(const float *rec, long n, dsdp_dock_stats *stats)
+{
+    for (long c = 0; c < n; c++) {
+        const int *ri = reinterpret_cast<const int *>(rec + c * kRecWords);
+        stats->pose_evals += ri[kRecEvals];
+        stats->accepted += ri[kRecAccepted];
+        stats->local_opts += ri[kRecLocalOpts];
+        if (!std::isfinite(rec[c * kRecWords + kRecE])) stats->n_nonfinite++;
+    }
+}
 
 }  // namespace
 
@@ -645,9 +684,9 @@ dsdp_status dsdp_eval_poses(dsdp_grids g, const dsdp_ligand *lig, const float *d
     if (n_poses == 0) return DSDP_OK;
     hipStream_t s = (hipStream_t)stream;
     char *ws = (char *)d_ws;
-    st = upload_blob(pl, ws + w.blob, s);
+    st = upload_blob(pl, ws + w.arena, s);
     if (st) return st;
-    HIP_TRY(launch_eval((const uint32_t *)(ws + w.blob), pl.h.total_words, pl.h, g->view, to_search(prm), d_poses,
+    HIP_TRY(launch_eval((const uint32_t *)(ws + w.arena), pl.h.total_words, pl.h, g->view, to_search(prm), d_poses,
                         n_poses, d_energy, d_grad, d_xyz, s),
             "eval launch");
     return DSDP_OK;
@@ -672,12 +711,12 @@ dsdp_status dsdp_local_opt(dsdp_grids g, const dsdp_ligand *lig, const float *d_
     if (n_poses == 0) return DSDP_OK;
     hipStream_t s = (hipStream_t)stream;
     char *ws = (char *)d_ws;
-    st = upload_blob(pl, ws + w.blob, s);
+    st = upload_blob(pl, ws + w.arena, s);
     if (st) return st;
     int waves = 1;
     st = pick_waves(prm, pl.h, n_poses, waves);
     if (st) return st;
-    HIP_TRY(launch_local_opt((const uint32_t *)(ws + w.blob), pl.h.total_words, pl.h, g->view, to_search(prm), waves,
+    HIP_TRY(launch_local_opt((const uint32_t *)(ws + w.arena), pl.h.total_words, pl.h, g->view, to_search(prm), waves,
                              d_poses_in, n_poses, d_poses_out, d_energy, d_evals, s),
             "local-opt launch");
     return DSDP_OK;
@@ -709,8 +748,31 @@ dsdp_status dsdp_dock(dsdp_grids g, const dsdp_ligand *lig, int32_t n_chains, in
     if (st) return st;
     hipStream_t s = (hipStream_t)stream;
     char *ws = (char *)d_ws;
-    st = upload_blob(pl, ws + w.blob, s);
-    if (st) return st;
+
+    HostImage img(w.host_end);
+    std::memcpy(img.at<uint32_t>(w.arena), pl.blob.data(), pl.blob.size() * 4);
+    ChainTask *tasks = img.at<ChainTask>(w.tasks);
+    for (int c = 0; c < n_chains; c++) {
+        ChainTask &t = tasks[c];
+        t.blob_off = 0;
+        t.blob_words = (uint32_t)pl.h.total_words;
+        t.chain = (uint32_t)c;
+        t.n_steps = n_steps;
+        t.seed_lo = (uint32_t)seed;
+        t.seed_hi = (uint32_t)(seed >> 32);
+        t.grid = 0;
+        t.slot = c;
+    }
+    *img.at<GridView>(w.grids) = g->view;
+    RankSeg *seg = img.at<RankSeg>(w.segs);
+    seg->slot0 = 0;
+    seg->n_chains = n_chains;
+    seg->n_atoms = pl.h.n_atoms;
+    seg->top_k = top_k;
+    seg->sel_off = 0;
+    HIP_TRY(hipMemcpyAsync(ws, img.bytes.data(), img.bytes.size(), hipMemcpyHostToDevice, s), "task upload");
+    HIP_TRY(hipStreamSynchronize(s), "task upload");
+
     Events ev;
     if (stats) {
         HIP_TRY(ev.create(), "event");
@@ -719,11 +781,12 @@ dsdp_status dsdp_dock(dsdp_grids g, const dsdp_ligand *lig, int32_t n_chains, in
     float *rec = (float *)(ws + w.records);
     float4 *bxyz = (float4 *)(ws + w.xyz);
     int *sel = (int *)(ws + w.sel);
-    HIP_TRY(launch_dock((const uint32_t *)(ws + w.blob), pl.h.total_words, pl.h, g->view, sp, waves, n_chains, n_steps,
-                        seed, rec, bxyz, s),
-            "dock launch");
+    HIP_TRY(launch_tick(pair_slots_class(pl.h.n_pairs), waves, search_lds_bytes(pl.h, waves),
+                        (const uint32_t *)(ws + w.arena), (const ChainTask *)(ws + w.tasks), n_chains,
+                        (const GridView *)(ws + w.grids), sp, n_steps, 1, (float *)(ws + w.state), rec, bxyz, s),
+            "search launch");
     if (stats) HIP_TRY(hipEventRecord(ev.e[1], s), "event");
-    HIP_TRY(launch_rank(rec, bxyz, n_chains, pl.h.n_atoms, top_k, sp.rmsd_cluster, sel, s), "rank launch");
+    HIP_TRY(launch_rank(rec, bxyz, (const RankSeg *)(ws + w.segs), 1, n_chains, sp.rmsd_cluster, sel, s), "rank launch");
     if (stats) HIP_TRY(hipEventRecord(ev.e[2], s), "event");
     std::vector<float> h_rec((size_t)n_chains * kRecWords);
     std::vector<int> h_sel((size_t)top_k + 1);
@@ -731,53 +794,226 @@ dsdp_status dsdp_dock(dsdp_grids g, const dsdp_ligand *lig, int32_t n_chains, in
     HIP_TRY(hipMemcpyAsync(h_sel.data(), sel, h_sel.size() * 4, hipMemcpyDeviceToHost, s), "result copy");
     std::vector<float4> h_xyz;
     if (out_xyz && top_k > 0) {
-        h_xyz.resize((size_t)n_chains * pl.h.n_atoms);
+        h_xyz.resize((size_t)n_chains * kXyzStride);
         HIP_TRY(hipMemcpyAsync(h_xyz.data(), bxyz, h_xyz.size() * 16, hipMemcpyDeviceToHost, s), "result copy");
     }
     HIP_TRY(hipStreamSynchronize(s), "dock");
-    const int nt = pl.h.n_tors, nx = 7 + nt;
-    auto fill_pose = [&](int c, dsdp_pose &p) {
-        std::memset(&p, 0, sizeof p);
-        const float *r = &h_rec[(size_t)c * kRecWords];
-        for (int a = 0; a < 3; a++) p.pos[a] = r[kRecPose + a];
-        for (int a = 0; a < 4; a++) p.quat[a] = r[kRecPose + 3 + a];
-        for (int k = 0; k < nt; k++) p.tors[k] = r[kRecPose + 7 + k];
-        p.e_total = r[kRecE];
-        p.e_inter = r[kRecE + 1];
-        p.e_intra = r[kRecE + 2];
-        p.e_wall = r[kRecE + 3];
-        p.score = p.e_inter / (1.0f + kWRot * (float)nt);
-        p.chain = c;
-    };
-    (void)nx;
-    int cnt = top_k > 0 ? h_sel[0] : 0;
+    const int nt = pl.h.n_tors;
+    const int cnt = top_k > 0 ? h_sel[0] : 0;
     for (int q = 0; q < cnt; q++) {
         const int c = h_sel[1 + q];
-        fill_pose(c, out[q]);
+        fill_pose(&h_rec[(size_t)c * kRecWords], nt, c, out[q]);
         if (out_xyz)
             for (int a = 0; a < pl.h.n_atoms; a++) {
-                const float4 v = h_xyz[(size_t)c * pl.h.n_atoms + a];
+                const float4 v = h_xyz[(size_t)c * kXyzStride + a];
                 float *o = out_xyz + ((size_t)q * pl.h.n_atoms + a) * 3;
                 o[0] = v.x; o[1] = v.y; o[2] = v.z;
             }
     }
     if (n_out) *n_out = cnt;
     if (chains_out)
-        for (int c = 0; c < n_chains; c++) fill_pose(c, chains_out[c]);
+        for (int c = 0; c < n_chains; c++) fill_pose(&h_rec[(size_t)c * kRecWords], nt, c, chains_out[c]);
     if (stats) {
         std::memset(stats, 0, sizeof *stats);
-        for (int c = 0; c < n_chains; c++) {
-            const int *ri = reinterpret_cast<const int *>(&h_rec[(size_t)c * kRecWords]);
-            stats->pose_evals += ri[kRecEvals];
-            stats->accepted += ri[kRecAccepted];
-            stats->local_opts += ri[kRecLocalOpts];
-            if (!std::isfinite(h_rec[(size_t)c * kRecWords + kRecE])) stats->n_nonfinite++;
-        }
+        add_stats(h_rec.data(), n_chains, stats);
         float ms = 0, ms_search = 0;
         HIP_TRY(hipEventElapsedTime(&ms, ev.e[0], ev.e[2]), "event");
         HIP_TRY(hipEventElapsedTime(&ms_search, ev.e[0], ev.e[1]), "event");
         stats->kernel_ms = ms;
         stats->search_ms = ms_search;
+    }
+    return DSDP_OK;
+}
+
+size_t dsdp_dock_batch_workspace_bytes(const dsdp_ligand *ligs, int32_t n_ligs, int32_t n_chains)
+{
+    if (!ligs || n_ligs < 1 || n_chains < 1) return 0;
+    size_t words = 0;
+    for (int l = 0; l < n_ligs; l++) {
+        Prepared pl;
+        if (prepare_ligand(&ligs[l], nullptr, pl)) return 0;
+        words += (size_t)pl.h.total_words;
+    }
+    return search_ws(words, (long)n_ligs * n_chains, 1, n_ligs).total;
+}
+
+dsdp_status dsdp_dock_batch(dsdp_grids g, const dsdp_ligand *ligs, int32_t n_ligs, int32_t n_chains, int32_t n_steps,
+                            const uint64_t *seeds, const dsdp_params *prm, int32_t top_k, int32_t steps_per_tick,
+                            void *d_ws, size_t ws_bytes, void *stream, dsdp_pose *out, int32_t *n_out,
+                            dsdp_dock_stats *stats)
+{
+    if (!g) return fail(DSDP_ERR_INVALID_ARG, "grids handle is NULL");
+    if (!ligs || n_ligs < 1 || !seeds) return fail(DSDP_ERR_INVALID_ARG, "ligands/seeds missing");
+    if (n_chains < 1 || n_chains > 65536) return fail(DSDP_ERR_INVALID_ARG, "n_chains %d outside 1..65536", n_chains);
+    if ((long)n_ligs * n_chains > (1L << 24)) return fail(DSDP_ERR_UNSUPPORTED, "more than 2^24 chains in one batch");
+    if (n_steps < 0 || steps_per_tick < 0) return fail(DSDP_ERR_INVALID_ARG, "negative step count");
+    if (top_k < 0 || top_k > n_chains) return fail(DSDP_ERR_INVALID_ARG, "top_k %d outside 0..n_chains", top_k);
+    if (top_k > 0 && (!out || !n_out)) return fail(DSDP_ERR_INVALID_ARG, "out/n_out is NULL");
+    dsdp_status st = check_params(prm);
+    if (st) return st;
+    std::vector<Prepared> pls((size_t)n_ligs);
+    size_t words = 0;
+    for (int l = 0; l < n_ligs; l++) {
+        st = prepare_ligand(&ligs[l], g->view.map_of_type, pls[l]);
+        if (st) {
+            char msg[600];
+            snprintf(msg, sizeof msg, "ligand %d: %s", l, g_error.c_str());
+            return fail(st, "%s", msg);
+        }
+        words += (size_t)pls[l].h.total_words;
+    }
+    const long n_slots = (long)n_ligs * n_chains;
+    const SearchWs w = search_ws(words, n_slots, 1, n_ligs);
+    if (!d_ws || ws_bytes < w.total) return fail(DSDP_ERR_WORKSPACE_TOO_SMALL, "workspace needs %zu bytes", w.total);
+    if (!aligned256(d_ws)) return fail(DSDP_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    const SearchParams sp = to_search(prm);
+    hipStream_t s = (hipStream_t)stream;
+    char *ws = (char *)d_ws;
+
+    // buckets by pair-slot class; in each, the tuner's wave count for the bucket's
+    // chain count and the largest ligand's LDS
+    struct Bucket {
+        int ppl = 0, waves = 1;
+        size_t lds = 0;
+        long first = 0, count = 0;
+    };
+    std::vector<Bucket> buckets;
+    std::vector<int> order;
+    for (int cls : {8, 16, 32}) {
+        Bucket b;
+        b.ppl = cls;
+        LigHeader worst{};
+        size_t worst_lds = 0;
+        for (int l = 0; l < n_ligs; l++)
+            if (pair_slots_class(pls[l].h.n_pairs) == cls) {
+                order.push_back(l);
+                b.count += n_chains;
+                if (search_lds_bytes(pls[l].h, 1) > worst_lds) {
+                    worst_lds = search_lds_bytes(pls[l].h, 1);
+                    worst = pls[l].h;
+                }
+            }
+        if (!b.count) continue;
+        b.first = (long)order.size() * n_chains - b.count;
+        st = pick_waves(prm, worst, (int)std::min<long>(b.count, 1L << 30), b.waves);
+        if (st) return st;
+        for (;;) {
+            b.lds = 0;
+            for (int l : order)
+                if (pair_slots_class(pls[l].h.n_pairs) == cls)
+                    b.lds = std::max(b.lds, search_lds_bytes(pls[l].h, b.waves));
+            if (b.lds <= device_max_lds() || b.waves == 1) break;
+            b.waves--;
+        }
+        if (b.lds > device_max_lds()) return fail(DSDP_ERR_UNSUPPORTED, "a ligand needs %zu bytes of LDS", b.lds);
+        buckets.push_back(b);
+    }
+
+    HostImage img(w.host_end);
+    std::vector<uint32_t> blob_off((size_t)n_ligs);
+    {
+        size_t o = 0;
+        for (int l = 0; l < n_ligs; l++) {
+            blob_off[l] = (uint32_t)o;
+            std::memcpy(img.at<uint32_t>(w.arena) + o, pls[l].blob.data(), pls[l].blob.size() * 4);
+            o += pls[l].blob.size();
+        }
+    }
+    ChainTask *tasks = img.at<ChainTask>(w.tasks);
+    long ti = 0;
+    for (int l : order)
+        for (int c = 0; c < n_chains; c++, ti++) {
+            ChainTask &t = tasks[ti];
+            t.blob_off = blob_off[l];
+            t.blob_words = (uint32_t)pls[l].h.total_words;
+            t.chain = (uint32_t)c;
+            t.n_steps = n_steps;
+            t.seed_lo = (uint32_t)seeds[l];
+            t.seed_hi = (uint32_t)(seeds[l] >> 32);
+            t.grid = 0;
+            t.slot = (int)((long)l * n_chains + c);
+        }
+    *img.at<GridView>(w.grids) = g->view;
+    RankSeg *segs = img.at<RankSeg>(w.segs);
+    for (int l = 0; l < n_ligs; l++) {
+        segs[l].slot0 = l * n_chains;
+        segs[l].n_chains = n_chains;
+        segs[l].n_atoms = pls[l].h.n_atoms;
+        segs[l].top_k = top_k;
+        segs[l].sel_off = l * (n_chains + 1);
+    }
+    HIP_TRY(hipMemcpyAsync(ws, img.bytes.data(), img.bytes.size(), hipMemcpyHostToDevice, s), "task upload");
+    HIP_TRY(hipStreamSynchronize(s), "task upload");
+
+    // ticks of steps_per_tick MC steps (0: about eight ticks), captured once as a
+    // graph: for each tick one launch per bucket, then the ranking
+    const int spt = steps_per_tick > 0 ? steps_per_tick : std::max(1, (n_steps + 7) / 8);
+    const int n_ticks = n_steps > 0 ? (n_steps + spt - 1) / spt : 1;
+    float *rec = (float *)(ws + w.records);
+    float4 *bxyz = (float4 *)(ws + w.xyz);
+    int *sel = (int *)(ws + w.sel);
+    hipStream_t cs = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "stream");
+    struct StreamGuard {
+        hipStream_t s;
+        ~StreamGuard() { (void)hipStreamDestroy(s); }
+    } guard{cs};
+    hipGraph_t graph = nullptr;
+    HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed), "graph capture");
+    hipError_t le = hipSuccess;
+    for (int k = 0; k < n_ticks && le == hipSuccess; k++)
+        for (const Bucket &b : buckets) {
+            le = launch_tick(b.ppl, b.waves, b.lds, (const uint32_t *)(ws + w.arena),
+                             (const ChainTask *)(ws + w.tasks) + b.first, (int)b.count, (const GridView *)(ws + w.grids),
+                             sp, spt, k == 0 ? 1 : 0, (float *)(ws + w.state), rec, bxyz, cs);
+            if (le != hipSuccess) break;
+        }
+    if (le == hipSuccess) le = launch_rank(rec, bxyz, (const RankSeg *)(ws + w.segs), n_ligs, n_chains, sp.rmsd_cluster, sel, cs);
+    hipError_t ce = hipStreamEndCapture(cs, &graph);
+    if (le != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return hip_fail(le, "batch launch");
+    }
+    HIP_TRY(ce, "graph capture");
+    hipGraphExec_t exec = nullptr;
+    hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    HIP_TRY(ie, "graph instantiate");
+    struct ExecGuard {
+        hipGraphExec_t e;
+        ~ExecGuard() { (void)hipGraphExecDestroy(e); }
+    } eguard{exec};
+    Events ev;
+    if (stats) {
+        HIP_TRY(ev.create(), "event");
+        HIP_TRY(hipEventRecord(ev.e[0], s), "event");
+    }
+    HIP_TRY(hipGraphLaunch(exec, s), "graph launch");
+    if (stats) {
+        HIP_TRY(hipEventRecord(ev.e[1], s), "event");
+        HIP_TRY(hipEventRecord(ev.e[2], s), "event");
+    }
+    std::vector<float> h_rec((size_t)n_slots * kRecWords);
+    std::vector<int> h_sel((size_t)n_slots + n_ligs);
+    HIP_TRY(hipMemcpyAsync(h_rec.data(), rec, h_rec.size() * 4, hipMemcpyDeviceToHost, s), "result copy");
+    HIP_TRY(hipMemcpyAsync(h_sel.data(), sel, h_sel.size() * 4, hipMemcpyDeviceToHost, s), "result copy");
+    HIP_TRY(hipStreamSynchronize(s), "batch");
+    for (int l = 0; l < n_ligs; l++) {
+        const int *sl = &h_sel[(size_t)l * (n_chains + 1)];
+        const int cnt = top_k > 0 ? sl[0] : 0;
+        for (int q = 0; q < cnt; q++) {
+            const int c = sl[1 + q];
+            fill_pose(&h_rec[((size_t)l * n_chains + c) * kRecWords], pls[l].h.n_tors, c, out[(size_t)l * top_k + q]);
+        }
+        if (n_out) n_out[l] = cnt;
+    }
+    if (stats) {
+        std::memset(stats, 0, sizeof *stats);
+        add_stats(h_rec.data(), n_slots, stats);
+        float ms = 0;
+        HIP_TRY(hipEventElapsedTime(&ms, ev.e[0], ev.e[2]), "event");
+        stats->kernel_ms = ms;
+        stats->search_ms = ms;
     }
     return DSDP_OK;
 }

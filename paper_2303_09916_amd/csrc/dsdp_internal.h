@@ -86,6 +86,37 @@ constexpr int kRecAccepted = 45;   // int32 Metropolis acceptances
 constexpr int kRecLocalOpts = 46;  // int32 local optimisations
 constexpr int kRecWords = 48;
 
+// One chain of one docking request, as a search workgroup sees it.
+struct ChainTask {
+    uint32_t blob_off;       // word offset of the ligand blob in the blob arena
+    uint32_t blob_words;
+    uint32_t chain;          // chain index within its request (Philox counter word)
+    int32_t n_steps;         // total MC steps of the chain; < 0 marks an empty slot
+    uint32_t seed_lo, seed_hi;
+    int32_t grid;            // index into the GridView array
+    int32_t slot;            // index of the chain's state, record and best coordinates
+};
+
+// Resumable chain state in device memory (words): a chain advanced in several
+// ticks computes exactly what one uninterrupted run computes.
+constexpr int kStCur = 0;          // 40 floats: current pose
+constexpr int kStBest = 40;        // 40 floats: best pose
+constexpr int kStE = 80;           // current energy (total, inter, intra, wall)
+constexpr int kStEb = 84;          // best energy
+constexpr int kStStep = 88;        // int: next MC step
+constexpr int kStEvals = 89, kStAcc = 90, kStLopt = 91;
+constexpr int kStWords = 96;
+constexpr int kXyzStride = 64;     // best-pose coordinates per slot (float4)
+
+// Ranking of one request's chains.
+struct RankSeg {
+    int32_t slot0;           // first slot of the request
+    int32_t n_chains;
+    int32_t n_atoms;
+    int32_t top_k;
+    int32_t sel_off;         // output: sel[sel_off] = count, then chain indices
+};
+
 // Random-number streams (Philox4x32-10 counter = chain, step, stream, block; key = seed).
 constexpr uint32_t kTagInit = 0, kTagMutate = 1, kTagMetropolis = 2;
 
@@ -106,10 +137,13 @@ hipError_t launch_eval(const uint32_t *blob, int blob_words, const LigHeader &h,
 hipError_t launch_local_opt(const uint32_t *blob, int blob_words, const LigHeader &h, const GridView &g,
                             const SearchParams &p, int waves, const float *poses_in, int n, float *poses_out,
                             float *energy, int *evals, hipStream_t stream);
-hipError_t launch_dock(const uint32_t *blob, int blob_words, const LigHeader &h, const GridView &g,
-                       const SearchParams &p, int waves, int n_chains, int n_steps, uint64_t seed, float *records,
-                       float4 *best_xyz, hipStream_t stream);
-hipError_t launch_rank(const float *records, const float4 *best_xyz, int n_chains, int n_atoms, int top_k,
-                       float rmsd_cut, int *sel, hipStream_t stream);
+// Advance every task by up to tick_steps MC steps (init = start chains afresh).
+// ppl: pair slots per lane (8, 16 or 32); lds_bytes: per-workgroup LDS.
+hipError_t launch_tick(int ppl, int waves, size_t lds_bytes, const uint32_t *arena, const ChainTask *tasks,
+                       int n_tasks, const GridView *grids, const SearchParams &p, int tick_steps, int init,
+                       float *state, float *records, float4 *best_xyz, hipStream_t stream);
+hipError_t launch_rank(const float *records, const float4 *best_xyz, const RankSeg *segs, int n_segs,
+                       int max_chains, float rmsd_cut, int *sel, hipStream_t stream);
+int pair_slots_class(int n_pairs);   // 8, 16 or 32
 
 }  // namespace dsdp

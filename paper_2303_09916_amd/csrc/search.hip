@@ -834,63 +834,80 @@ __global__ __launch_bounds__(256) void local_opt_kernel(const uint32_t *blob, in
     }
 }
 
-// One Monte Carlo chain per workgroup of W waves: initial pose, then n_steps of
-// mutate -> BFGS -> Metropolis, keeping the lowest accepted energy.  Results go
-// to `records` (kRecWords per chain) and the best pose's coordinates to best_xyz.
+// One Monte Carlo chain per workgroup of W waves, resumable: a task's chain
+// starts from its initial pose (position uniform in the box, Shoemake
+// orientation, uniform torsions) or from its saved state, runs up to tick_steps
+// steps of mutate -> BFGS -> Metropolis, keeping the lowest accepted energy, and
+// saves its state.  A chain that reaches its last step writes its record and the
+// coordinates of its best pose (for ranking).
 template <int PPL>
-__global__ __launch_bounds__(256) void dock_kernel(const uint32_t *blob, int blob_words, GridView G, SearchParams P,
-                                                   int n_chains, int n_steps, uint64_t seed, float *records,
-                                                   float4 *best_xyz)
+__global__ __launch_bounds__(256) void tick_kernel(const uint32_t *arena, const ChainTask *tasks, const GridView *grids,
+                                                   SearchParams P, int tick_steps, int init, float *state,
+                                                   float *records, float4 *best_xyz)
 {
+    const ChainTask t = tasks[blockIdx.x];
+    if (t.n_steps < 0) return;
     extern __shared__ float4 lds4[];
     uint32_t *lds = reinterpret_cast<uint32_t *>(lds4);
-    stage_blob(blob, blob_words, lds);
+    stage_blob(arena + t.blob_off, (int)t.blob_words, lds);
+    const GridView G = grids[t.grid];
     const LigL L = make_lig(lds);
     const Layout lay = make_layout(L.na, L.nf, L.np, L.D, L.nx);
-    float *cbase = reinterpret_cast<float *>(lds) + blob_words;
+    float *cbase = reinterpret_cast<float *>(lds) + t.blob_words;
     const ChainL C = make_chain(cbase, lay);
     float *wbase = cbase + lay.chain_words;
     const int W = (int)(blockDim.x >> 6);
-    const int chain = blockIdx.x;
     const PairRegs<PPL> pr = load_pairs<PPL>(L);
     const int lane = lane_id(), w = wave_id();
-    const uint32_t c = (uint32_t)chain;
+    const uint32_t c = t.chain;
+    const uint64_t seed = (uint64_t)t.seed_lo | ((uint64_t)t.seed_hi << 32);
+    float *st = state + (long)t.slot * kStWords;
+    int *sti = reinterpret_cast<int *>(st);
     if (lane == 0) make_wave(wbase + w * lay.wave_words, lay).pf[L.np] = make_float4(0.f, 0.f, 0.f, 0.f);
 
-    // initial pose: position uniform in the box, Shoemake orientation, uniform torsions
-    if (w == 0) {
-        const int nw = 6 + L.nt;
-        if (lane < nw) {
-            const uint4 r = draw(seed, c, 0u, kTagInit, (uint32_t)(lane >> 2));
-            const uint32_t v = (lane & 3) == 0 ? r.x : ((lane & 3) == 1 ? r.y : ((lane & 3) == 2 ? r.z : r.w));
-            C.misc[lane] = unif(v);
+    Energy Ex, Eb;
+    int step, evals, accepted, lopts;
+    if (init) {
+        if (w == 0) {
+            const int nw = 6 + L.nt;
+            if (lane < nw) {
+                const uint4 r = draw(seed, c, 0u, kTagInit, (uint32_t)(lane >> 2));
+                const uint32_t v = (lane & 3) == 0 ? r.x : ((lane & 3) == 1 ? r.y : ((lane & 3) == 2 ? r.z : r.w));
+                C.misc[lane] = unif(v);
+            }
+            wave_sync();
+            if (lane < 3) {
+                C.cur[lane] = G.origin[lane] + C.misc[lane] * ((float)(G.n[lane] - 1) * G.h);
+            } else if (lane < 7) {
+                const float u1 = C.misc[3], u2 = C.misc[4], u3 = C.misc[5];
+                const float s1 = sqrtf(1.f - u1), s2 = sqrtf(u1);
+                const float sa = __sinf(2 * kPi * u2), ca = __cosf(2 * kPi * u2);
+                const float sb = __sinf(2 * kPi * u3), cb = __cosf(2 * kPi * u3);
+                const float v = lane == 3 ? s2 * cb : (lane == 4 ? s1 * sa : (lane == 5 ? s1 * ca : s2 * sb));
+                C.cur[lane] = v;
+            } else if (lane < L.nx) {
+                C.cur[lane] = -kPi + 2 * kPi * C.misc[6 + lane - 7];
+            }
+            wave_sync();
+            copy_pose(L, C.cur, C.best);
         }
-        wave_sync();
-        if (lane < 3) {
-            C.cur[lane] = G.origin[lane] + C.misc[lane] * ((float)(G.n[lane] - 1) * G.h);
-        } else if (lane < 7) {
-            const float u1 = C.misc[3], u2 = C.misc[4], u3 = C.misc[5];
-            const float s1 = sqrtf(1.f - u1), s2 = sqrtf(u1);
-            const float sa = __sinf(2 * kPi * u2), ca = __cosf(2 * kPi * u2);
-            const float sb = __sinf(2 * kPi * u3), cb = __cosf(2 * kPi * u3);
-            const float v = lane == 3 ? s2 * cb : (lane == 4 ? s1 * sa : (lane == 5 ? s1 * ca : s2 * sb));
-            C.cur[lane] = v;
-        } else if (lane < L.nx) {
-            C.cur[lane] = -kPi + 2 * kPi * C.misc[6 + lane - 7];
+        Ex.total = 0.f; Ex.inter = 0.f; Ex.intra = 0.f; Ex.wall = 0.f;
+        Eb.total = __int_as_float(0x7f800000); Eb.inter = Eb.intra = Eb.wall = 0.f;
+        step = 0; evals = 0; accepted = 0; lopts = 0;
+    } else {
+        if (w == 0 && lane < L.nx) {
+            C.cur[lane] = st[kStCur + lane];
+            C.best[lane] = st[kStBest + lane];
         }
-        wave_sync();
-        copy_pose(L, C.cur, C.best);
+        Ex = get_energy(st + kStE);
+        Eb = get_energy(st + kStEb);
+        step = sti[kStStep]; evals = sti[kStEvals]; accepted = sti[kStAcc]; lopts = sti[kStLopt];
     }
     __syncthreads();
 
-    Energy Ex;
-    Ex.total = 0.f; Ex.inter = 0.f; Ex.intra = 0.f; Ex.wall = 0.f;
-    Energy Eb;
-    Eb.total = __int_as_float(0x7f800000); Eb.inter = Eb.intra = Eb.wall = 0.f;
-    int evals = 0, accepted = 0, lopts = 0;
     const float rot_amp = L.rg > 0.f ? P.trans_amp / L.rg : 0.f;
-
-    for (int step = 0; step < n_steps; step++) {
+    const int s_end = min(t.n_steps, step + tick_steps);
+    for (; step < s_end; step++) {
         if (w == 0) {
             copy_pose(L, C.cur, C.cand);
             // mutation: one of 2 + n_tors moves, chosen in integer arithmetic
@@ -929,49 +946,65 @@ __global__ __launch_bounds__(256) void dock_kernel(const uint32_t *blob, int blo
         }
     }
 
-    // coordinates of the best pose (for RMSD clustering)
-    if (w == 0) {
-        const WaveL S = make_wave(wbase, lay);
-        eval_pose(L, S, pr, G, C.best, nullptr, P.wall_slope);
-        float *rec = records + (long)chain * kRecWords;
-        if (lane < L.nx) rec[kRecPose + lane] = C.best[lane];
-        if (lane == 0) {
-            rec[kRecE + 0] = Eb.total;
-            rec[kRecE + 1] = Eb.inter;
-            rec[kRecE + 2] = Eb.intra;
-            rec[kRecE + 3] = Eb.wall;
-            reinterpret_cast<int *>(rec)[kRecEvals] = evals;
-            reinterpret_cast<int *>(rec)[kRecAccepted] = accepted;
-            reinterpret_cast<int *>(rec)[kRecLocalOpts] = lopts;
-        }
-        if (lane < L.na) best_xyz[(long)chain * L.na + lane] = S.xyz[lane];
+    if (w != 0) return;
+    // save the chain state
+    if (lane < L.nx) {
+        st[kStCur + lane] = C.cur[lane];
+        st[kStBest + lane] = C.best[lane];
     }
+    if (lane == 0) {
+        put_energy(st + kStE, Ex);
+        put_energy(st + kStEb, Eb);
+        sti[kStStep] = step;
+        sti[kStEvals] = evals;
+        sti[kStAcc] = accepted;
+        sti[kStLopt] = lopts;
+    }
+    if (step < t.n_steps) return;
+    // finished: record, and the coordinates of the best pose for RMSD clustering
+    const WaveL S = make_wave(wbase, lay);
+    eval_pose(L, S, pr, G, C.best, nullptr, P.wall_slope);
+    float *rec = records + (long)t.slot * kRecWords;
+    if (lane < L.nx) rec[kRecPose + lane] = C.best[lane];
+    if (lane == 0) {
+        rec[kRecE + 0] = Eb.total;
+        rec[kRecE + 1] = Eb.inter;
+        rec[kRecE + 2] = Eb.intra;
+        rec[kRecE + 3] = Eb.wall;
+        reinterpret_cast<int *>(rec)[kRecEvals] = evals;
+        reinterpret_cast<int *>(rec)[kRecAccepted] = accepted;
+        reinterpret_cast<int *>(rec)[kRecLocalOpts] = lopts;
+    }
+    if (lane < L.na) best_xyz[(long)t.slot * kXyzStride + lane] = S.xyz[lane];
 }
 
-// Ranking (post-processing): repeatedly take the lowest (energy, chain) candidate
-// still alive, then drop every candidate within rmsd_cut of it.  This selects the
-// same poses as a greedy pass over the sorted list that keeps a pose when its
-// RMSD to every kept pose exceeds the cut.
-__global__ __launch_bounds__(1024) void rank_kernel(const float *records, const float4 *best_xyz, int n_chains,
-                                                    int n_atoms, int top_k, float rmsd_cut, int *sel)
+// Ranking (post-processing), one workgroup per request: repeatedly take the
+// lowest (energy, chain) candidate still alive, then drop every candidate within
+// rmsd_cut of it.  This selects the same poses as a greedy pass over the sorted
+// list that keeps a pose when its RMSD to every kept pose exceeds the cut.
+__global__ __launch_bounds__(1024) void rank_kernel(const float *records, const float4 *best_xyz, const RankSeg *segs,
+                                                    float rmsd_cut, int *sel)
 {
     extern __shared__ unsigned char rank_lds[];
     unsigned char *alive = rank_lds;
     __shared__ unsigned long long s_red[16];
     __shared__ int s_pick;
+    const RankSeg g = segs[blockIdx.x];
     const int tid = threadIdx.x, nt = blockDim.x;
-    for (int c = tid; c < n_chains; c += nt) {
-        const float e = records[(long)c * kRecWords + kRecE];
+    const float *rec0 = records + (long)g.slot0 * kRecWords;
+    const float4 *xyz0 = best_xyz + (long)g.slot0 * kXyzStride;
+    for (int c = tid; c < g.n_chains; c += nt) {
+        const float e = rec0[(long)c * kRecWords + kRecE];
         alive[c] = (e == e && fabsf(e) != __int_as_float(0x7f800000)) ? 1 : 0;
     }
     __syncthreads();
-    const float cut2n = rmsd_cut * rmsd_cut * (float)n_atoms;
+    const float cut2n = rmsd_cut * rmsd_cut * (float)g.n_atoms;
     int count = 0;
-    for (int r = 0; r < top_k; r++) {
+    for (int r = 0; r < g.top_k; r++) {
         unsigned long long best = ~0ull;
-        for (int c = tid; c < n_chains; c += nt) {
+        for (int c = tid; c < g.n_chains; c += nt) {
             if (!alive[c]) continue;
-            const uint32_t b = __float_as_uint(records[(long)c * kRecWords + kRecE]);
+            const uint32_t b = __float_as_uint(rec0[(long)c * kRecWords + kRecE]);
             const uint32_t key = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
             const unsigned long long k = ((unsigned long long)key << 32) | (uint32_t)c;
             best = k < best ? k : best;
@@ -990,14 +1023,14 @@ __global__ __launch_bounds__(1024) void rank_kernel(const float *records, const 
         __syncthreads();
         const int pick = s_pick;
         if (pick < 0) break;
-        if (tid == 0) sel[1 + count] = pick;
+        if (tid == 0) sel[g.sel_off + 1 + count] = pick;
         count++;
-        const float4 *xp = best_xyz + (long)pick * n_atoms;
-        for (int c = tid; c < n_chains; c += nt) {
+        const float4 *xp = xyz0 + (long)pick * kXyzStride;
+        for (int c = tid; c < g.n_chains; c += nt) {
             if (!alive[c]) continue;
-            const float4 *xc = best_xyz + (long)c * n_atoms;
+            const float4 *xc = xyz0 + (long)c * kXyzStride;
             float s = 0.f;
-            for (int a = 0; a < n_atoms; a++) {
+            for (int a = 0; a < g.n_atoms; a++) {
                 const float4 p = xp[a], q = xc[a];
                 const float dx = p.x - q.x, dy = p.y - q.y, dz = p.z - q.z;
                 s += dx * dx + dy * dy + dz * dz;
@@ -1006,7 +1039,7 @@ __global__ __launch_bounds__(1024) void rank_kernel(const float *records, const 
         }
         __syncthreads();
     }
-    if (tid == 0) sel[0] = count;
+    if (tid == 0) sel[g.sel_off] = count;
 }
 
 inline int pick_eval_waves(size_t blob_bytes, size_t wave_bytes)
@@ -1062,31 +1095,34 @@ hipError_t launch_local_opt(const uint32_t *blob, int blob_words, const LigHeade
     return hipGetLastError();
 }
 
-hipError_t launch_dock(const uint32_t *blob, int blob_words, const LigHeader &h, const GridView &g,
-                       const SearchParams &p, int waves, int n_chains, int n_steps, uint64_t seed, float *records,
-                       float4 *best_xyz, hipStream_t stream)
+int pair_slots_class(int n_pairs) { return n_pairs <= 512 ? 8 : (n_pairs <= 1024 ? 16 : 32); }
+
+hipError_t launch_tick(int ppl, int waves, size_t lds_bytes, const uint32_t *arena, const ChainTask *tasks,
+                       int n_tasks, const GridView *grids, const SearchParams &p, int tick_steps, int init,
+                       float *state, float *records, float4 *best_xyz, hipStream_t stream)
 {
-    if (n_chains <= 0) return hipSuccess;
+    if (n_tasks <= 0) return hipSuccess;
     if (waves < 1 || waves > kMaxWaves) return hipErrorInvalidValue;
-    const size_t lds = search_lds_bytes(h, waves);
-    if (h.n_pairs <= 512)
-        dock_kernel<8><<<n_chains, 64 * waves, lds, stream>>>(blob, blob_words, g, p, n_chains, n_steps, seed, records,
-                                                              best_xyz);
-    else if (h.n_pairs <= 1024)
-        dock_kernel<16><<<n_chains, 64 * waves, lds, stream>>>(blob, blob_words, g, p, n_chains, n_steps, seed, records,
-                                                               best_xyz);
+    const dim3 grid(n_tasks), block(64 * waves);
+    if (ppl == 8)
+        tick_kernel<8><<<grid, block, lds_bytes, stream>>>(arena, tasks, grids, p, tick_steps, init, state, records,
+                                                           best_xyz);
+    else if (ppl == 16)
+        tick_kernel<16><<<grid, block, lds_bytes, stream>>>(arena, tasks, grids, p, tick_steps, init, state, records,
+                                                            best_xyz);
     else
-        dock_kernel<32><<<n_chains, 64 * waves, lds, stream>>>(blob, blob_words, g, p, n_chains, n_steps, seed, records,
-                                                               best_xyz);
+        tick_kernel<32><<<grid, block, lds_bytes, stream>>>(arena, tasks, grids, p, tick_steps, init, state, records,
+                                                            best_xyz);
     return hipGetLastError();
 }
 
-hipError_t launch_rank(const float *records, const float4 *best_xyz, int n_chains, int n_atoms, int top_k,
+hipError_t launch_rank(const float *records, const float4 *best_xyz, const RankSeg *segs, int n_segs, int max_chains,
                        float rmsd_cut, int *sel, hipStream_t stream)
 {
-    const int threads = n_chains >= 1024 ? 1024 : ((n_chains + 63) / 64) * 64;
-    rank_kernel<<<1, threads < 64 ? 64 : threads, (size_t)n_chains, stream>>>(records, best_xyz, n_chains, n_atoms,
-                                                                              top_k, rmsd_cut, sel);
+    if (n_segs <= 0) return hipSuccess;
+    const int threads = max_chains >= 1024 ? 1024 : ((max_chains + 63) / 64) * 64;
+    rank_kernel<<<n_segs, threads < 64 ? 64 : threads, (size_t)max_chains, stream>>>(records, best_xyz, segs, rmsd_cut,
+                                                                                    sel);
     return hipGetLastError();
 }
 

@@ -1,0 +1,66 @@
+"""Batched docking (many uneven ligands in one graph-launched submission) gives,
+for every ligand, bitwise the result of docking that ligand alone; ticks of any
+length give the same result as one uninterrupted run."""
+import numpy as np
+import pytest
+
+from synth import make_config, make_ligand, PALETTE_T9
+from helpers import box32
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def site():
+    import gpu_common as gc
+    cfg = make_config(1)
+    rec, box = cfg["receptor"], box32(cfg["box"])
+    g = gc.GpuGrid(rec.xyz, rec.types, box, list(PALETTE_T9))
+    return g
+
+
+def ligands():
+    # pair-list sizes in every size class (<= 512, <= 1024, > 1024 pairs) and rigid/one-atom cases
+    shapes = [(10, 3), (20, 4), (32, 7), (45, 12), (60, 15), (64, 20), (12, 0), (1, 0), (28, 9)]
+    return [make_ligand(na, nt, seed=100 + k, palette=PALETTE_T9) for k, (na, nt) in enumerate(shapes)]
+
+
+def poses_bytes(poses):
+    return [bytes(p) for p in poses]
+
+
+@pytest.mark.parametrize("steps_per_tick", [0, 1, 7])
+def test_batch_equals_alone(site, steps_per_tick):
+    import gpu_common as gc
+    import paper_2303_09916_amd as D
+    g = site
+    torch = g.torch
+    ligs = ligands()
+    Ls = [D.Ligand.from_synth(l) for l in ligs]
+    n_chains, n_steps, top_k = 24, 12, 5
+    seeds = [1000 + 17 * k for k in range(len(ligs))]
+    info = [D.dsdp_ligand_info(L) for L in Ls]
+    assert max(i[0] for i in info) > 1024 and min(i[0] for i in info) <= 512
+    ws = gc.dev_bytes(torch, D.dsdp_dock_batch_workspace_bytes(Ls, n_chains))
+    res, st = D.dsdp_dock_batch(g.handle, Ls, n_chains, n_steps, seeds, top_k, ws, steps_per_tick=steps_per_tick)
+    total = 0
+    for k, (lig, L) in enumerate(zip(ligs, Ls)):
+        alone, _, _, st1 = gc.gpu_dock(g, lig, n_chains, n_steps, seeds[k], top_k)
+        assert poses_bytes(res[k]) == poses_bytes(alone), (k, lig.n_atoms)
+        total += st1.pose_evals
+    assert st.pose_evals == total
+    assert st.local_opts == len(ligs) * n_chains * n_steps
+
+
+def test_batch_mixed_wave_counts(site):
+    """Forcing 1 or 3 waves per chain in the batch changes nothing."""
+    import gpu_common as gc
+    import paper_2303_09916_amd as D
+    g = site
+    ligs = ligands()[:4]
+    Ls = [D.Ligand.from_synth(l) for l in ligs]
+    ws = gc.dev_bytes(g.torch, D.dsdp_dock_batch_workspace_bytes(Ls, 16))
+    a, _ = D.dsdp_dock_batch(g.handle, Ls, 16, 6, [5, 6, 7, 8], 4, ws, D.dsdp_params_default(waves_per_chain=1), 2)
+    b, _ = D.dsdp_dock_batch(g.handle, Ls, 16, 6, [5, 6, 7, 8], 4, ws, D.dsdp_params_default(waves_per_chain=3), 0)
+    for x, y in zip(a, b):
+        assert poses_bytes(x) == poses_bytes(y)
