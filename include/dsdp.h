@@ -42,6 +42,7 @@ typedef int32_t dsdp_status;
 #define DSDP_ERR_UNSUPPORTED (-2)          /* valid but beyond the limits below */
 #define DSDP_ERR_WORKSPACE_TOO_SMALL (-3)  /* a caller buffer is smaller than the query says */
 #define DSDP_ERR_DEVICE (-4)               /* HIP runtime error; message carries its text */
+#define DSDP_ERR_BUSY (-5)                 /* the request cannot be served now (scheduler) */
 
 #define DSDP_MAX_ATOMS 64                  /* ligand heavy atoms (one wavefront per chain) */
 #define DSDP_MAX_TORSIONS 31               /* rotatable bonds; fragments = torsions + 1 */
@@ -257,6 +258,89 @@ dsdp_status dsdp_dock_batch(dsdp_grids g, const dsdp_ligand *ligs, int32_t n_lig
                             const uint64_t *seeds, const dsdp_params *prm, int32_t top_k, int32_t steps_per_tick,
                             void *d_ws, size_t ws_bytes, void *stream, dsdp_pose *out, int32_t *n_out,
                             dsdp_dock_stats *stats);
+
+/* ------------------------------------------------------------------------ */
+/* Serving: continuous batching of docking requests in one device pool.      */
+/* ------------------------------------------------------------------------ */
+
+typedef struct dsdp_sched_s *dsdp_sched;
+
+#define DSDP_REQ_QUEUED 0
+#define DSDP_REQ_RUNNING 1
+#define DSDP_REQ_DONE 2
+#define DSDP_REQ_CANCELLED 3
+
+typedef struct {
+    int32_t queued, running;
+    int64_t completed;
+    int32_t resident_receptors, free_slots;
+    int64_t pool_bytes, pool_free;       /* device pool, and its part not holding maps or ligands */
+    int64_t map_builds, evictions, ticks;
+} dsdp_sched_info;
+
+/* Pool bytes the scheduler keeps for per-slot chain state and tables. */
+size_t dsdp_sched_fixed_bytes(int32_t slot_capacity);
+
+/*
+ * Scheduler over one caller-owned device pool (d_pool, pool_bytes, 256-byte
+ * aligned; it must stay allocated until dsdp_sched_destroy).  The pool holds
+ * dsdp_sched_fixed_bytes(slot_capacity) of tables; the rest holds receptor maps
+ * and ligand descriptions.  slot_capacity = chains that can run at once;
+ * steps_per_tick = MC steps every running chain advances per dsdp_sched_tick.
+ * prm nullable (defaults), applies to every request.  Not thread-safe: one
+ * thread drives a scheduler.  This is the paper's many-copies search (Section 2,
+ * parallelisation paragraph) run for a stream of requests.
+ */
+dsdp_status dsdp_sched_create(void *d_pool, size_t pool_bytes, int32_t slot_capacity, int32_t steps_per_tick,
+                              const dsdp_params *prm, void *stream, dsdp_sched *out);
+void dsdp_sched_destroy(dsdp_sched s);
+
+/*
+ * Register a receptor and its box/map types (host arrays copied).  Its maps are
+ * built into the pool when a request needs them and may be evicted, least
+ * recently used first, when memory is needed and no running request uses them.
+ * DSDP_ERR_WORKSPACE_TOO_SMALL when its maps could never fit in the pool.
+ */
+dsdp_status dsdp_sched_add_receptor(dsdp_sched s, const dsdp_atom *rec, int32_t n_rec, const dsdp_box *box,
+                                    const int32_t *types, int32_t n_types, int32_t *receptor_id);
+
+/*
+ * Queue a dock request (as dsdp_dock with the scheduler's parameters).  The ligand
+ * is validated and copied now.  Admission happens in dsdp_sched_tick, in arrival
+ * order, as soon as n_chains slots, arena space and the receptor's maps fit.
+ */
+dsdp_status dsdp_sched_submit(dsdp_sched s, int32_t receptor_id, const dsdp_ligand *lig, int32_t n_chains,
+                              int32_t n_steps, uint64_t seed, int32_t top_k, int64_t *ticket);
+
+/* Cancel a queued or running request (takes effect at the next tick). */
+dsdp_status dsdp_sched_cancel(dsdp_sched s, int64_t ticket);
+
+/*
+ * One scheduling round: admit what fits, advance every running chain by
+ * steps_per_tick steps (all requests share the launches), rank the requests
+ * that finished.  Synchronous; *n_completed = requests finished in this round.
+ */
+dsdp_status dsdp_sched_tick(dsdp_sched s, int32_t *n_completed);
+
+/*
+ * State of a request (DSDP_REQ_*).  When done: out host [top_k] ranked poses,
+ * *n_out, stats; times (nullable) host [3] = submit, admit, done in seconds on
+ * the scheduler's clock.
+ */
+dsdp_status dsdp_sched_poll(dsdp_sched s, int64_t ticket, int32_t *state, dsdp_pose *out, int32_t *n_out,
+                            double *times, dsdp_dock_stats *stats);
+
+/*
+ * Tickets of requests that finished (done or cancelled) since the previous call,
+ * in the order they finished: up to cap into tickets (host), count in *n; the
+ * rest stay for the next call.
+ */
+dsdp_status dsdp_sched_drain(dsdp_sched s, int64_t *tickets, int32_t cap, int32_t *n);
+
+/* Forget a finished or cancelled request. */
+dsdp_status dsdp_sched_release(dsdp_sched s, int64_t ticket);
+
+dsdp_status dsdp_sched_get_info(dsdp_sched s, dsdp_sched_info *info);
 
 #ifdef __cplusplus
 }

@@ -22,6 +22,8 @@ DSDP_ERR_INVALID_ARG = -1
 DSDP_ERR_UNSUPPORTED = -2
 DSDP_ERR_WORKSPACE_TOO_SMALL = -3
 DSDP_ERR_DEVICE = -4
+DSDP_ERR_BUSY = -5
+DSDP_REQ_QUEUED, DSDP_REQ_RUNNING, DSDP_REQ_DONE, DSDP_REQ_CANCELLED = 0, 1, 2, 3
 MAX_ATOMS = 64
 MAX_TORSIONS = 31
 N_XS = 17
@@ -65,6 +67,12 @@ class dsdp_dock_stats(C.Structure):
                 ("n_nonfinite", C.c_int32), ("kernel_ms", C.c_float), ("search_ms", C.c_float)]
 
 
+class dsdp_sched_info(C.Structure):
+    _fields_ = [("queued", C.c_int32), ("running", C.c_int32), ("completed", C.c_int64),
+                ("resident_receptors", C.c_int32), ("free_slots", C.c_int32), ("pool_bytes", C.c_int64),
+                ("pool_free", C.c_int64), ("map_builds", C.c_int64), ("evictions", C.c_int64), ("ticks", C.c_int64)]
+
+
 _vp = C.c_void_p
 _SIGS = {
     "dsdp_last_error": (C.c_char_p, []),
@@ -91,6 +99,21 @@ _SIGS = {
                                     C.POINTER(C.c_uint64), C.POINTER(dsdp_params), C.c_int32, C.c_int32, _vp,
                                     C.c_size_t, _vp, C.POINTER(dsdp_pose), C.POINTER(C.c_int32),
                                     C.POINTER(dsdp_dock_stats)]),
+    "dsdp_sched_fixed_bytes": (C.c_size_t, [C.c_int32]),
+    "dsdp_sched_create": (C.c_int32, [_vp, C.c_size_t, C.c_int32, C.c_int32, C.POINTER(dsdp_params), _vp,
+                                      C.POINTER(_vp)]),
+    "dsdp_sched_destroy": (None, [_vp]),
+    "dsdp_sched_add_receptor": (C.c_int32, [_vp, C.POINTER(dsdp_atom), C.c_int32, C.POINTER(dsdp_box),
+                                            C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32)]),
+    "dsdp_sched_submit": (C.c_int32, [_vp, C.c_int32, C.POINTER(dsdp_ligand), C.c_int32, C.c_int32, C.c_uint64,
+                                      C.c_int32, C.POINTER(C.c_int64)]),
+    "dsdp_sched_cancel": (C.c_int32, [_vp, C.c_int64]),
+    "dsdp_sched_tick": (C.c_int32, [_vp, C.POINTER(C.c_int32)]),
+    "dsdp_sched_poll": (C.c_int32, [_vp, C.c_int64, C.POINTER(C.c_int32), C.POINTER(dsdp_pose),
+                                    C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(dsdp_dock_stats)]),
+    "dsdp_sched_drain": (C.c_int32, [_vp, C.POINTER(C.c_int64), C.c_int32, C.POINTER(C.c_int32)]),
+    "dsdp_sched_release": (C.c_int32, [_vp, C.c_int64]),
+    "dsdp_sched_get_info": (C.c_int32, [_vp, C.POINTER(dsdp_sched_info)]),
 }
 EXPORTED = tuple(_SIGS)
 
@@ -304,3 +327,79 @@ def dsdp_dock_batch(grids, ligs, n_chains, n_steps, seeds, top_k, d_ws, params=N
                                  _ptr(d_ws), _nbytes(d_ws), _stream(stream), out, n_out, C.byref(stats)))
     res = [[out[l * top_k + q] for q in range(n_out[l])] for l in range(n)]
     return res, stats
+
+
+# ---------------------------------------------------------------- serving scheduler
+
+def dsdp_sched_fixed_bytes(slot_capacity):
+    return int(lib().dsdp_sched_fixed_bytes(int(slot_capacity)))
+
+
+def dsdp_sched_create(d_pool, slot_capacity, steps_per_tick, params=None, stream=None):
+    h = C.c_void_p()
+    _check(lib().dsdp_sched_create(_ptr(d_pool), _nbytes(d_pool), int(slot_capacity), int(steps_per_tick),
+                                   C.byref(params) if params is not None else None, _stream(stream), C.byref(h)))
+    return h
+
+
+def dsdp_sched_destroy(h):
+    lib().dsdp_sched_destroy(h)
+
+
+def dsdp_sched_add_receptor(h, rec_xyz, rec_types, box, types):
+    atoms = atoms_array(rec_xyz, rec_types)
+    tarr = np.ascontiguousarray(types, dtype=np.int32)
+    rid = C.c_int32()
+    _check(lib().dsdp_sched_add_receptor(h, atoms, int(np.asarray(rec_types).size), C.byref(_box(box)),
+                                         tarr.ctypes.data_as(C.POINTER(C.c_int32)), len(tarr), C.byref(rid)))
+    return rid.value
+
+
+def dsdp_sched_submit(h, receptor_id, lig, n_chains, n_steps, seed, top_k):
+    t = C.c_int64()
+    _check(lib().dsdp_sched_submit(h, int(receptor_id), C.byref(lig.c), int(n_chains), int(n_steps),
+                                   C.c_uint64(int(seed)), int(top_k), C.byref(t)))
+    return t.value
+
+
+def dsdp_sched_cancel(h, ticket):
+    _check(lib().dsdp_sched_cancel(h, C.c_int64(int(ticket))))
+
+
+def dsdp_sched_tick(h):
+    n = C.c_int32()
+    _check(lib().dsdp_sched_tick(h, C.byref(n)))
+    return n.value
+
+
+def dsdp_sched_poll(h, ticket, top_k):
+    """(state, poses, times[submit, admit, done], stats)"""
+    st = C.c_int32()
+    out = (dsdp_pose * max(top_k, 1))()
+    n = C.c_int32()
+    times = (C.c_double * 3)()
+    stats = dsdp_dock_stats()
+    _check(lib().dsdp_sched_poll(h, C.c_int64(int(ticket)), C.byref(st), out, C.byref(n), times, C.byref(stats)))
+    return st.value, list(out)[:n.value], list(times), stats
+
+
+def dsdp_sched_drain(h, cap=4096):
+    """Tickets finished (done or cancelled) since the previous drain."""
+    buf = (C.c_int64 * cap)()
+    out = []
+    while True:
+        n = C.c_int32()
+        _check(lib().dsdp_sched_drain(h, buf, cap, C.byref(n)))
+        out.extend(buf[:n.value])
+        if n.value < cap:
+            return out
+
+
+def dsdp_sched_release(h, ticket):
+    _check(lib().dsdp_sched_release(h, C.c_int64(int(ticket))))
+
+
+def dsdp_sched_get_info(h):
+    info = dsdp_sched_info()
+    _check(lib().dsdp_sched_get_info(h, C.byref(info)))
+    return info

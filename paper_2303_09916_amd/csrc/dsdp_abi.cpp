@@ -7,6 +7,7 @@
 // the ranked chain results into output poses.
 #include "../../include/dsdp.h"
 #include "dsdp_internal.h"
+#include "dsdp_host.h"
 
 #include <hip/hip_runtime.h>
 
@@ -20,14 +21,8 @@
 
 using namespace dsdp;
 
-struct dsdp_grids_s {
-    GridView view;
-    dsdp_box box;
-    int types[kNXS];
-    size_t bytes;
-};
-
-namespace {
+namespace dsdp {
+namespace host {
 
 thread_local std::string g_error;
 
@@ -47,13 +42,6 @@ dsdp_status hip_fail(hipError_t e, const char *where)
     return fail(DSDP_ERR_DEVICE, "%s: %s", where, hipGetErrorString(e));
 }
 
-#define HIP_TRY(expr, where)                   \
-    do {                                       \
-        hipError_t e_ = (expr);                \
-        if (e_ != hipSuccess) return hip_fail(e_, where); \
-    } while (0)
-
-constexpr size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 bool finite3(float a, float b, float c) { return std::isfinite(a) && std::isfinite(b) && std::isfinite(c); }
 
@@ -99,11 +87,6 @@ CellGeom cell_geometry(const int n[3], const double origin[3], double h)
 
 // ---------------------------------------------------------------- ligand preparation
 
-struct Prepared {
-    LigHeader h;
-    std::vector<uint32_t> blob;
-    std::vector<int> map_index;   // per atom
-};
 
 dsdp_status validate_ligand(const dsdp_ligand *lig)
 {
@@ -493,7 +476,10 @@ void add_stats(const float *rec, long n, dsdp_dock_stats *stats)
     }
 }
 
-}  // namespace
+}  // namespace host
+}  // namespace dsdp
+
+using namespace dsdp::host;
 
 extern "C" {
 
@@ -762,6 +748,7 @@ dsdp_status dsdp_dock(dsdp_grids g, const dsdp_ligand *lig, int32_t n_chains, in
         t.seed_hi = (uint32_t)(seed >> 32);
         t.grid = 0;
         t.slot = c;
+        t.fresh = 1;
     }
     *img.at<GridView>(w.grids) = g->view;
     RankSeg *seg = img.at<RankSeg>(w.segs);
@@ -932,6 +919,7 @@ dsdp_status dsdp_dock_batch(dsdp_grids g, const dsdp_ligand *ligs, int32_t n_lig
             t.seed_hi = (uint32_t)(seeds[l] >> 32);
             t.grid = 0;
             t.slot = (int)((long)l * n_chains + c);
+            t.fresh = 0;
         }
     *img.at<GridView>(w.grids) = g->view;
     RankSeg *segs = img.at<RankSeg>(w.segs);

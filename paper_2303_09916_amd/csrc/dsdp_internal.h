@@ -95,6 +95,8 @@ struct ChainTask {
     uint32_t seed_lo, seed_hi;
     int32_t grid;            // index into the GridView array
     int32_t slot;            // index of the chain's state, record and best coordinates
+    int32_t fresh;           // 1: start the chain from its initial pose in this launch
+    int32_t pad[3];
 };
 
 // Resumable chain state in device memory (words): a chain advanced in several

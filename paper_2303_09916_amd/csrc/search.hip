@@ -867,7 +867,7 @@ __global__ __launch_bounds__(256) void tick_kernel(const uint32_t *arena, const 
 
     Energy Ex, Eb;
     int step, evals, accepted, lopts;
-    if (init) {
+    if (init || t.fresh) {
         if (w == 0) {
             const int nw = 6 + L.nt;
             if (lane < nw) {

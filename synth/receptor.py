@@ -57,44 +57,78 @@ def _draw_types(elems, rng):
     return out
 
 
-def _rsa(n, radius, dmin, pocket, pocket_r, rng, max_fail):
-    """Random sequential addition; returns (n,3) positions or None when jammed."""
-    cell = dmin
-    grid = {}
-    pts = np.empty((n, 3))
+def _rsa(n, radius, dmin, pocket, pocket_r, rng, max_fail, batch=512):
+    """Random sequential addition; returns (n,3) positions or None when jammed.
+
+    Candidates are drawn uniformly in the bounding cube and taken in draw order:
+    one outside the sphere or inside the pocket is skipped, one closer than dmin
+    to a placed atom is a failure (max_fail failures in a row: jammed), any
+    other is placed.  Candidates are drawn and tested against the atoms placed
+    before their batch in vectorised form, then against the batch's own
+    earlier placements one by one, which decides exactly as a one-at-a-time
+    loop over the same draws."""
     d2 = dmin * dmin
+    cell = dmin
+    G = int(np.ceil(2.0 * radius / cell)) + 3
+    S = 8                                   # slots per cell (a cell of side dmin holds far fewer)
+    occ = np.full((G, G, G, S), -1, dtype=np.int64)
+    cnt = np.zeros((G, G, G), dtype=np.int64)
+    pts = np.empty((n, 3))
+    off = np.array([(dx, dy, dz) for dx in (-1, 0, 1) for dy in (-1, 0, 1) for dz in (-1, 0, 1)])
     placed = 0
     fails = 0
+    empty = 0
+    r2 = radius * radius
     while placed < n:
-        p = rng.uniform(-radius, radius, size=3)
-        if p @ p > radius * radius:
+        P = rng.uniform(-radius, radius, size=(batch, 3))
+        keep = np.einsum("ij,ij->i", P, P) <= r2
+        if pocket is not None:
+            keep &= np.sum((P - pocket) ** 2, axis=1) >= pocket_r * pocket_r
+        P = P[keep]
+        if len(P) == 0:
+            empty += 1
+            if empty > 1000:
+                raise ValueError("the pocket leaves no room in the sphere")
             continue
-        if pocket is not None and np.sum((p - pocket) ** 2) < pocket_r * pocket_r:
-            continue
-        key = tuple(np.floor(p / cell).astype(int))
-        ok = True
-        for dx in (-1, 0, 1):
-            for dy in (-1, 0, 1):
-                for dz in (-1, 0, 1):
-                    for q in grid.get((key[0] + dx, key[1] + dy, key[2] + dz), ()):
-                        if np.sum((pts[q] - p) ** 2) < d2:
-                            ok = False
-                            break
-                    if not ok:
-                        break
-                if not ok:
-                    break
-            if not ok:
-                break
-        if not ok:
-            fails += 1
-            if fails > max_fail:
-                return None
-            continue
-        fails = 0
-        pts[placed] = p
-        grid.setdefault(key, []).append(placed)
-        placed += 1
+        empty = 0
+        K = np.floor((P + radius) / cell).astype(np.int64) + 1
+        nb = K[:, None, :] + off[None, :, :]                     # (k, 27, 3)
+        idx = occ[nb[..., 0], nb[..., 1], nb[..., 2]].reshape(len(P), -1)
+        valid = idx >= 0
+        q = pts[np.where(valid, idx, 0)]
+        dd = np.sum((q - P[:, None, :]) ** 2, axis=2)
+        clash = np.any(valid & (dd < d2), axis=1)
+        # in-batch conflicts among the candidates clear of earlier atoms
+        cand = np.flatnonzero(~clash)
+        ok = np.zeros(len(P), dtype=bool)
+        if len(cand):
+            C = P[cand]
+            conf = np.sum((C[:, None, :] - C[None, :, :]) ** 2, axis=2) < d2
+            taken = np.zeros(len(cand), dtype=bool)
+            for a in range(len(cand)):
+                if not np.any(conf[a, :a] & taken[:a]):
+                    taken[a] = True
+            ok[cand[taken]] = True
+        # walk the decisions in draw order: stop at n atoms, or when max_fail
+        # failures come in a row (jammed)
+        tpos = np.flatnonzero(ok)
+        need = n - placed
+        cut = int(tpos[need - 1]) if len(tpos) >= need else len(P) - 1
+        tpos = tpos[:need]
+        runs = np.diff(np.concatenate(([-1 - fails], tpos))) - 1 if len(tpos) else np.array([fails + cut + 1])
+        tail = cut - int(tpos[-1]) if len(tpos) else 0
+        if np.any(runs > max_fail) or (len(tpos) and tail > max_fail):
+            return None
+        fails = (tail if len(tpos) else int(runs[0]))
+        for i in tpos.tolist():
+            kx, ky, kz = K[i].tolist()
+            c = int(cnt[kx, ky, kz])
+            if c >= S:
+                raise RuntimeError("cell overflow in random sequential addition")
+            occ[kx, ky, kz, c] = placed
+            cnt[kx, ky, kz] = c + 1
+            pts[placed] = P[i]
+            placed += 1
     return pts
 
 

@@ -103,3 +103,60 @@ def test_ligand_validation():
     too_big = D.Ligand(xyz, np.concatenate([big.types, big.types[:1]]), np.array([0, 65]), np.array([-1]),
                        np.array([[-1, -1]]), big.bonds)
     assert D.dsdp_dock_workspace_bytes(too_big, 32) == 0
+
+
+def test_scheduler_host_logic():
+    """Scheduler calls that touch no device memory: validation, queueing, cancel, release."""
+    cfg = make_config(1)
+    rec, box = cfg["receptor"], cfg["box"]
+    cap = 64
+    fixed = D.dsdp_sched_fixed_bytes(cap)
+    assert fixed > 0 and fixed % 256 == 0 and D.dsdp_sched_fixed_bytes(0) == 0
+    maps = D.dsdp_grids_bytes(box, 4) + D.dsdp_build_grids_workspace_bytes(rec.n, box)
+    for pool, c, spt, code in ((FakeDev(fixed - 1), cap, 4, D.DSDP_ERR_WORKSPACE_TOO_SMALL),
+                               (FakeDev(fixed), 0, 4, D.DSDP_ERR_INVALID_ARG),
+                               (FakeDev(fixed), cap, 0, D.DSDP_ERR_INVALID_ARG),
+                               (FakeDev(1 << 35), cap, 4, D.DSDP_ERR_UNSUPPORTED)):
+        with pytest.raises(D.DsdpError) as e:
+            D.dsdp_sched_create(pool, c, spt)
+        assert e.value.status == code
+    # a pool too small for this receptor's maps rejects it up front
+    h = D.dsdp_sched_create(FakeDev(fixed + 4096), cap, 4)
+    with pytest.raises(D.DsdpError) as e:
+        D.dsdp_sched_add_receptor(h, rec.xyz, rec.types, box, cfg["map_types"])
+    assert e.value.status == D.DSDP_ERR_WORKSPACE_TOO_SMALL
+    D.dsdp_sched_destroy(h)
+
+    h = D.dsdp_sched_create(FakeDev(fixed + 2 * maps + (1 << 20)), cap, 4)
+    rid = D.dsdp_sched_add_receptor(h, rec.xyz, rec.types, box, cfg["map_types"])
+    assert rid == 0
+    L = D.Ligand.from_synth(cfg["ligands"][0])
+    for args, code in (((7, L, 8, 10, 1, 3), D.DSDP_ERR_INVALID_ARG),
+                       ((rid, L, cap + 1, 10, 1, 3), D.DSDP_ERR_INVALID_ARG),
+                       ((rid, L, 8, -1, 1, 3), D.DSDP_ERR_INVALID_ARG),
+                       ((rid, L, 8, 10, 1, 9), D.DSDP_ERR_INVALID_ARG)):
+        with pytest.raises(D.DsdpError) as e:
+            D.dsdp_sched_submit(h, *args)
+        assert e.value.status == code, args
+    t1 = D.dsdp_sched_submit(h, rid, L, 8, 10, 1, 3)
+    t2 = D.dsdp_sched_submit(h, rid, L, 16, 10, 2, 3)
+    assert t2 > t1
+    info = D.dsdp_sched_get_info(h)
+    assert (info.queued, info.running, info.free_slots, info.resident_receptors) == (2, 0, cap, 0)
+    state, poses, times, _ = D.dsdp_sched_poll(h, t1, 3)
+    assert state == D.DSDP_REQ_QUEUED and poses == [] and times[0] >= 0.0
+    with pytest.raises(D.DsdpError) as e:
+        D.dsdp_sched_release(h, t1)
+    assert e.value.status == D.DSDP_ERR_BUSY
+    D.dsdp_sched_cancel(h, t1)
+    D.dsdp_sched_cancel(h, t2)
+    assert D.dsdp_sched_tick(h) == 0          # only cancelled work: nothing reaches the device
+    assert D.dsdp_sched_drain(h, cap=1) == [t1, t2] and D.dsdp_sched_drain(h) == []
+    for t in (t1, t2):
+        assert D.dsdp_sched_poll(h, t, 3)[0] == D.DSDP_REQ_CANCELLED
+        D.dsdp_sched_release(h, t)
+    with pytest.raises(D.DsdpError):
+        D.dsdp_sched_poll(h, t1, 3)
+    info = D.dsdp_sched_get_info(h)
+    assert (info.queued, info.running, info.ticks, info.completed) == (0, 0, 0, 0)
+    D.dsdp_sched_destroy(h)
