@@ -17,7 +17,16 @@ Printed JSON line (one):
                its average device time (HIP events on the call's stream), vs the
                MI355X FP32 vector peak; also its gather bytes per second;
   cpu_baseline the FP64 oracle on a bounded sample of the same workload, timed
-               on this host's cores (OpenMP over chains).
+               on this host's cores (OpenMP over chains);
+  batched      the batched workload (one receptor, uneven ligands of 10-60 atoms
+               and 0-15 rotatable bonds, 128 chains x 1000 steps each): ligands/s
+               of one dsdp_dock_batch call over all of them against ligands/s of
+               plain per-ligand dsdp_dock calls on a sample of the same ligands;
+  served       the served workload (16 receptors, Poisson arrivals, one ligand
+               per request, 128 chains x 1000 steps): the serving scheduler fed
+               at the workload's 200 requests/s (saturation throughput, whether
+               the queue was stable) and at a rate below saturation; p50/p99
+               latency from scheduled arrival to result.
 """
 import argparse
 import json
@@ -92,6 +101,182 @@ def cpu_baseline(cfg, cpu_steps):
             "cpu_model": cpu_model(), "nproc": os.cpu_count()}
 
 
+def make_inputs(args):
+    """Every synthetic input, built before the GPU is touched (a fork pool
+    over the independent ligand and receptor builds)."""
+    import multiprocessing as mp
+    from synth import make_config, request_ligand_job
+    t0 = time.time()
+    workers = max(1, min(16, os.cpu_count() or 1))
+    inp = {"cfg2": make_config(2)}
+    with mp.get_context("fork").Pool(workers) as pool:
+        if args.batch_ligands > 0:
+            inp["cfg4"] = make_config(4, n_ligands=args.batch_ligands, pmap=pool.map)
+        n_req = args.serve_requests + args.serve_requests_below
+        if n_req > 0:
+            c5 = make_config(5, n_ligands=n_req, pmap=pool.map)
+            c5["request_ligands"] = pool.map(request_ligand_job, [(c5["shapes"][k], k) for k in range(n_req)])
+            inp["cfg5"] = c5
+    print(f"[bench] inputs built in {time.time() - t0:.1f}s with {workers} processes", file=sys.stderr, flush=True)
+    return inp
+
+
+def batch_leg(D, torch, cfg, n_plain):
+    """Batched workload: one dsdp_dock_batch over every ligand vs plain dsdp_dock
+    calls, one ligand at a time, over the first n_plain of the same ligands."""
+    rec, box, types = cfg["receptor"], cfg["box"], cfg["map_types"]
+    n_chains, n_steps, top_k = cfg["n_chains"], cfg["n_steps"], cfg["top_k"]
+    ligs = cfg["ligands"]
+    Ls = [D.Ligand.from_synth(l) for l in ligs]
+    seeds = [cfg["seed"] * 1000003 + 1 + i for i in range(len(Ls))]
+    maps = torch.empty(D.dsdp_grids_bytes(box, len(types)), dtype=torch.uint8, device="cuda")
+    gws = torch.empty(D.dsdp_build_grids_workspace_bytes(rec.n, box), dtype=torch.uint8, device="cuda")
+    g = D.dsdp_build_grids(rec.xyz, rec.types, box, types, maps, gws)
+    torch.cuda.synchronize()
+    del gws
+    n_plain = min(n_plain, len(Ls))
+    plain_ws = torch.empty(max(D.dsdp_dock_workspace_bytes(L, n_chains) for L in Ls[:max(n_plain, 1)]),
+                           dtype=torch.uint8, device="cuda")
+    # warm-up (code objects, first-launch costs) on a short run
+    D.dsdp_dock(g, Ls[0], n_chains, 2, seeds[0], top_k, plain_ws, want_xyz=False)
+    small = Ls[:4]
+    sws = torch.empty(D.dsdp_dock_batch_workspace_bytes(small, n_chains), dtype=torch.uint8, device="cuda")
+    D.dsdp_dock_batch(g, small, n_chains, 2, seeds[:4], top_k, sws)
+    del sws
+    torch.cuda.synchronize()
+
+    plain_res, plain_evals = [], 0
+    t0 = time.perf_counter()
+    for i in range(n_plain):
+        poses, _, _, st = D.dsdp_dock(g, Ls[i], n_chains, n_steps, seeds[i], top_k, plain_ws, want_xyz=False)
+        plain_res.append(poses)
+        plain_evals += st.pose_evals
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    del plain_ws
+    print(f"[bench] batched workload: plain {n_plain} ligands in {t_plain:.2f}s", file=sys.stderr, flush=True)
+
+    bws = torch.empty(D.dsdp_dock_batch_workspace_bytes(Ls, n_chains), dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res, st = D.dsdp_dock_batch(g, Ls, n_chains, n_steps, seeds, top_k, bws)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    D.dsdp_grids_release(g)
+    print(f"[bench] batched workload: one batch of {len(Ls)} ligands in {t_batch:.2f}s", file=sys.stderr, flush=True)
+    same = all([bytes(p) for p in res[i]] == [bytes(p) for p in plain_res[i]] for i in range(n_plain))
+    atoms = np.array([l.n_atoms for l in ligs])
+    tors = np.array([l.n_torsions for l in ligs])
+    return {
+        "workload": (f"one {rec.n}-atom receptor, 30 A box ({len(types)} maps), {len(Ls)} ligands of "
+                     f"{atoms.min()}-{atoms.max()} atoms (mean {atoms.mean():.1f}) and {tors.min()}-{tors.max()} "
+                     f"rotatable bonds, {n_chains} chains x {n_steps} MC steps each, top {top_k}"),
+        "ligands": len(Ls),
+        "ligands_per_s": len(Ls) / t_batch,
+        "pose_evals_per_s": st.pose_evals / t_batch,
+        "batch_s": t_batch,
+        "search_ms": st.search_ms,
+        "plain_sample": n_plain,
+        "plain_ligands_per_s": n_plain / t_plain if n_plain else None,
+        "plain_pose_evals_per_s": plain_evals / t_plain if n_plain else None,
+        "speedup_vs_plain": (len(Ls) / t_batch) / (n_plain / t_plain) if n_plain else None,
+        "batch_equals_plain_bitwise": bool(same),
+    }
+
+
+def serve_leg(D, torch, cfg, first, count, rate, slots, spt, label):
+    """Feed requests first..first+count of the served workload to the scheduler
+    at `rate` requests/s (the workload's Poisson gaps rescaled), ticking
+    whenever work is in flight; latency = result time - scheduled arrival."""
+    n_chains, n_steps, top_k = cfg["n_chains"], cfg["n_steps"], cfg["top_k"]
+    types = cfg["map_types"]
+    recs, boxes = cfg["receptors"], cfg["boxes"]
+    arr = np.asarray(cfg["arrivals"][first:first + count], dtype=np.float64)
+    arr = (arr - arr[0]) * (200.0 / rate)
+    Ls = [D.Ligand.from_synth(l) for l in cfg["request_ligands"][first:first + count]]
+    target = [int(t) for t in cfg["target"][first:first + count]]
+    maps = sum(D.dsdp_grids_bytes(b, len(types)) + 256 for b in boxes)
+    wsb = max(D.dsdp_build_grids_workspace_bytes(r.n, b) for r, b in zip(recs, boxes))
+    pool_bytes = D.dsdp_sched_fixed_bytes(slots) + maps + wsb + (64 << 20)
+    pool = torch.empty(pool_bytes, dtype=torch.uint8, device="cuda")
+    h = D.dsdp_sched_create(pool, slots, spt)
+    try:
+        rids = [D.dsdp_sched_add_receptor(h, r.xyz, r.types, b, types) for r, b in zip(recs, boxes)]
+        # make every receptor resident (one short request each), untimed
+        warm = [D.dsdp_sched_submit(h, rids[k], Ls[0], 8, 1, k, 1) for k in range(len(rids))]
+        while D.dsdp_sched_get_info(h).running + D.dsdp_sched_get_info(h).queued:
+            D.dsdp_sched_tick(h)
+        for t in warm:
+            D.dsdp_sched_release(h, t)
+        D.dsdp_sched_drain(h)
+        info0 = D.dsdp_sched_get_info(h)
+
+        lat = np.zeros(count)
+        t_done = []
+        owner = {}
+        nxt = done = ticks = 0
+        max_queued = 0
+        queued_at_last_arrival = None
+        t0 = time.perf_counter()
+        while done < count:
+            now = time.perf_counter() - t0
+            while nxt < count and arr[nxt] <= now:
+                t = D.dsdp_sched_submit(h, rids[target[nxt]], Ls[nxt], n_chains, n_steps, 1 + first + nxt, top_k)
+                owner[t] = nxt
+                nxt += 1
+            info = D.dsdp_sched_get_info(h)
+            max_queued = max(max_queued, info.queued)
+            if nxt == count and queued_at_last_arrival is None:
+                queued_at_last_arrival = info.queued
+            if info.running + info.queued == 0:
+                if nxt < count:
+                    time.sleep(max(0.0, min(arr[nxt] - now, 0.01)))
+                continue
+            D.dsdp_sched_tick(h)
+            ticks += 1
+            t_now = time.perf_counter() - t0
+            for t in D.dsdp_sched_drain(h):
+                k = owner.pop(t)
+                lat[k] = t_now - arr[k]
+                t_done.append(t_now)
+                D.dsdp_sched_release(h, t)
+                done += 1
+        elapsed = time.perf_counter() - t0
+        info = D.dsdp_sched_get_info(h)
+    finally:
+        D.dsdp_sched_destroy(h)
+    thr = count / elapsed
+    half = count // 2
+    # steady state: completions between the 10th and 90th percentile of the run
+    td = np.sort(np.asarray(t_done))
+    a, b = int(0.1 * count), int(0.9 * count) - 1
+    steady = (b - a) / (td[b] - td[a]) if b > a and td[b] > td[a] else None
+    p50a = float(np.percentile(lat[:half], 50)) if half else None
+    p50b = float(np.percentile(lat[half:], 50)) if half else None
+    out = {
+        "offered_rate": rate,
+        "requests": count,
+        "ligands_per_s": thr,
+        "steady_ligands_per_s": steady,
+        "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                      "p50_first_half": p50a, "p50_second_half": p50b},
+        # a stable queue keeps latency flat over the run; an overloaded one grows it
+        "queue_stable": bool(half and p50b <= 1.5 * p50a),
+        "elapsed_s": elapsed,
+        "slot_capacity": slots,
+        "steps_per_tick": spt,
+        "ticks": ticks,
+        "max_queued": max_queued,
+        "queued_at_last_arrival": queued_at_last_arrival,
+        "map_builds": info.map_builds - info0.map_builds,
+        "pool_bytes": pool_bytes,
+    }
+    print(f"[bench] served ({label}): {count} requests at {rate:.1f}/s -> {thr:.1f}/s, p50 "
+          f"{out['latency_s']['p50']:.2f}s p99 {out['latency_s']['p99']:.2f}s, max queue {max_queued}",
+          file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +285,15 @@ def main():
     ap.add_argument("--mc-steps", type=int, default=2000, help="MC steps per chain (2000 = the workload)")
     ap.add_argument("--cpu-steps", type=int, default=200, help="MC steps per chain of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-ligands", type=int, default=512, help="ligands of the batched workload (0: skip)")
+    ap.add_argument("--plain-sample", type=int, default=24, help="of these, docked one at a time for comparison")
+    ap.add_argument("--serve-requests", type=int, default=480,
+                    help="requests fed at the served workload's 200/s (0: skip the served legs)")
+    ap.add_argument("--serve-requests-below", type=int, default=240,
+                    help="requests fed at --serve-below x the measured saturation throughput")
+    ap.add_argument("--serve-below", type=float, default=0.7)
+    ap.add_argument("--serve-slots", type=int, default=8192, help="scheduler chain slots")
+    ap.add_argument("--serve-steps-per-tick", type=int, default=50)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one plain device copy of this size (for counter calibration)")
     args = ap.parse_args()
@@ -109,20 +303,18 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    inp = make_inputs(args)
     import torch
     import paper_2303_09916_amd as D
-    from synth import make_config
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    t_setup = time.time()
-    cfg = make_config(2)
+    cfg = inp["cfg2"]
     rec, box, lig = cfg["receptor"], cfg["box"], cfg["ligands"][0]
     n_chains, n_steps, top_k, seed = cfg["n_chains"], args.mc_steps, cfg["top_k"], cfg["seed"]
     types = cfg["map_types"]
-    print(f"[bench] setup: receptor {rec.n} atoms (R={rec.radius:.1f} A), ligand {lig.n_atoms} atoms / "
-          f"{lig.n_torsions} torsions, {n_chains} chains x {n_steps} steps ({time.time() - t_setup:.1f}s)",
-          file=sys.stderr, flush=True)
+    print(f"[bench] receptor {rec.n} atoms (R={rec.radius:.1f} A), ligand {lig.n_atoms} atoms / "
+          f"{lig.n_torsions} torsions, {n_chains} chains x {n_steps} steps", file=sys.stderr, flush=True)
 
     maps = torch.empty(D.dsdp_grids_bytes(box, len(types)), dtype=torch.uint8, device="cuda")
     gws = torch.empty(D.dsdp_build_grids_workspace_bytes(rec.n, box), dtype=torch.uint8, device="cuda")
@@ -167,11 +359,11 @@ def main():
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    del maps, gws, dws
 
     value = evals / elapsed
     evals_per_launch = evals / args.steps
     avg_search_s = float(np.mean(search_ms)) * 1e-3
-    iters_per_lopt = None
     # evaluations per BFGS iteration: each local optimisation makes one start
     # evaluation plus at most bfgs_iters line searches
     evals_per_lopt = stats.pose_evals / max(stats.local_opts, 1)
@@ -206,7 +398,7 @@ def main():
         "evals_per_step": evals_per_launch,
         "best_e_total": best,
         "roofline": {
-            "kernel": "dock_kernel",
+            "kernel": "tick_kernel",
             "bound": "alu",
             "achieved": achieved,
             "peak": FP32_PEAK_TFLOPS,
@@ -219,7 +411,31 @@ def main():
             "gather_frac_of_hbm": gather_gbps / HBM_PEAK_GBPS,
         },
         "cpu_baseline": None,
+        "batched": None,
+        "served": None,
     }
+
+    if "cfg4" in inp:
+        out["batched"] = batch_leg(D, torch, inp["cfg4"], args.plain_sample)
+    if "cfg5" in inp:
+        c5 = inp["cfg5"]
+        served = {"workload": (f"16 receptors of {min(r.n for r in c5['receptors'])}-"
+                               f"{max(r.n for r in c5['receptors'])} atoms, 22-30 A boxes (9 maps, all resident), "
+                               f"Poisson arrivals, one ligand of 10-60 atoms and 0-15 rotatable bonds per request "
+                               f"against a random receptor, {c5['n_chains']} chains x {c5['n_steps']} MC steps, "
+                               f"top {c5['top_k']}")}
+        if args.serve_requests > 0:
+            sat = serve_leg(D, torch, c5, 0, args.serve_requests, 200.0, args.serve_slots,
+                            args.serve_steps_per_tick, "200 req/s")
+            served["at_200_per_s"] = sat
+            served["saturation_ligands_per_s"] = sat["steady_ligands_per_s"] or sat["ligands_per_s"]
+            if args.serve_requests_below > 0:
+                rate = args.serve_below * served["saturation_ligands_per_s"]
+                below = serve_leg(D, torch, c5, args.serve_requests, args.serve_requests_below, rate,
+                                  args.serve_slots, args.serve_steps_per_tick,
+                                  f"{args.serve_below:.0%} of saturation")
+                served["below_saturation"] = below
+        out["served"] = served
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps)

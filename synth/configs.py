@@ -30,8 +30,30 @@ def make_box(centre, size, spacing=0.375):
     return {"centre": c, "size": s, "spacing": float(spacing)}
 
 
-def make_config(cfg, seed=None, n_ligands=None):
-    """Inputs of workload ``cfg`` (1..5).  ``seed`` defaults to the workload seed 0."""
+def _lig_job(a):
+    na, nt, sd = a
+    return make_ligand(na, nt, seed=sd, palette=PALETTE_T9)
+
+
+def _rec_job(a):
+    na, sd = a
+    return make_receptor(na, radius=0.0, seed=sd)
+
+
+def request_ligand(shape, k):
+    """Ligand of request ``k`` of the served workload, for its (atoms, torsions) shape."""
+    return make_ligand(int(shape[0]), int(shape[1]), seed=100000 + int(k), palette=PALETTE_T9)
+
+
+def request_ligand_job(a):
+    return request_ligand(*a)
+
+
+def make_config(cfg, seed=None, n_ligands=None, pmap=map):
+    """Inputs of workload ``cfg`` (1..5).  ``seed`` defaults to the workload seed 0.
+
+    ``pmap`` maps the independent per-ligand and per-receptor builds (a process
+    pool's ``map`` gives the same inputs faster)."""
     seed = 0 if seed is None else int(seed)
     if cfg == 1:
         rec = make_receptor(300, radius=10.0, seed=seed)
@@ -55,22 +77,22 @@ def make_config(cfg, seed=None, n_ligands=None):
         box = make_box(rec.pocket, 30.0)
         nl = 512 if n_ligands is None else int(n_ligands)
         rng = np.random.default_rng([seed, 4])
-        ligs = []
+        jobs = []
         for i in range(nl):
             na = int(rng.integers(10, 61))
             nt = int(rng.integers(0, 16))
-            ligs.append(make_ligand(na, nt, seed=i, palette=PALETTE_T9))
+            jobs.append((na, nt, i))
+        ligs = list(pmap(_lig_job, jobs))
         return dict(cfg=4, receptor=rec, box=box, map_types=list(PALETTE_T9), ligands=ligs,
                     n_chains=128, n_steps=1000, top_k=9, seed=seed)
     if cfg == 5:
         rng = np.random.default_rng([seed, 5])
-        recs, boxes = [], []
+        jobs, sizes = [], []
         for r in range(16):
-            na = int(rng.integers(2000, 8001))
-            rec = make_receptor(na, radius=0.0, seed=1000 + r)
-            size = float(rng.uniform(22.0, 30.0))
-            recs.append(rec)
-            boxes.append(make_box(rec.pocket, size))
+            jobs.append((int(rng.integers(2000, 8001)), 1000 + r))
+            sizes.append(float(rng.uniform(22.0, 30.0)))
+        recs = list(pmap(_rec_job, jobs))
+        boxes = [make_box(rec.pocket, size) for rec, size in zip(recs, sizes)]
         nreq = 20000 if n_ligands is None else int(n_ligands)
         gaps = rng.exponential(1.0 / 200.0, size=nreq)
         arrivals = np.cumsum(gaps)
