@@ -103,7 +103,14 @@ typedef struct {
     int32_t waves_per_chain; /* wavefronts per chain, 1..4: that many line-search trials are
                                 evaluated at once; results do not depend on it.  0 = chosen
                                 by the library from the chain count and the device (0) */
+    int32_t intra_form;      /* layout of the intra-ligand term on the device: DSDP_INTRA_AUTO
+                                (chosen by the library for the launch), DSDP_INTRA_PAIRS or
+                                DSDP_INTRA_ATOMS.  Results do not depend on it (0) */
 } dsdp_params;
+
+#define DSDP_INTRA_AUTO 0
+#define DSDP_INTRA_PAIRS 1   /* each pair evaluated once, its force stored and gathered per atom */
+#define DSDP_INTRA_ATOMS 2   /* each pair evaluated from both atoms; no per-pair device scratch */
 
 /* One ranked output pose. */
 typedef struct {

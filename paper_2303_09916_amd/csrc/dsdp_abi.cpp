@@ -136,9 +136,31 @@ dsdp_status validate_ligand(const dsdp_ligand *lig)
     return DSDP_OK;
 }
 
-// map_of_type == nullptr: map indices are left 0 (used only for sizing)
-dsdp_status prepare_ligand(const dsdp_ligand *lig, const int *map_of_type, Prepared &out)
+// Layout of the intra-ligand term for a launch context (both give the same
+// bits, so this only moves speed).  Measured on MI355X: pair lists are faster
+// for one ligand's chains unless the ligand has many pairs and the chains fill
+// the device; launches that mix ligands (batches, the scheduler) run faster
+// with atom lists, whose smaller register and LDS footprint lets more
+// workgroups share a compute unit.
+int choose_intra_form(int n_pairs, long chains, bool mixed)
 {
+    if (mixed) return kFormAtoms;
+    return (n_pairs > 600 && chains >= 2048) ? kFormAtoms : kFormPairs;
+}
+
+IntraCtx intra_ctx(const dsdp_params *prm, long chains, bool mixed)
+{
+    IntraCtx c;
+    c.form = prm ? prm->intra_form : DSDP_INTRA_AUTO;
+    c.chains = chains;
+    c.mixed = mixed;
+    return c;
+}
+
+// map_of_type == nullptr: map indices are left 0 (used only for sizing).
+dsdp_status prepare_ligand(const dsdp_ligand *lig, const int *map_of_type, Prepared &out, const IntraCtx &ctx)
+{
+    const int form = ctx.form;
     dsdp_status st = validate_ligand(lig);
     if (st) return st;
     const int na = lig->n_atoms, nf = lig->n_frags;
@@ -173,7 +195,7 @@ dsdp_status prepare_ligand(const dsdp_ligand *lig, const int *map_of_type, Prepa
         adj[lig->bonds[2 * b + 1]].push_back(lig->bonds[2 * b]);
     }
     // pairs ordered by (j - i, i): 64 consecutive pairs (one wave-wide step of the
-    // kernel) then touch distinct atoms, so their force updates do not collide
+    // kernel) then touch distinct atoms
     std::vector<std::pair<int, int>> plist;
     for (int i = 0; i < na; i++) {
         std::vector<int> dist(na, 1 << 20), queue;
@@ -231,32 +253,52 @@ dsdp_status prepare_ligand(const dsdp_ligand *lig, const int *map_of_type, Prepa
     h.off_frag_off = take(4 * nf, 4);
     h.off_atom_frag = take(na, 1);
     h.off_frag_start = take(nf + 1, 1);
-    h.off_pair = take(np, 1);
-    h.off_pair_rsum = take(np, 1);
-    // per-atom pair lists for the force gather: lane l serves atom l % 32 (half
-    // l / 32) when there are at most 32 atoms, else atom l; entries are pair
-    // indices with a sign bit (set when the atom is the pair's second atom), padded
-    // with the zero slot n_pairs
     const int lpa = na <= 32 ? 2 : 1;
+    h.lanes_per_atom = lpa;
+    h.intra_form = form == DSDP_INTRA_PAIRS ? kFormPairs
+                   : form == DSDP_INTRA_ATOMS ? kFormAtoms
+                                              : choose_intra_form(np, ctx.chains, ctx.mixed);
+
+    // per-lane lists of the chosen form.  Lane l serves atom l % 32 (every other
+    // entry of the atom's list, from l / 32) when there are at most 32 atoms,
+    // else atom l.
+    //   pair lists: pair indices with a sign bit (set when the atom is the pair's
+    //   second atom), padded with the zero slot n_pairs, 8 per 16-byte chunk;
+    //   atom lists: partner bytes j | flags << 6, padded with kNbrNone, 4 per word
     std::vector<std::vector<uint16_t>> lane_list(64);
+    std::vector<std::vector<uint8_t>> lane_nbr(64);
+    size_t maxlen = 0;
     {
         std::vector<std::vector<uint16_t>> atom_list(na);
+        std::vector<std::vector<uint8_t>> atom_nbr(na);
         for (int p = 0; p < np; p++) {
             const int i = pairs[p] & 255u, j = (pairs[p] >> 8) & 255u;
+            const uint32_t fl = pairs[p] >> 16;
             atom_list[i].push_back((uint16_t)p);
             atom_list[j].push_back((uint16_t)(p | 0x8000));
+            atom_nbr[i].push_back((uint8_t)(j | (fl << 6)));
+            atom_nbr[j].push_back((uint8_t)(i | (fl << 6)));
         }
         for (int l = 0; l < 64; l++) {
             const int a = lpa == 2 ? (l & 31) : l, half = lpa == 2 ? (l >> 5) : 0;
             if (a >= na) continue;
-            for (size_t e = half; e < atom_list[a].size(); e += lpa) lane_list[l].push_back(atom_list[a][e]);
+            for (size_t e = half; e < atom_list[a].size(); e += lpa) {
+                lane_list[l].push_back(atom_list[a][e]);
+                lane_nbr[l].push_back(atom_nbr[a][e]);
+            }
+            maxlen = std::max(maxlen, lane_list[l].size());
         }
     }
-    size_t maxlen = 0;
-    for (const auto &v : lane_list) maxlen = std::max(maxlen, v.size());
-    h.n_chunks = (int)((maxlen + 7) / 8);
-    h.lanes_per_atom = lpa;
-    h.off_plist = take(h.n_chunks * 64 * 4, 4);
+    if (h.intra_form == kFormPairs) {
+        h.off_pair = take(np, 1);
+        h.off_pair_rsum = take(np, 1);
+        h.n_chunks = (int)((maxlen + 7) / 8);
+        h.off_plist = take(h.n_chunks * 64 * 4, 4);
+    } else {
+        h.nbr_words = (int)((maxlen + 3) / 4);
+        h.off_nbr = take(h.nbr_words * 64, 1);
+        h.off_atom_rad = take(na, 1);
+    }
     h.total_words = (w + 3) / 4 * 4;
 
     std::vector<uint32_t> blob((size_t)h.total_words, 0u);
@@ -297,21 +339,42 @@ dsdp_status prepare_ligand(const dsdp_ligand *lig, const int *map_of_type, Prepa
         blob[(size_t)h.off_frag_off + 4 * k + 3] = sub[k];
     }
     for (int k = 0; k <= nf; k++) blob[(size_t)h.off_frag_start + k] = (uint32_t)lig->frag_start[k];
-    for (int p = 0; p < np; p++) {
-        blob[(size_t)h.off_pair + p] = pairs[p];
-        fput(h.off_pair_rsum + p, rsum[p]);
-    }
-    for (int c = 0; c < h.n_chunks; c++)
-        for (int l = 0; l < 64; l++)
-            for (int q = 0; q < 8; q++) {
-                const size_t e = (size_t)c * 8 + q;
-                const uint32_t v = e < lane_list[l].size() ? lane_list[l][e] : (uint32_t)np;
-                uint32_t &word = blob[(size_t)h.off_plist + ((size_t)c * 64 + l) * 4 + q / 2];
-                word |= (q & 1) ? (v << 16) : v;
+    if (h.intra_form == kFormPairs) {
+        for (int p = 0; p < np; p++) {
+            blob[(size_t)h.off_pair + p] = pairs[p];
+            fput(h.off_pair_rsum + p, rsum[p]);
+        }
+        for (int c = 0; c < h.n_chunks; c++)
+            for (int l = 0; l < 64; l++)
+                for (int q = 0; q < 8; q++) {
+                    const size_t e = (size_t)c * 8 + q;
+                    const uint32_t v = e < lane_list[l].size() ? lane_list[l][e] : (uint32_t)np;
+                    uint32_t &word = blob[(size_t)h.off_plist + ((size_t)c * 64 + l) * 4 + q / 2];
+                    word |= (q & 1) ? (v << 16) : v;
+                }
+    } else {
+        for (int m = 0; m < h.nbr_words; m++)
+            for (int l = 0; l < 64; l++) {
+                uint32_t word = 0;
+                for (int b = 0; b < 4; b++) {
+                    const size_t e = (size_t)m * 4 + b;
+                    const uint32_t v = e < lane_nbr[l].size() ? lane_nbr[l][e] : kNbrNone;
+                    word |= v << (8 * b);
+                }
+                blob[(size_t)h.off_nbr + (size_t)m * 64 + l] = word;
             }
+        for (int i = 0; i < na; i++) fput(h.off_atom_rad + i, xs_radius(lig->atoms[i].xs_type));
+    }
     out.h = h;
     out.blob.swap(blob);
     return DSDP_OK;
+}
+
+size_t max_blob_words(const dsdp_ligand *lig)
+{
+    Prepared a, b;
+    if (prepare_ligand(lig, nullptr, a, IntraCtx{DSDP_INTRA_PAIRS}) || prepare_ligand(lig, nullptr, b, IntraCtx{DSDP_INTRA_ATOMS})) return 0;
+    return (size_t)std::max(a.h.total_words, b.h.total_words);
 }
 
 SearchParams to_search(const dsdp_params *p)
@@ -337,7 +400,8 @@ dsdp_status check_params(const dsdp_params *p)
     if (p->struct_size != sizeof(dsdp_params)) return fail(DSDP_ERR_INVALID_ARG, "params.struct_size mismatch");
     if (!(p->temperature > 0) || !(p->wall_slope >= 0) || !(p->rmsd_cluster >= 0) || !(p->trans_amp >= 0) ||
         p->bfgs_iters < 0 || p->ls_trials < 1 || !(p->ls_shrink > 0 && p->ls_shrink < 1) || !(p->armijo_c1 >= 0) ||
-        p->waves_per_chain < 0 || p->waves_per_chain > 4)
+        p->waves_per_chain < 0 || p->waves_per_chain > 4 || p->intra_form < DSDP_INTRA_AUTO ||
+        p->intra_form > DSDP_INTRA_ATOMS)
         return fail(DSDP_ERR_INVALID_ARG, "search parameter out of range");
     return DSDP_OK;
 }
@@ -451,6 +515,46 @@ struct Events {
     }
 };
 
+dsdp_status plan_groups(const dsdp_params *prm, const std::vector<const LigHeader *> &hdr,
+                        const std::vector<long> &chains, std::vector<LaunchGroup> &out)
+{
+    out.clear();
+    const int n = (int)hdr.size();
+    std::vector<int> idx(n);
+    std::vector<size_t> lds1(n);
+    for (int i = 0; i < n; i++) {
+        idx[i] = i;
+        lds1[i] = search_lds_bytes(*hdr[i], 1);
+    }
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+        const int ca = search_class(*hdr[a]), cb = search_class(*hdr[b]);
+        return ca != cb ? ca < cb : lds1[a] < lds1[b];
+    });
+    for (int k = 0; k < n;) {
+        LaunchGroup g;
+        g.cls = search_class(*hdr[idx[k]]);
+        int worst = idx[k];
+        while (k < n && search_class(*hdr[idx[k]]) == g.cls) {
+            g.members.push_back(idx[k]);
+            g.chains += chains[idx[k]];
+            worst = idx[k];   // sorted by LDS: the last member needs the most
+            k++;
+        }
+        // waves per chain from the group's chain count (groups are launched one
+        // after another), then lowered until the largest member fits
+        dsdp_status st = pick_waves(prm, *hdr[worst], (int)std::min<long>(g.chains, 1L << 30), g.waves);
+        if (st) return st;
+        for (;;) {
+            g.lds = search_lds_bytes(*hdr[worst], g.waves);
+            if (g.lds <= device_max_lds() || g.waves == 1) break;
+            g.waves--;
+        }
+        if (g.lds > device_max_lds()) return fail(DSDP_ERR_UNSUPPORTED, "a ligand needs %zu bytes of LDS", g.lds);
+        out.push_back(std::move(g));
+    }
+    return DSDP_OK;
+}
+
 void fill_pose(const float *r, int nt, int chain, dsdp_pose &p)
 {
     std::memset(&p, 0, sizeof p);
@@ -500,6 +604,7 @@ void dsdp_params_default(dsdp_params *p)
     p->ls_shrink = 0.1f;
     p->armijo_c1 = 1e-4f;
     p->waves_per_chain = 0;
+    p->intra_form = DSDP_INTRA_AUTO;
 }
 
 dsdp_status dsdp_grid_dims(const dsdp_box *box, int32_t *n, float *origin)
@@ -619,9 +724,9 @@ dsdp_status dsdp_build_grids(const dsdp_atom *rec, int32_t n_rec, const dsdp_box
     g->view.h = box->spacing;
     g->view.inv_h = 1.0f / box->spacing;
     g->view.T = n_types;
-    for (int t = 0; t < kNXS; t++) g->view.map_of_type[t] = -1;
+    for (int t = 0; t < kNXS; t++) g->map_of_type[t] = -1;
     for (int t = 0; t < n_types; t++) {
-        g->view.map_of_type[tl[t]] = t;
+        g->map_of_type[tl[t]] = t;
         g->types[t] = tl[t];
     }
     hipError_t e = launch_grid_build(d_atoms, d_start, cg.cn, cg.clo, cg.cell, g->view, tl, (float4 *)d_maps, s);
@@ -638,7 +743,7 @@ void dsdp_grids_release(dsdp_grids g) { delete g; }
 dsdp_status dsdp_ligand_info(const dsdp_ligand *lig, int32_t *n_pairs, int32_t *tree_depth)
 {
     Prepared pl;
-    dsdp_status st = prepare_ligand(lig, nullptr, pl);
+    dsdp_status st = prepare_ligand(lig, nullptr, pl, IntraCtx{});
     if (st) return st;
     if (n_pairs) *n_pairs = pl.h.n_pairs;
     if (tree_depth) *tree_depth = pl.h.max_depth;
@@ -647,9 +752,9 @@ dsdp_status dsdp_ligand_info(const dsdp_ligand *lig, int32_t *n_pairs, int32_t *
 
 size_t dsdp_dock_workspace_bytes(const dsdp_ligand *lig, int32_t n_chains)
 {
-    Prepared pl;
-    if (n_chains < 1 || prepare_ligand(lig, nullptr, pl)) return 0;
-    return search_ws(pl.h, n_chains).total;
+    const size_t words = max_blob_words(lig);
+    if (n_chains < 1 || words == 0) return 0;
+    return search_ws(words, n_chains, 1, 1).total;
 }
 
 dsdp_status dsdp_eval_poses(dsdp_grids g, const dsdp_ligand *lig, const float *d_poses, int32_t n_poses,
@@ -662,7 +767,7 @@ dsdp_status dsdp_eval_poses(dsdp_grids g, const dsdp_ligand *lig, const float *d
     dsdp_status st = check_params(prm);
     if (st) return st;
     Prepared pl;
-    st = prepare_ligand(lig, g->view.map_of_type, pl);
+    st = prepare_ligand(lig, g->map_of_type, pl, intra_ctx(prm, n_poses, false));
     if (st) return st;
     const SearchWs w = search_ws(pl.h, std::max(n_poses, 1));
     if (!d_ws || ws_bytes < w.total) return fail(DSDP_ERR_WORKSPACE_TOO_SMALL, "workspace needs %zu bytes", w.total);
@@ -689,7 +794,7 @@ dsdp_status dsdp_local_opt(dsdp_grids g, const dsdp_ligand *lig, const float *d_
     dsdp_status st = check_params(prm);
     if (st) return st;
     Prepared pl;
-    st = prepare_ligand(lig, g->view.map_of_type, pl);
+    st = prepare_ligand(lig, g->map_of_type, pl, intra_ctx(prm, n_poses, false));
     if (st) return st;
     const SearchWs w = search_ws(pl.h, std::max(n_poses, 1));
     if (!d_ws || ws_bytes < w.total) return fail(DSDP_ERR_WORKSPACE_TOO_SMALL, "workspace needs %zu bytes", w.total);
@@ -723,7 +828,7 @@ dsdp_status dsdp_dock(dsdp_grids g, const dsdp_ligand *lig, int32_t n_chains, in
     dsdp_status st = check_params(prm);
     if (st) return st;
     Prepared pl;
-    st = prepare_ligand(lig, g->view.map_of_type, pl);
+    st = prepare_ligand(lig, g->map_of_type, pl, intra_ctx(prm, n_chains, false));
     if (st) return st;
     const SearchWs w = search_ws(pl.h, n_chains);
     if (!d_ws || ws_bytes < w.total) return fail(DSDP_ERR_WORKSPACE_TOO_SMALL, "workspace needs %zu bytes", w.total);
@@ -768,7 +873,7 @@ dsdp_status dsdp_dock(dsdp_grids g, const dsdp_ligand *lig, int32_t n_chains, in
     float *rec = (float *)(ws + w.records);
     float4 *bxyz = (float4 *)(ws + w.xyz);
     int *sel = (int *)(ws + w.sel);
-    HIP_TRY(launch_tick(pair_slots_class(pl.h.n_pairs), waves, search_lds_bytes(pl.h, waves),
+    HIP_TRY(launch_tick(search_class(pl.h), waves, search_lds_bytes(pl.h, waves),
                         (const uint32_t *)(ws + w.arena), (const ChainTask *)(ws + w.tasks), n_chains,
                         (const GridView *)(ws + w.grids), sp, n_steps, 1, (float *)(ws + w.state), rec, bxyz, s),
             "search launch");
@@ -817,9 +922,9 @@ size_t dsdp_dock_batch_workspace_bytes(const dsdp_ligand *ligs, int32_t n_ligs, 
     if (!ligs || n_ligs < 1 || n_chains < 1) return 0;
     size_t words = 0;
     for (int l = 0; l < n_ligs; l++) {
-        Prepared pl;
-        if (prepare_ligand(&ligs[l], nullptr, pl)) return 0;
-        words += (size_t)pl.h.total_words;
+        const size_t lw = max_blob_words(&ligs[l]);
+        if (lw == 0) return 0;
+        words += lw;
     }
     return search_ws(words, (long)n_ligs * n_chains, 1, n_ligs).total;
 }
@@ -841,7 +946,7 @@ dsdp_status dsdp_dock_batch(dsdp_grids g, const dsdp_ligand *ligs, int32_t n_lig
     std::vector<Prepared> pls((size_t)n_ligs);
     size_t words = 0;
     for (int l = 0; l < n_ligs; l++) {
-        st = prepare_ligand(&ligs[l], g->view.map_of_type, pls[l]);
+        st = prepare_ligand(&ligs[l], g->map_of_type, pls[l], intra_ctx(prm, (long)n_ligs * n_chains, true));
         if (st) {
             char msg[600];
             snprintf(msg, sizeof msg, "ligand %d: %s", l, g_error.c_str());
@@ -857,43 +962,32 @@ dsdp_status dsdp_dock_batch(dsdp_grids g, const dsdp_ligand *ligs, int32_t n_lig
     hipStream_t s = (hipStream_t)stream;
     char *ws = (char *)d_ws;
 
-    // buckets by pair-slot class; in each, the tuner's wave count for the bucket's
-    // chain count and the largest ligand's LDS
+    // launch groups (kernel variant and LDS need); each group's chains are
+    // contiguous in the task table
     struct Bucket {
-        int ppl = 0, waves = 1;
+        int cls = 0, waves = 1;
         size_t lds = 0;
         long first = 0, count = 0;
     };
     std::vector<Bucket> buckets;
     std::vector<int> order;
-    for (int cls : {8, 16, 32}) {
-        Bucket b;
-        b.ppl = cls;
-        LigHeader worst{};
-        size_t worst_lds = 0;
-        for (int l = 0; l < n_ligs; l++)
-            if (pair_slots_class(pls[l].h.n_pairs) == cls) {
-                order.push_back(l);
-                b.count += n_chains;
-                if (search_lds_bytes(pls[l].h, 1) > worst_lds) {
-                    worst_lds = search_lds_bytes(pls[l].h, 1);
-                    worst = pls[l].h;
-                }
-            }
-        if (!b.count) continue;
-        b.first = (long)order.size() * n_chains - b.count;
-        st = pick_waves(prm, worst, (int)std::min<long>(b.count, 1L << 30), b.waves);
+    {
+        std::vector<const LigHeader *> hdr((size_t)n_ligs);
+        std::vector<long> ch((size_t)n_ligs, n_chains);
+        for (int l = 0; l < n_ligs; l++) hdr[l] = &pls[l].h;
+        std::vector<LaunchGroup> groups;
+        st = plan_groups(prm, hdr, ch, groups);
         if (st) return st;
-        for (;;) {
-            b.lds = 0;
-            for (int l : order)
-                if (pair_slots_class(pls[l].h.n_pairs) == cls)
-                    b.lds = std::max(b.lds, search_lds_bytes(pls[l].h, b.waves));
-            if (b.lds <= device_max_lds() || b.waves == 1) break;
-            b.waves--;
+        for (const LaunchGroup &g : groups) {
+            Bucket b;
+            b.cls = g.cls;
+            b.waves = g.waves;
+            b.lds = g.lds;
+            b.first = (long)order.size() * n_chains;
+            b.count = g.chains;
+            for (int l : g.members) order.push_back(l);
+            buckets.push_back(b);
         }
-        if (b.lds > device_max_lds()) return fail(DSDP_ERR_UNSUPPORTED, "a ligand needs %zu bytes of LDS", b.lds);
-        buckets.push_back(b);
     }
 
     HostImage img(w.host_end);
@@ -951,7 +1045,7 @@ dsdp_status dsdp_dock_batch(dsdp_grids g, const dsdp_ligand *ligs, int32_t n_lig
     hipError_t le = hipSuccess;
     for (int k = 0; k < n_ticks && le == hipSuccess; k++)
         for (const Bucket &b : buckets) {
-            le = launch_tick(b.ppl, b.waves, b.lds, (const uint32_t *)(ws + w.arena),
+            le = launch_tick(b.cls, b.waves, b.lds, (const uint32_t *)(ws + w.arena),
                              (const ChainTask *)(ws + w.tasks) + b.first, (int)b.count, (const GridView *)(ws + w.grids),
                              sp, spt, k == 0 ? 1 : 0, (float *)(ws + w.state), rec, bxyz, cs);
             if (le != hipSuccess) break;

@@ -47,14 +47,13 @@ constexpr float kWHydrophobic = -0.0351f;
 constexpr float kWHBond = -0.587f;
 constexpr float kWRot = 0.0585f;
 
-// Device view of one set of maps.
+// Device view of one set of maps (kept small: kernels hold it in scalar registers).
 struct GridView {
     const float4 *maps;      // [T][nz][ny][nx] (E, dE/dx, dE/dy, dE/dz)
     int n[3];
     float origin[3];
     float h, inv_h;
     int T;
-    int map_of_type[kNXS];   // XS type -> map index or -1
 };
 
 // Ligand blob: 32-bit words, built on the host per (ligand, grids), copied to the
@@ -74,8 +73,23 @@ struct LigHeader {
     int32_t off_plist;       // uint4[n_chunks][64]: per gather lane, 8 u16 entries (pair | sign << 15) per chunk
     int32_t n_chunks;        // chunks of 8 entries per gather lane
     int32_t lanes_per_atom;  // 2 when n_atoms <= 32 (lanes a and a + 32 split atom a's list), else 1
+    int32_t intra_form;      // kFormPairs or kFormAtoms (how the intra-ligand term is laid out)
+    int32_t nbr_words;       // atom lists: words of packed partner bytes per lane
+    int32_t off_nbr;         // atom lists: uint32[nbr_words][64], byte = partner | hydrophobic << 6 | hbond << 7
+    int32_t off_atom_rad;    // atom lists: float[n_atoms] XS radius
     int32_t total_words;     // multiple of 4
 };
+
+// Two layouts of the intra-ligand term.  Pair lists: lane l evaluates pairs
+// l + 64 k once and stores each pair's force in LDS; every atom then gathers the
+// forces of its pairs.  Atom lists: a lane owns an atom (or half of its partners
+// when there are at most 32 atoms) and evaluates each of the atom's pairs from
+// its own side, so every pair is evaluated twice but nothing per pair is kept
+// in LDS.  The second trades arithmetic for LDS and registers; which one a ligand
+// uses depends on its shape only (choose_intra_form).
+constexpr int kFormPairs = 0;
+constexpr int kFormAtoms = 1;
+constexpr uint32_t kNbrNone = 0xFFu;   // empty partner byte (no pair is both hydrophobic and H-bonding)
 constexpr int kHeaderWords = (int)(sizeof(LigHeader) / 4 + 3) / 4 * 4;
 
 // Per-chain result record in device memory (words).
@@ -140,12 +154,15 @@ hipError_t launch_local_opt(const uint32_t *blob, int blob_words, const LigHeade
                             const SearchParams &p, int waves, const float *poses_in, int n, float *poses_out,
                             float *energy, int *evals, hipStream_t stream);
 // Advance every task by up to tick_steps MC steps (init = start chains afresh).
-// ppl: pair slots per lane (8, 16 or 32); lds_bytes: per-workgroup LDS.
-hipError_t launch_tick(int ppl, int waves, size_t lds_bytes, const uint32_t *arena, const ChainTask *tasks,
+// cls: search_class of every task's ligand; lds_bytes: per-workgroup LDS.
+hipError_t launch_tick(int cls, int waves, size_t lds_bytes, const uint32_t *arena, const ChainTask *tasks,
                        int n_tasks, const GridView *grids, const SearchParams &p, int tick_steps, int init,
                        float *state, float *records, float4 *best_xyz, hipStream_t stream);
 hipError_t launch_rank(const float *records, const float4 *best_xyz, const RankSeg *segs, int n_segs,
                        int max_chains, float rmsd_cut, int *sel, hipStream_t stream);
-int pair_slots_class(int n_pairs);   // 8, 16 or 32
+// Kernel variant of a prepared ligand: 0..2 pair lists with 8, 16, 32 pair
+// slots per lane; 3 atom lists.
+constexpr int kNumClasses = 4;
+int search_class(const LigHeader &h);
 
 }  // namespace dsdp

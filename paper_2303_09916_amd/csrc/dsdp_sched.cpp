@@ -388,7 +388,8 @@ dsdp_status dsdp_sched_submit(dsdp_sched s, int32_t receptor_id, const dsdp_liga
     if (n_steps < 0) return fail(DSDP_ERR_INVALID_ARG, "n_steps < 0");
     if (top_k < 0 || top_k > n_chains) return fail(DSDP_ERR_INVALID_ARG, "top_k %d outside 0..n_chains", top_k);
     std::unique_ptr<Request> q(new Request());
-    dsdp_status st = prepare_ligand(lig, s->receptors[(size_t)receptor_id].map_of_type, q->pl);
+    dsdp_status st = prepare_ligand(lig, s->receptors[(size_t)receptor_id].map_of_type, q->pl,
+                                    intra_ctx(&s->prm, s->capacity, true));
     if (st) return st;
     if (search_lds_bytes(q->pl.h, 1) > device_max_lds())
         return fail(DSDP_ERR_UNSUPPORTED, "ligand needs %zu bytes of LDS", search_lds_bytes(q->pl.h, 1));
@@ -438,24 +439,24 @@ dsdp_status dsdp_sched_tick(dsdp_sched s, int32_t *n_completed)
     if (s->running.empty()) return DSDP_OK;
     s->ticks++;
 
-    // tasks of every running chain, grouped by pair-slot class
+    // tasks of every running chain, in launch groups (kernel variant and LDS need)
     s->h_tasks.clear();
-    struct Group {
-        int ppl;
-        long first = 0, count = 0;
-        const LigHeader *worst = nullptr;
-        size_t worst_lds = 0;
-    };
-    std::vector<Group> groups;
-    for (int cls : {8, 16, 32}) {
-        Group g{cls};
-        g.first = (long)s->h_tasks.size();
+    std::vector<LaunchGroup> groups;
+    {
+        std::vector<const LigHeader *> hdr;
+        std::vector<long> ch;
         for (Request *q : s->running) {
-            if (pair_slots_class(q->pl.h.n_pairs) != cls) continue;
-            if (search_lds_bytes(q->pl.h, 1) > g.worst_lds) {
-                g.worst_lds = search_lds_bytes(q->pl.h, 1);
-                g.worst = &q->pl.h;
-            }
+            hdr.push_back(&q->pl.h);
+            ch.push_back(q->n_chains);
+        }
+        st = plan_groups(&s->prm, hdr, ch, groups);
+        if (st) return st;
+    }
+    std::vector<long> first;
+    for (const LaunchGroup &g : groups) {
+        first.push_back((long)s->h_tasks.size());
+        for (int m : g.members) {
+            const Request *q = s->running[(size_t)m];
             for (int c = 0; c < q->n_chains; c++) {
                 ChainTask t{};
                 t.blob_off = (uint32_t)(q->arena_off / 4);
@@ -470,8 +471,6 @@ dsdp_status dsdp_sched_tick(dsdp_sched s, int32_t *n_completed)
                 s->h_tasks.push_back(t);
             }
         }
-        g.count = (long)s->h_tasks.size() - g.first;
-        if (g.count) groups.push_back(g);
     }
     HIP_TRY(hipMemcpyAsync(s->pool + s->off_tasks, s->h_tasks.data(), s->h_tasks.size() * sizeof(ChainTask),
                            hipMemcpyHostToDevice, s->stream),
@@ -482,20 +481,10 @@ dsdp_status dsdp_sched_tick(dsdp_sched s, int32_t *n_completed)
                 "grid upload");
         s->grids_dirty = false;
     }
-    for (const Group &g : groups) {
-        int waves = 1;
-        st = pick_waves(&s->prm, *g.worst, (int)g.count, waves);
-        if (st) return st;
-        size_t lds = 0;
-        for (;;) {
-            lds = 0;
-            for (Request *q : s->running)
-                if (pair_slots_class(q->pl.h.n_pairs) == g.ppl) lds = std::max(lds, search_lds_bytes(q->pl.h, waves));
-            if (lds <= device_max_lds() || waves == 1) break;
-            waves--;
-        }
-        HIP_TRY(launch_tick(g.ppl, waves, lds, (const uint32_t *)s->pool,
-                            (const ChainTask *)(s->pool + s->off_tasks) + g.first, (int)g.count,
+    for (size_t k = 0; k < groups.size(); k++) {
+        const LaunchGroup &g = groups[k];
+        HIP_TRY(launch_tick(g.cls, g.waves, g.lds, (const uint32_t *)s->pool,
+                            (const ChainTask *)(s->pool + s->off_tasks) + first[k], (int)g.chains,
                             (const GridView *)(s->pool + s->off_grids), s->sp, s->spt, 0,
                             (float *)(s->pool + s->off_state), (float *)(s->pool + s->off_records),
                             (float4 *)(s->pool + s->off_xyz), s->stream),

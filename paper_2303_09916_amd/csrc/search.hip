@@ -191,6 +191,43 @@ __device__ __forceinline__ float2 vina_pair(float d, float wh, float wb)
 __device__ __forceinline__ float pair_wh(uint32_t flags) { return (flags & kPairHydrophobic) ? kWHydrophobic : 0.0f; }
 __device__ __forceinline__ float pair_wb(uint32_t flags) { return (flags & kPairHBond) ? kWHBond : 0.0f; }
 
+// Squared distance and the pair's (energy, dE/dr / r) for radius sum rsum and
+// class flags: one definition for both intra-ligand layouts, so that both
+// round alike.
+__device__ __forceinline__ float pair_r2(float dx, float dy, float dz) { return dx * dx + dy * dy + dz * dz; }
+__device__ __forceinline__ float2 pair_term(float r2, float rsum, uint32_t flags)
+{
+    const float inv_r = r2 > 1e-18f ? rsqrtf(r2) : 0.f;
+    const float2 ed = vina_pair(r2 * inv_r - rsum, pair_wh(flags), pair_wb(flags));
+    return make_float2(ed.x, ed.y * inv_r);
+}
+
+// Intra-ligand energies are summed as integers in units of 2^-32 kcal/mol:
+// the sum then does not depend on the order of the terms.
+__device__ __forceinline__ long long to_fixed(float e) { return __float2ll_rn(e * 4294967296.0f); }
+__device__ __forceinline__ float from_fixed(long long v) { return (float)((double)v * (1.0 / 4294967296.0)); }
+// s * d rounded on its own, and acc + s * d with the product rounded before the
+// addition (no fused multiply-add): the pair-list layout stores the product and
+// adds it later, and the atom-list layout must round the same way.
+__device__ __forceinline__ float mul_rounded(float s, float d)
+{
+#pragma clang fp contract(off)
+    return s * d;
+}
+__device__ __forceinline__ float add_product(float acc, float s, float d)
+{
+#pragma clang fp contract(off)
+    const float p = s * d;
+    return acc + p;
+}
+
+__device__ __forceinline__ long long wave_sum_i64(long long v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
 // ---------------------------------------------------------------- LDS layout
 struct LigL {
     int na, nf, nt, np, D, nx, maxdepth;
@@ -202,8 +239,11 @@ struct LigL {
     const int *frag_start;
     const uint32_t *pair;
     const float *rsum;
-    const uint4 *plist;      // [n_chunks][64] gather lists
+    const uint4 *plist;      // [n_chunks][64] gather lists (pair lists)
     int n_chunks, lanes_per_atom;
+    const uint32_t *nbr;     // [nbr_words][64] packed partner bytes (atom lists)
+    const float *arad;       // [na] XS radius (atom lists)
+    int nbr_words;
 };
 
 // Scratch of one pose evaluation (one per wave).
@@ -245,7 +285,7 @@ __host__ __device__ inline Layout make_layout(int na, int nf, int np, int D, int
     c.NXp = rup4(nx);
     int w = 0;
     c.xyz = w; w += 4 * na;
-    c.pf = w; w += 4 * (np + 1);
+    c.pf = w; w += 4 * (np + 1);   // np = -1: no pair-force scratch (atom lists)
     c.af = w; w += 4 * na;
     c.at = w; w += 4 * na;
     c.R = w; w += 16 * nf;
@@ -296,9 +336,12 @@ __device__ inline ChainL make_chain(float *base, const Layout &c)
     return C;
 }
 
-__device__ inline LigL make_lig(const uint32_t *blob)
+// `blob`: the LDS copy the data pointers refer to; `hdr`: the blob in global
+// memory, whose header is read with scalar loads so that sizes, offsets and the
+// pointers derived from them stay in scalar registers.
+__device__ inline LigL make_lig(const uint32_t *blob, const uint32_t *hdr)
 {
-    const LigHeader *h = reinterpret_cast<const LigHeader *>(blob);
+    const LigHeader *h = reinterpret_cast<const LigHeader *>(hdr);
     LigL L;
     L.na = h->n_atoms; L.nf = h->n_frags; L.nt = h->n_tors; L.np = h->n_pairs;
     L.D = 6 + L.nt; L.nx = 7 + L.nt;
@@ -314,27 +357,34 @@ __device__ inline LigL make_lig(const uint32_t *blob)
     L.plist = reinterpret_cast<const uint4 *>(blob + h->off_plist);
     L.n_chunks = h->n_chunks;
     L.lanes_per_atom = h->lanes_per_atom;
+    L.nbr = blob + h->off_nbr;
+    L.arad = reinterpret_cast<const float *>(blob + h->off_atom_rad);
+    L.nbr_words = h->nbr_words;
     return L;
 }
 
-// A lane's share of the intra-ligand pair list (pairs lane, lane + 64, ...),
-// loaded once per chain; unused slots carry kPairNone.
+// A lane's share of the intra-ligand term held in registers for the whole
+// chain.  Pair lists (PPL > 0): pairs lane + 64 k, unused slots carry kPairNone.
+// Atom lists (PPL == 0) keep nothing in registers: the partner words are read
+// from LDS as they are consumed, which bounds the registers the loop needs.
 constexpr uint32_t kPairNone = 0x80000000u;
-template <int PPL>
-struct PairRegs {
-    uint32_t w[PPL];
-    float rs[PPL];
+template <int PPL, int NBW>
+struct IntraRegs {
+    uint32_t w[PPL > 0 ? PPL : 1];
+    float rs[PPL > 0 ? PPL : 1];
 };
-template <int PPL>
-__device__ inline PairRegs<PPL> load_pairs(const LigL &L)
+template <int PPL, int NBW>
+__device__ inline IntraRegs<PPL, NBW> load_intra(const LigL &L)
 {
-    PairRegs<PPL> pr;
+    IntraRegs<PPL, NBW> pr;
     const int lane = lane_id();
+    if constexpr (PPL > 0) {
 #pragma unroll
-    for (int k = 0; k < PPL; k++) {
-        const int p = lane + 64 * k;
-        pr.w[k] = p < L.np ? L.pair[p] : kPairNone;
-        pr.rs[k] = p < L.np ? L.rsum[p] : 0.f;
+        for (int k = 0; k < PPL; k++) {
+            const int p = lane + 64 * k;
+            pr.w[k] = p < L.np ? L.pair[p] : kPairNone;
+            pr.rs[k] = p < L.np ? L.rsum[p] : 0.f;
+        }
     }
     return pr;
 }
@@ -344,15 +394,11 @@ struct Energy {
     float total, inter, intra, wall;
 };
 
-// Energy of `pose` (LDS, wave-uniform) and, if grad != nullptr, its gradient in
-// the tangent coordinates written to grad[0..D) (LDS).  Coordinates are left in
-// S.xyz.  Every lane returns the same values.
-template <int PPL>
-__device__ Energy eval_pose(const LigL &L, const WaveL &S, const PairRegs<PPL> &pr, const GridView &G,
-                            const float *pose, float *grad, float wall_slope)
+// World frame (rotation rows and origin) of every fragment for `pose`, in S.R;
+// the relative rotations are left in S.Q.
+__device__ inline void frames(const LigL &L, const WaveL &S, const float *pose)
 {
     const int lane = lane_id();
-
     // (1) rotation of every fragment relative to its parent (root: R(q)); clear
     //     the fragment force/torque accumulators
     if (lane < L.nf) {
@@ -396,6 +442,30 @@ __device__ Energy eval_pose(const LigL &L, const WaveL &S, const PairRegs<PPL> &
     }
     wave_sync();
 
+}
+
+// Position of ligand atom `a` (< n_atoms) after frames().
+__device__ inline float3 atom_position(const LigL &L, const WaveL &S, int a)
+{
+    const int frag = L.atom_frag[a];
+    const float4 loc = L.atom[a];
+    const float4 r0 = S.R[4 * frag], r1 = S.R[4 * frag + 1], r2 = S.R[4 * frag + 2], o = S.R[4 * frag + 3];
+    return make_float3(o.x + r0.x * loc.x + r0.y * loc.y + r0.z * loc.z,
+                       o.y + r1.x * loc.x + r1.y * loc.y + r1.z * loc.z,
+                       o.z + r2.x * loc.x + r2.y * loc.y + r2.z * loc.z);
+}
+
+// Energy of `pose` (LDS, wave-uniform) and, if grad != nullptr, its gradient in
+// the tangent coordinates written to grad[0..D) (LDS).  Coordinates are left in
+// S.xyz.  Every lane returns the same values.
+template <int PPL, int NBW>
+__device__ Energy eval_pose(const LigL &L, const WaveL &S, const IntraRegs<PPL, NBW> &pr, const GridView &G,
+                            const float *pose, float *grad, float wall_slope)
+{
+    const int lane = lane_id();
+
+    frames(L, S, pose);
+
     // (3) atom coordinates; issue the eight corner gathers of the inter-molecular
     //     term now and consume them after the intra-ligand pairs
     float w_atom = 0.f;
@@ -411,7 +481,7 @@ __device__ Energy eval_pose(const LigL &L, const WaveL &S, const PairRegs<PPL> &
         x = make_float3(o.x + r0.x * loc.x + r0.y * loc.y + r0.z * loc.z,
                         o.y + r1.x * loc.x + r1.y * loc.y + r1.z * loc.z,
                         o.z + r2.x * loc.x + r2.y * loc.y + r2.z * loc.z);
-        S.xyz[lane] = make_float4(x.x, x.y, x.z, 0.f);
+        S.xyz[lane] = make_float4(x.x, x.y, x.z, PPL == 0 ? L.arad[lane] : 0.f);
 
         // wall and clamping: a coordinate outside the box is clamped onto the face;
         // the atom pays wall_slope per Angstrom outside and the map gradient along
@@ -457,27 +527,59 @@ __device__ Energy eval_pose(const LigL &L, const WaveL &S, const PairRegs<PPL> &
     }
     wave_sync();
 
-    // (4) intra-ligand pairs, PPL per lane held in registers (pair lane + 64 k);
-    //     forces accumulate per atom in LDS
-    float e_pair = 0.f;
-    const int slots = (L.np + 63) >> 6;
+    // (4) intra-ligand terms.  Pair lists: PPL pairs per lane held in registers
+    //     (pair lane + 64 k), each pair's force stored once for the atoms to
+    //     gather.  Atom lists: every pair of the lane's atom (or half of them),
+    //     evaluated from the atom's side, the force kept in registers.  Energies
+    //     are summed in fixed point (each pair once), forces per atom in the
+    //     same order with the same roundings, so both layouts give the same bits.
+    long long e_fix = 0;
+    float3 fnb = make_float3(0.f, 0.f, 0.f);
+    if constexpr (PPL > 0) {
+        const int slots = (L.np + 63) >> 6;
 #pragma unroll
-    for (int k = 0; k < PPL; k++) {
-        if (k < slots) {
-        const uint32_t pw = pr.w[k];
-        const int i = (int)(pw & 255u), j = (int)((pw >> 8) & 255u);
-        const float4 xi = S.xyz[i], xj = S.xyz[j];
-        const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
-        const float r2 = dx * dx + dy * dy + dz * dz;
-        float sp = 0.f;
-        if (!(pw & kPairNone) && r2 < kCutoff2) {
-            const float inv_r = r2 > 1e-18f ? rsqrtf(r2) : 0.f;
-            const uint32_t fl = pw >> 16;
-            const float2 ed = vina_pair(r2 * inv_r - pr.rs[k], pair_wh(fl), pair_wb(fl));
-            e_pair += ed.x;
-            sp = ed.y * inv_r;
+        for (int k = 0; k < PPL; k++) {
+            if (k < slots) {
+                const uint32_t pw = pr.w[k];
+                const int i = (int)(pw & 255u), j = (int)((pw >> 8) & 255u);
+                const float4 xi = S.xyz[i], xj = S.xyz[j];
+                const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
+                const float r2 = pair_r2(dx, dy, dz);
+                float sp = 0.f;
+                if (!(pw & kPairNone) && r2 < kCutoff2) {
+                    const float2 es = pair_term(r2, pr.rs[k], pw >> 16);
+                    e_fix += to_fixed(es.x);
+                    sp = es.y;
+                }
+                if (grad != nullptr && !(pw & kPairNone))
+                    S.pf[lane + 64 * k] = make_float4(mul_rounded(sp, dx), mul_rounded(sp, dy), mul_rounded(sp, dz), 0.f);
+            }
         }
-        if (grad != nullptr && !(pw & kPairNone)) S.pf[lane + 64 * k] = make_float4(sp * dx, sp * dy, sp * dz, 0.f);
+    } else {
+        const int a = L.lanes_per_atom == 2 ? (lane & 31) : lane;
+        if (a < L.na) {
+            const float4 xa = S.xyz[a];
+#pragma unroll 1
+            for (int m = 0; m < L.nbr_words; m++) {
+                const uint32_t word = L.nbr[m * 64 + lane];
+#pragma unroll
+                for (int b = 0; b < 4; b++) {
+                    const uint32_t e = (word >> (8 * b)) & 255u;
+                    if (e != kNbrNone) {
+                        const int j = (int)(e & 63u);
+                        const float4 xj = S.xyz[j];
+                        const float dx = xa.x - xj.x, dy = xa.y - xj.y, dz = xa.z - xj.z;
+                        const float r2 = pair_r2(dx, dy, dz);
+                        if (r2 < kCutoff2) {
+                            const float2 es = pair_term(r2, xa.w + xj.w, e >> 6);
+                            if (a < j) e_fix += to_fixed(es.x);
+                            fnb.x = add_product(fnb.x, es.y, dx);
+                            fnb.y = add_product(fnb.y, es.y, dy);
+                            fnb.z = add_product(fnb.z, es.y, dz);
+                        }
+                    }
+                }
+            }
         }
     }
 
@@ -504,7 +606,7 @@ __device__ Energy eval_pose(const LigL &L, const WaveL &S, const PairRegs<PPL> &
         e_atom = E + w_atom;
     }
     const float e_inter = wave_sum(e_atom);
-    const float e_intra = wave_sum(e_pair);
+    const float e_intra = from_fixed(wave_sum_i64(e_fix));
     const float wall = wave_sum(w_atom);
     Energy out;
     out.inter = e_inter;
@@ -514,24 +616,36 @@ __device__ Energy eval_pose(const LigL &L, const WaveL &S, const PairRegs<PPL> &
     if (grad == nullptr) return out;
     wave_sync();
 
-    // (6) pair forces gathered per atom from its list (8 entries per 16-byte chunk;
-    //     two lanes per atom when there are at most 32 atoms), then the atom's total
+    // (6) pair lists: pair forces gathered per atom from its list (8 entries per
+    //     16-byte chunk); atom lists: the lane's own sum.  Two lanes per atom when
+    //     there are at most 32 atoms.  Then the atom's total
     //     force and its torque about the fragment origin; per-fragment sums over
     //     the fragment's contiguous atom range
     {
         float3 fp = make_float3(0.f, 0.f, 0.f);
-        for (int c = 0; c < L.n_chunks; c++) {
-            const uint4 q = L.plist[c * 64 + lane];
-            const uint32_t e[8] = {q.x & 0xffffu, q.x >> 16, q.y & 0xffffu, q.y >> 16,
-                                   q.z & 0xffffu, q.z >> 16, q.w & 0xffffu, q.w >> 16};
-            float4 v[8];
+        if constexpr (PPL > 0) {
+            for (int c = 0; c < L.n_chunks; c++) {
+                const uint4 q = L.plist[c * 64 + lane];
+                const uint32_t e[8] = {q.x & 0xffffu, q.x >> 16, q.y & 0xffffu, q.y >> 16,
+                                       q.z & 0xffffu, q.z >> 16, q.w & 0xffffu, q.w >> 16};
+                float4 v[8];
 #pragma unroll
-            for (int t = 0; t < 8; t++) v[t] = S.pf[e[t] & 0x7fffu];
+                for (int t = 0; t < 8; t++) v[t] = S.pf[e[t] & 0x7fffu];
 #pragma unroll
-            for (int t = 0; t < 8; t++) {
-                const float sg = (e[t] & 0x8000u) ? -1.f : 1.f;
-                fp = fp + sg * f3(v[t]);
+                for (int t = 0; t < 8; t++) {
+                    if (e[t] & 0x8000u) {
+                        fp.x = __fsub_rn(fp.x, v[t].x);
+                        fp.y = __fsub_rn(fp.y, v[t].y);
+                        fp.z = __fsub_rn(fp.z, v[t].z);
+                    } else {
+                        fp.x = __fadd_rn(fp.x, v[t].x);
+                        fp.y = __fadd_rn(fp.y, v[t].y);
+                        fp.z = __fadd_rn(fp.z, v[t].z);
+                    }
+                }
             }
+        } else {
+            fp = fnb;
         }
         if (L.lanes_per_atom == 2) {
             fp.x += __shfl_xor(fp.x, 32, 64);
@@ -656,51 +770,49 @@ __device__ inline Energy get_energy(const float *slot)
 // one-at-a-time search makes (speculative trials past the accepted one are not
 // counted).  Wave 0 owns the direction and the inverse-Hessian update.  The
 // final gradient is left in C.g.
-template <int PPL>
+template <int PPL, int NBW>
 __device__ Energy local_opt_group(const LigL &L, const Layout &lay, float *wave_base, const ChainL &C,
-                                  const PairRegs<PPL> &pr, const GridView &G, const SearchParams &P, float *x,
+                                  const IntraRegs<PPL, NBW> &pr, const GridView &G, const SearchParams &P, float *x,
                                   int &evals, int W)
 {
     const int lane = lane_id(), w = wave_id(), D = L.D;
     const WaveL S = make_wave(wave_base + w * lay.wave_words, lay);
-    if (w == 0) {
-        const Energy e = eval_pose(L, S, pr, G, x, C.g, P.wall_slope);
-        put_energy(C.et, e);
-        if (lane < D)
-            for (int c = 0; c < D; c++) C.H[lane * C.hs + c] = (c == lane) ? 1.f : 0.f;
-    }
-    __syncthreads();
-    Energy Ex = get_energy(C.et);
-    evals++;
-    for (int it = 0; it < P.bfgs_iters; it++) {
-        if (w == 0) {
-            float pl = 0.f, gl = 0.f;
-            if (lane < D) {
-                float acc = 0.f;
-#pragma unroll 4
-                for (int c = 0; c < D; c++) acc += C.H[lane * C.hs + c] * C.g[c];
-                pl = -acc;
-                gl = C.g[lane];
-                C.p[lane] = pl;
-            }
-            const float gp = wave_sum(pl * gl);
-            if (lane == 0) C.misc[kMiscGp] = gp;
-        }
-        __syncthreads();
-        const float gp = C.misc[kMiscGp];
-        int acc_slot = -1;
-        float alpha_acc = 0.f;
-        float alpha0 = 1.f;   // alpha of the round's first trial
-        for (int t0 = 0; t0 < P.ls_trials; t0 += W) {
-            const int t = t0 + w;
-            if (t < P.ls_trials) {
+    Energy Ex;
+    float gp = 0.f;
+    int it = 0;           // BFGS iterations done
+    int t0 = -1;          // first line-search trial of this round; -1: the start evaluation
+    float alpha0 = 1.f;   // alpha of the round's first trial
+    // Every evaluation of the local optimisation goes through the one call below
+    // (the start pose by wave 0, then one line-search trial per wave per round),
+    // so the kernel holds a single copy of the evaluation code.
+    for (;;) {
+        bool active;
+        if (t0 < 0) {
+            active = (w == 0);
+            if (active && lane < L.nx) S.trial[lane] = x[lane];
+        } else {
+            active = t0 + w < P.ls_trials;
+            if (active) {
                 float alpha = alpha0;
                 for (int q = 0; q < w; q++) alpha *= P.ls_shrink;
                 pose_step(L, x, alpha, C.p, S.trial);
-                put_energy(C.et + 4 * w, eval_pose(L, S, pr, G, S.trial, S.gt, P.wall_slope));
             }
-            __syncthreads();
-            float a = alpha0;
+        }
+        if (active) {
+            wave_sync();
+            put_energy(C.et + 4 * w, eval_pose(L, S, pr, G, S.trial, S.gt, P.wall_slope));
+        }
+        __syncthreads();
+        if (t0 < 0) {
+            Ex = get_energy(C.et);
+            evals++;
+            if (w == 0 && lane < D) {
+                C.g[lane] = S.gt[lane];
+                for (int c = 0; c < D; c++) C.H[lane * C.hs + c] = (c == lane) ? 1.f : 0.f;
+            }
+        } else {
+            int acc_slot = -1;
+            float a = alpha0, alpha_acc = 0.f;
             int v = 0;
             for (; v < W && t0 + v < P.ls_trials; v++) {
                 if (C.et[4 * v] <= Ex.total + P.armijo_c1 * a * gp) {
@@ -711,49 +823,73 @@ __device__ Energy local_opt_group(const LigL &L, const Layout &lay, float *wave_
                 a *= P.ls_shrink;
             }
             evals += acc_slot >= 0 ? acc_slot + 1 : v;
-            alpha0 = a;
-            if (acc_slot >= 0) break;
-            __syncthreads();   // this round's energies are read before the next round writes
-        }
-        if (acc_slot < 0) break;
-        const Energy Et = get_energy(C.et + 4 * acc_slot);
-        if (w == 0) {
-            const WaveL A = make_wave(wave_base + acc_slot * lay.wave_words, lay);
-            float sl = 0.f, yl = 0.f;
-            if (lane < D) {
-                const float gl = C.g[lane];
-                sl = alpha_acc * C.p[lane];
-                yl = A.gt[lane] - gl;
-                C.s[lane] = sl;
-                C.y[lane] = yl;
-                C.g[lane] = A.gt[lane];
+            if (acc_slot < 0) {
+                if (t0 + W >= P.ls_trials) break;   // every trial rejected: stop at x
+                alpha0 = a;
+                t0 += W;
+                __syncthreads();   // this round's energies are read before the next round writes
+                continue;
             }
-            if (lane < L.nx) x[lane] = A.trial[lane];
-            const float ys = wave_sum(sl * yl);
-            wave_sync();
-            if (ys > 0.f) {
-                const float rho = 1.f / ys;
-                float hy = 0.f;
+            const Energy Et = get_energy(C.et + 4 * acc_slot);
+            if (w == 0) {
+                const WaveL A = make_wave(wave_base + acc_slot * lay.wave_words, lay);
+                float sl = 0.f, yl = 0.f;
                 if (lane < D) {
-#pragma unroll 4
-                    for (int c = 0; c < D; c++) hy += C.H[lane * C.hs + c] * C.y[c];
-                    C.Hy[lane] = hy;
+                    const float gl = C.g[lane];
+                    sl = alpha_acc * C.p[lane];
+                    yl = A.gt[lane] - gl;
+                    C.s[lane] = sl;
+                    C.y[lane] = yl;
+                    C.g[lane] = A.gt[lane];
                 }
-                const float yHy = wave_sum(yl * hy);
+                if (lane < L.nx) x[lane] = A.trial[lane];
+                const float ys = wave_sum(sl * yl);
                 wave_sync();
-                if (lane < D) {
-                    const float a = rho * (1.f + rho * yHy) * sl, b = rho * sl, cc = rho * hy;
+                if (ys > 0.f) {
+                    const float rho = 1.f / ys;
+                    float hy = 0.f;
+                    if (lane < D) {
 #pragma unroll 4
-                    for (int c = 0; c < D; c++) {
-                        const float sc = C.s[c], hc = C.Hy[c];
-                        C.H[lane * C.hs + c] += a * sc - b * hc - cc * sc;
+                        for (int c = 0; c < D; c++) hy += C.H[lane * C.hs + c] * C.y[c];
+                        C.Hy[lane] = hy;
+                    }
+                    const float yHy = wave_sum(yl * hy);
+                    wave_sync();
+                    if (lane < D) {
+                        const float aa = rho * (1.f + rho * yHy) * sl, bb = rho * sl, cc = rho * hy;
+#pragma unroll 4
+                        for (int c = 0; c < D; c++) {
+                            const float sc = C.s[c], hc = C.Hy[c];
+                            C.H[lane * C.hs + c] += aa * sc - bb * hc - cc * sc;
+                        }
                     }
                 }
             }
+            Ex = Et;
+            it++;
         }
-        Ex = Et;
+        if (it >= P.bfgs_iters) break;
+        // direction of the next iteration, p = -H g (wave 0, which also wrote g and H)
+        if (w == 0) {
+            wave_sync();
+            float pl = 0.f, gl = 0.f;
+            if (lane < D) {
+                float acc = 0.f;
+#pragma unroll 4
+                for (int c = 0; c < D; c++) acc += C.H[lane * C.hs + c] * C.g[c];
+                pl = -acc;
+                gl = C.g[lane];
+                C.p[lane] = pl;
+            }
+            const float g_p = wave_sum(pl * gl);
+            if (lane == 0) C.misc[kMiscGp] = g_p;
+        }
         __syncthreads();
+        gp = C.misc[kMiscGp];
+        t0 = 0;
+        alpha0 = 1.f;
     }
+    __syncthreads();
     return Ex;
 }
 
@@ -767,23 +903,23 @@ __device__ inline void stage_blob(const uint32_t *blob, int words, uint32_t *lds
 // ---------------------------------------------------------------- kernels
 
 // One pose per wave (independent waves).
-template <int PPL>
-__global__ __launch_bounds__(256) void eval_kernel(const uint32_t *blob, int blob_words, GridView G, SearchParams P,
+template <int PPL, int NBW>
+__global__ __launch_bounds__(256) void eval_kernel(const uint32_t *__restrict__ blob, int blob_words, GridView G, SearchParams P,
                                                    const float *poses, int n, float *energy, float *grad, float *xyz)
 {
     extern __shared__ float4 lds4[];
     uint32_t *lds = reinterpret_cast<uint32_t *>(lds4);
     stage_blob(blob, blob_words, lds);
-    const LigL L = make_lig(lds);
-    const Layout lay = make_layout(L.na, L.nf, L.np, L.D, L.nx);
+    const LigL L = make_lig(lds, blob);
+    const Layout lay = make_layout(L.na, L.nf, PPL > 0 ? L.np : -1, L.D, L.nx);
     const WaveL S = make_wave(reinterpret_cast<float *>(lds) + blob_words + wave_id() * lay.wave_words, lay);
     const int idx = blockIdx.x * (blockDim.x >> 6) + wave_id();
     if (idx >= n) return;
     const int lane = lane_id();
-    if (lane == 0) S.pf[L.np] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (PPL > 0 && lane == 0) S.pf[L.np] = make_float4(0.f, 0.f, 0.f, 0.f);
     if (lane < L.nx) S.trial[lane] = poses[(long)idx * L.nx + lane];
     wave_sync();
-    const PairRegs<PPL> pr = load_pairs<PPL>(L);
+    const IntraRegs<PPL, NBW> pr = load_intra<PPL, NBW>(L);
     const Energy E = eval_pose(L, S, pr, G, S.trial, S.gt, P.wall_slope);
     if (lane == 0) {
         energy[4 * idx + 0] = E.total;
@@ -800,7 +936,7 @@ __global__ __launch_bounds__(256) void eval_kernel(const uint32_t *blob, int blo
 }
 
 // One pose per workgroup of W waves.
-template <int PPL>
+template <int PPL, int NBW>
 __global__ __launch_bounds__(256) void local_opt_kernel(const uint32_t *blob, int blob_words, GridView G,
                                                         SearchParams P, const float *poses_in, int n,
                                                         float *poses_out, float *energy, int *evals_out)
@@ -808,19 +944,19 @@ __global__ __launch_bounds__(256) void local_opt_kernel(const uint32_t *blob, in
     extern __shared__ float4 lds4[];
     uint32_t *lds = reinterpret_cast<uint32_t *>(lds4);
     stage_blob(blob, blob_words, lds);
-    const LigL L = make_lig(lds);
-    const Layout lay = make_layout(L.na, L.nf, L.np, L.D, L.nx);
+    const LigL L = make_lig(lds, blob);
+    const Layout lay = make_layout(L.na, L.nf, PPL > 0 ? L.np : -1, L.D, L.nx);
     float *cbase = reinterpret_cast<float *>(lds) + blob_words;
     const ChainL C = make_chain(cbase, lay);
     float *wbase = cbase + lay.chain_words;
     const int W = (int)(blockDim.x >> 6);
     const int idx = blockIdx.x;
     const int lane = lane_id(), w = wave_id();
-    if (lane == 0) make_wave(wbase + w * lay.wave_words, lay).pf[L.np] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (PPL > 0 && lane == 0) make_wave(wbase + w * lay.wave_words, lay).pf[L.np] = make_float4(0.f, 0.f, 0.f, 0.f);
     if (w == 0 && lane < L.nx) C.cur[lane] = poses_in[(long)idx * L.nx + lane];
     __syncthreads();
     int evals = 0;
-    const PairRegs<PPL> pr = load_pairs<PPL>(L);
+    const IntraRegs<PPL, NBW> pr = load_intra<PPL, NBW>(L);
     const Energy E = local_opt_group(L, lay, wbase, C, pr, G, P, C.cur, evals, W);
     if (w == 0) {
         if (lane < L.nx) poses_out[(long)idx * L.nx + lane] = C.cur[lane];
@@ -840,7 +976,7 @@ __global__ __launch_bounds__(256) void local_opt_kernel(const uint32_t *blob, in
 // steps of mutate -> BFGS -> Metropolis, keeping the lowest accepted energy, and
 // saves its state.  A chain that reaches its last step writes its record and the
 // coordinates of its best pose (for ranking).
-template <int PPL>
+template <int PPL, int NBW>
 __global__ __launch_bounds__(256) void tick_kernel(const uint32_t *arena, const ChainTask *tasks, const GridView *grids,
                                                    SearchParams P, int tick_steps, int init, float *state,
                                                    float *records, float4 *best_xyz)
@@ -851,19 +987,19 @@ __global__ __launch_bounds__(256) void tick_kernel(const uint32_t *arena, const 
     uint32_t *lds = reinterpret_cast<uint32_t *>(lds4);
     stage_blob(arena + t.blob_off, (int)t.blob_words, lds);
     const GridView G = grids[t.grid];
-    const LigL L = make_lig(lds);
-    const Layout lay = make_layout(L.na, L.nf, L.np, L.D, L.nx);
+    const LigL L = make_lig(lds, arena + t.blob_off);
+    const Layout lay = make_layout(L.na, L.nf, PPL > 0 ? L.np : -1, L.D, L.nx);
     float *cbase = reinterpret_cast<float *>(lds) + t.blob_words;
     const ChainL C = make_chain(cbase, lay);
     float *wbase = cbase + lay.chain_words;
     const int W = (int)(blockDim.x >> 6);
-    const PairRegs<PPL> pr = load_pairs<PPL>(L);
+    const IntraRegs<PPL, NBW> pr = load_intra<PPL, NBW>(L);
     const int lane = lane_id(), w = wave_id();
     const uint32_t c = t.chain;
     const uint64_t seed = (uint64_t)t.seed_lo | ((uint64_t)t.seed_hi << 32);
     float *st = state + (long)t.slot * kStWords;
     int *sti = reinterpret_cast<int *>(st);
-    if (lane == 0) make_wave(wbase + w * lay.wave_words, lay).pf[L.np] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (PPL > 0 && lane == 0) make_wave(wbase + w * lay.wave_words, lay).pf[L.np] = make_float4(0.f, 0.f, 0.f, 0.f);
 
     Energy Ex, Eb;
     int step, evals, accepted, lopts;
@@ -877,7 +1013,10 @@ __global__ __launch_bounds__(256) void tick_kernel(const uint32_t *arena, const 
             }
             wave_sync();
             if (lane < 3) {
-                C.cur[lane] = G.origin[lane] + C.misc[lane] * ((float)(G.n[lane] - 1) * G.h);
+                // select the axis without indexing the (scalar) map view by lane
+                const float org = lane == 0 ? G.origin[0] : (lane == 1 ? G.origin[1] : G.origin[2]);
+                const int nn = lane == 0 ? G.n[0] : (lane == 1 ? G.n[1] : G.n[2]);
+                C.cur[lane] = org + C.misc[lane] * ((float)(nn - 1) * G.h);
             } else if (lane < 7) {
                 const float u1 = C.misc[3], u2 = C.misc[4], u3 = C.misc[5];
                 const float s1 = sqrtf(1.f - u1), s2 = sqrtf(u1);
@@ -963,7 +1102,7 @@ __global__ __launch_bounds__(256) void tick_kernel(const uint32_t *arena, const 
     if (step < t.n_steps) return;
     // finished: record, and the coordinates of the best pose for RMSD clustering
     const WaveL S = make_wave(wbase, lay);
-    eval_pose(L, S, pr, G, C.best, nullptr, P.wall_slope);
+    frames(L, S, C.best);
     float *rec = records + (long)t.slot * kRecWords;
     if (lane < L.nx) rec[kRecPose + lane] = C.best[lane];
     if (lane == 0) {
@@ -975,7 +1114,10 @@ __global__ __launch_bounds__(256) void tick_kernel(const uint32_t *arena, const 
         reinterpret_cast<int *>(rec)[kRecAccepted] = accepted;
         reinterpret_cast<int *>(rec)[kRecLocalOpts] = lopts;
     }
-    if (lane < L.na) best_xyz[(long)t.slot * kXyzStride + lane] = S.xyz[lane];
+    if (lane < L.na) {
+        const float3 xb = atom_position(L, S, lane);
+        best_xyz[(long)t.slot * kXyzStride + lane] = make_float4(xb.x, xb.y, xb.z, 0.f);
+    }
 }
 
 // Ranking (post-processing), one workgroup per request: repeatedly take the
@@ -1052,28 +1194,46 @@ inline int pick_eval_waves(size_t blob_bytes, size_t wave_bytes)
 
 }  // namespace
 
+namespace {
+int pf_pairs(const LigHeader &h) { return h.intra_form == kFormAtoms ? -1 : h.n_pairs; }
+}  // namespace
+
 size_t search_lds_bytes(const LigHeader &h, int waves)
 {
-    const Layout c = make_layout(h.n_atoms, h.n_frags, h.n_pairs, 6 + h.n_tors, 7 + h.n_tors);
+    const Layout c = make_layout(h.n_atoms, h.n_frags, pf_pairs(h), 6 + h.n_tors, 7 + h.n_tors);
     return (size_t)h.total_words * 4 + (size_t)c.chain_words * 4 + (size_t)waves * c.wave_words * 4;
 }
+
+int search_class(const LigHeader &h)
+{
+    if (h.intra_form == kFormAtoms) return 3;
+    return h.n_pairs <= 512 ? 0 : (h.n_pairs <= 1024 ? 1 : 2);
+}
+
+// One switch over the six kernel variants: F(PPL, NBW).
+#define DSDP_DISPATCH(cls, F)             \
+    switch (cls) {                        \
+    case 0: F(8, 0); break;               \
+    case 1: F(16, 0); break;              \
+    case 2: F(32, 0); break;              \
+    case 3: F(0, 1); break;               \
+    default: return hipErrorInvalidValue; \
+    }
 
 hipError_t launch_eval(const uint32_t *blob, int blob_words, const LigHeader &h, const GridView &g,
                        const SearchParams &p, const float *poses, int n, float *energy, float *grad, float *xyz,
                        hipStream_t stream)
 {
     if (n <= 0) return hipSuccess;
-    const Layout c = make_layout(h.n_atoms, h.n_frags, h.n_pairs, 6 + h.n_tors, 7 + h.n_tors);
+    const Layout c = make_layout(h.n_atoms, h.n_frags, pf_pairs(h), 6 + h.n_tors, 7 + h.n_tors);
     const size_t wb = (size_t)c.wave_words * 4, bb = (size_t)blob_words * 4;
     const int w = pick_eval_waves(bb, wb);
     const int blocks = (n + w - 1) / w;
     const size_t lds = bb + w * wb;
-    if (h.n_pairs <= 512)
-        eval_kernel<8><<<blocks, 64 * w, lds, stream>>>(blob, blob_words, g, p, poses, n, energy, grad, xyz);
-    else if (h.n_pairs <= 1024)
-        eval_kernel<16><<<blocks, 64 * w, lds, stream>>>(blob, blob_words, g, p, poses, n, energy, grad, xyz);
-    else
-        eval_kernel<32><<<blocks, 64 * w, lds, stream>>>(blob, blob_words, g, p, poses, n, energy, grad, xyz);
+#define DSDP_EVAL(A, B) \
+    eval_kernel<A, B><<<blocks, 64 * w, lds, stream>>>(blob, blob_words, g, p, poses, n, energy, grad, xyz)
+    DSDP_DISPATCH(search_class(h), DSDP_EVAL)
+#undef DSDP_EVAL
     return hipGetLastError();
 }
 
@@ -1084,37 +1244,29 @@ hipError_t launch_local_opt(const uint32_t *blob, int blob_words, const LigHeade
     if (n <= 0) return hipSuccess;
     if (waves < 1 || waves > kMaxWaves) return hipErrorInvalidValue;
     const size_t lds = search_lds_bytes(h, waves);
-    if (h.n_pairs <= 512)
-        local_opt_kernel<8><<<n, 64 * waves, lds, stream>>>(blob, blob_words, g, p, poses_in, n, poses_out, energy, evals);
-    else if (h.n_pairs <= 1024)
-        local_opt_kernel<16><<<n, 64 * waves, lds, stream>>>(blob, blob_words, g, p, poses_in, n, poses_out, energy,
-                                                             evals);
-    else
-        local_opt_kernel<32><<<n, 64 * waves, lds, stream>>>(blob, blob_words, g, p, poses_in, n, poses_out, energy,
-                                                             evals);
+#define DSDP_LOPT(A, B)                                                                                              \
+    local_opt_kernel<A, B><<<n, 64 * waves, lds, stream>>>(blob, blob_words, g, p, poses_in, n, poses_out, energy, \
+                                                           evals)
+    DSDP_DISPATCH(search_class(h), DSDP_LOPT)
+#undef DSDP_LOPT
     return hipGetLastError();
 }
 
-int pair_slots_class(int n_pairs) { return n_pairs <= 512 ? 8 : (n_pairs <= 1024 ? 16 : 32); }
-
-hipError_t launch_tick(int ppl, int waves, size_t lds_bytes, const uint32_t *arena, const ChainTask *tasks,
+hipError_t launch_tick(int cls, int waves, size_t lds_bytes, const uint32_t *arena, const ChainTask *tasks,
                        int n_tasks, const GridView *grids, const SearchParams &p, int tick_steps, int init,
                        float *state, float *records, float4 *best_xyz, hipStream_t stream)
 {
     if (n_tasks <= 0) return hipSuccess;
     if (waves < 1 || waves > kMaxWaves) return hipErrorInvalidValue;
     const dim3 grid(n_tasks), block(64 * waves);
-    if (ppl == 8)
-        tick_kernel<8><<<grid, block, lds_bytes, stream>>>(arena, tasks, grids, p, tick_steps, init, state, records,
-                                                           best_xyz);
-    else if (ppl == 16)
-        tick_kernel<16><<<grid, block, lds_bytes, stream>>>(arena, tasks, grids, p, tick_steps, init, state, records,
-                                                            best_xyz);
-    else
-        tick_kernel<32><<<grid, block, lds_bytes, stream>>>(arena, tasks, grids, p, tick_steps, init, state, records,
-                                                            best_xyz);
+#define DSDP_TICK(A, B)                                                                                          \
+    tick_kernel<A, B><<<grid, block, lds_bytes, stream>>>(arena, tasks, grids, p, tick_steps, init, state, records, \
+                                                          best_xyz)
+    DSDP_DISPATCH(cls, DSDP_TICK)
+#undef DSDP_TICK
     return hipGetLastError();
 }
+#undef DSDP_DISPATCH
 
 hipError_t launch_rank(const float *records, const float4 *best_xyz, const RankSeg *segs, int n_segs, int max_chains,
                        float rmsd_cut, int *sel, hipStream_t stream)

@@ -100,12 +100,13 @@ def test_grid_empty_receptor():
     assert np.all(g.maps_host() == 0)
 
 
-def eval_case(ref, g, lig, n, rng, margin, label):
+def eval_case(ref, g, lig, n, rng, margin, label, form=0):
     gc = _gc()
+    import paper_2303_09916_amd as D
     L = O.LigandModel(lig)
     lo, hi = ref.origin, ref.origin + (ref.n - 1) * ref.h
     P = random_poses(L.n_tors, n, lo, hi, rng, margin=margin)
-    E, G, X = gc.gpu_eval(g, lig, P)
+    E, G, X = gc.gpu_eval(g, lig, P, D.dsdp_params_default(intra_form=form))
     worstE = worstG = 0.0
     for k in range(n):
         Eo, go, parts, xo, mass = L.eval(ref, P[k].astype(np.float64), want_mass=True)
@@ -122,8 +123,10 @@ def eval_case(ref, g, lig, n, rng, margin, label):
     log(f"[{label}] n={n} worst |dE|/tol = {worstE:.3g}, worst |dg|/tol = {worstG:.3g}")
 
 
+# both layouts of the intra-ligand term (pair lists, atom lists) on every shape
+@pytest.mark.parametrize("form", [1, 2])
 @pytest.mark.parametrize("shape", [(20, 4), (32, 7), (60, 15), (12, 0), (1, 0), (64, 31)])
-def test_eval_parity(cfg1, shape):
+def test_eval_parity(cfg1, shape, form):
     cfg, _, _ = cfg1
     gc = _gc()
     rec, box = cfg["receptor"], box32(cfg["box"])
@@ -132,11 +135,12 @@ def test_eval_parity(cfg1, shape):
     na, nt = shape
     lig = make_ligand(na, nt, seed=na + nt, palette=PALETTE_T9)
     rng = np.random.default_rng(na)
-    eval_case(ref, g, lig, 150, rng, 0.0, f"eval {na}/{lig.n_torsions} inside")
-    eval_case(ref, g, lig, 50, rng, 6.0, f"eval {na}/{lig.n_torsions} walls")
+    eval_case(ref, g, lig, 150, rng, 0.0, f"eval {na}/{lig.n_torsions} form {form} inside", form)
+    eval_case(ref, g, lig, 50, rng, 6.0, f"eval {na}/{lig.n_torsions} form {form} walls", form)
 
 
-def test_local_opt_endpoint_parity_short(cfg1):
+@pytest.mark.parametrize("form", [1, 2])
+def test_local_opt_endpoint_parity_short(cfg1, form):
     """Two BFGS iterations: the oracle's own endpoint spread under 1e-7 relative
     input noise is ~2e-5 A here, so GPU endpoints must sit within 1e-3 A."""
     cfg, ref, g = cfg1
@@ -145,7 +149,7 @@ def test_local_opt_endpoint_parity_short(cfg1):
     L = O.LigandModel(lig)
     import paper_2303_09916_amd as D
     prm_o = O.default_params(bfgs_iters=2)
-    prm_g = D.dsdp_params_default(bfgs_iters=2)
+    prm_g = D.dsdp_params_default(bfgs_iters=2, intra_form=form)
     rng = np.random.default_rng(7)
     lo, hi = ref.origin, ref.origin + (ref.n - 1) * ref.h
     P = random_poses(L.n_tors, 300, lo, hi, rng)
@@ -212,22 +216,25 @@ def test_local_opt_endpoint_spread_default(cfg1):
     assert ks_e > 0.01
 
 
-def test_dock_deterministic_and_chain_independent(cfg1):
+@pytest.mark.parametrize("form", [1, 2])
+def test_dock_deterministic_and_chain_independent(cfg1, form):
     """A chain's result is bitwise the same across runs, chain counts and the
-    number of waves per chain (concurrent line-search trials)."""
+    number of waves per chain (concurrent line-search trials), in both layouts
+    of the intra-ligand term."""
     cfg, ref, g = cfg1
     gc = _gc()
     import paper_2303_09916_amd as D
     lig = cfg["ligands"][0]
-    a = gc.gpu_dock(g, lig, 32, 20, 3, 5)
-    b = gc.gpu_dock(g, lig, 32, 20, 3, 5)
-    c = gc.gpu_dock(g, lig, 96, 20, 3, 5)
+    prm = D.dsdp_params_default(intra_form=form)
+    a = gc.gpu_dock(g, lig, 32, 20, 3, 5, prm)
+    b = gc.gpu_dock(g, lig, 32, 20, 3, 5, prm)
+    c = gc.gpu_dock(g, lig, 96, 20, 3, 5, prm)
     for k in range(32):
         assert bytes(a[2][k]) == bytes(b[2][k])
         assert bytes(a[2][k]) == bytes(c[2][k])
     assert [bytes(p) for p in a[0]] == [bytes(p) for p in b[0]]
     for w in (1, 2, 3, 4):
-        d = gc.gpu_dock(g, lig, 32, 20, 3, 5, D.dsdp_params_default(waves_per_chain=w))
+        d = gc.gpu_dock(g, lig, 32, 20, 3, 5, D.dsdp_params_default(waves_per_chain=w, intra_form=form))
         for k in range(32):
             assert bytes(a[2][k]) == bytes(d[2][k]), (w, k)
         assert d[3].pose_evals == a[3].pose_evals
@@ -306,3 +313,28 @@ def test_edge_cases(cfg1):
     if not set(lig.types.tolist()) <= set(cfg["map_types"]):
         with pytest.raises(D.DsdpError):
             gc.gpu_dock(g, lig, 4, 2, 1, 2)
+
+
+@pytest.mark.parametrize("shape", [(20, 4), (32, 7), (45, 12), (60, 15), (64, 31), (12, 0), (2, 1)])
+def test_intra_layouts_bitwise_equal(cfg1, shape):
+    """The two device layouts of the intra-ligand term (pair lists, atom lists)
+    give the same bits: energies, gradients, coordinates and whole searches."""
+    cfg, ref, _ = cfg1
+    gc = _gc()
+    import paper_2303_09916_amd as D
+    rec, box = cfg["receptor"], box32(cfg["box"])
+    g = gc.GpuGrid(rec.xyz, rec.types, box, list(PALETTE_T9))
+    na, nt = shape
+    lig = make_ligand(na, nt, seed=3 * na + nt, palette=PALETTE_T9)
+    L = O.LigandModel(lig)
+    lo, hi = ref.origin, ref.origin + (ref.n - 1) * ref.h
+    P = random_poses(L.n_tors, 64, lo, hi, np.random.default_rng(na), margin=2.0)
+    r1 = gc.gpu_eval(g, lig, P, D.dsdp_params_default(intra_form=1))
+    r2 = gc.gpu_eval(g, lig, P, D.dsdp_params_default(intra_form=2))
+    for name, a, b in zip(("energy", "gradient", "coordinates"), r1, r2):
+        diff = np.argwhere(a.view(np.uint32) != b.view(np.uint32))
+        assert len(diff) == 0, (name, len(diff), diff[:4].tolist(), a[tuple(diff[0])], b[tuple(diff[0])])
+    d1 = gc.gpu_dock(g, lig, 24, 8, 11, 4, D.dsdp_params_default(intra_form=1))
+    d2 = gc.gpu_dock(g, lig, 24, 8, 11, 4, D.dsdp_params_default(intra_form=2))
+    assert [bytes(p) for p in d1[2]] == [bytes(p) for p in d2[2]]
+    assert [bytes(p) for p in d1[0]] == [bytes(p) for p in d2[0]]
