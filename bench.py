@@ -112,7 +112,7 @@ def make_inputs(args):
     with mp.get_context("fork").Pool(workers) as pool:
         if args.batch_ligands > 0:
             inp["cfg4"] = make_config(4, n_ligands=args.batch_ligands, pmap=pool.map)
-        n_req = args.serve_requests + args.serve_requests_below
+        n_req = args.serve_requests + args.serve_requests_below if args.serve_requests > 0 else 0
         if n_req > 0:
             c5 = make_config(5, n_ligands=n_req, pmap=pool.map)
             c5["request_ligands"] = pool.map(request_ligand_job, [(c5["shapes"][k], k) for k in range(n_req)])

@@ -178,13 +178,18 @@ __device__ __forceinline__ float3 ball(float u1, float u2, float u3)
 // at a kink the left-hand slope is taken.
 __device__ __forceinline__ float2 vina_pair(float d, float wh, float wb)
 {
-    const float g1 = __expf(-4.0f * d * d);
+    // The fused multiply-adds are written out and no others are formed: the two
+    // intra-ligand layouts inline this in different surroundings and must round
+    // alike.
+#pragma clang fp contract(off)
+    const float g1 = __expf(-4.0f * (d * d));
     const float b = d - 3.0f;
-    const float g2 = __expf(-0.25f * b * b);
+    const float g2 = __expf(-0.25f * (b * b));
     const float dn = fminf(d, 0.0f);
-    float e = kWGauss1 * g1 + kWGauss2 * g2 + kWRepulsion * dn * dn;
-    float de = kWGauss1 * g1 * (-8.0f * d) + kWGauss2 * g2 * (-0.5f * b) + kWRepulsion * 2.0f * dn;
-    e += wh * fminf(fmaxf(1.5f - d, 0.0f), 1.0f) + wb * fminf(fmaxf(-d * (1.0f / 0.7f), 0.0f), 1.0f);
+    const float w1 = kWGauss1 * g1, w2 = kWGauss2 * g2;
+    float e = fmaf(kWRepulsion * dn, dn, fmaf(w2, 1.0f, w1));
+    float de = fmaf(kWRepulsion * 2.0f, dn, fmaf(w2, -0.5f * b, w1 * (-8.0f * d)));
+    e = fmaf(wh, fminf(fmaxf(1.5f - d, 0.0f), 1.0f), fmaf(wb, fminf(fmaxf(-d * (1.0f / 0.7f), 0.0f), 1.0f), e));
     de += ((d > 0.5f && d <= 1.5f) ? -wh : 0.0f) + ((d > -0.7f && d <= 0.0f) ? -wb * (1.0f / 0.7f) : 0.0f);
     return make_float2(e, de);
 }
@@ -194,18 +199,18 @@ __device__ __forceinline__ float pair_wb(uint32_t flags) { return (flags & kPair
 // Squared distance and the pair's (energy, dE/dr / r) for radius sum rsum and
 // class flags: one definition for both intra-ligand layouts, so that both
 // round alike.
-__device__ __forceinline__ float pair_r2(float dx, float dy, float dz) { return dx * dx + dy * dy + dz * dz; }
+__device__ __forceinline__ float pair_r2(float dx, float dy, float dz)
+{
+    return fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+}
 __device__ __forceinline__ float2 pair_term(float r2, float rsum, uint32_t flags)
 {
+#pragma clang fp contract(off)
     const float inv_r = r2 > 1e-18f ? rsqrtf(r2) : 0.f;
-    const float2 ed = vina_pair(r2 * inv_r - rsum, pair_wh(flags), pair_wb(flags));
+    const float2 ed = vina_pair(fmaf(r2, inv_r, -rsum), pair_wh(flags), pair_wb(flags));
     return make_float2(ed.x, ed.y * inv_r);
 }
 
-// Intra-ligand energies are summed as integers in units of 2^-32 kcal/mol:
-// the sum then does not depend on the order of the terms.
-__device__ __forceinline__ long long to_fixed(float e) { return __float2ll_rn(e * 4294967296.0f); }
-__device__ __forceinline__ float from_fixed(long long v) { return (float)((double)v * (1.0 / 4294967296.0)); }
 // s * d rounded on its own, and acc + s * d with the product rounded before the
 // addition (no fused multiply-add): the pair-list layout stores the product and
 // adds it later, and the atom-list layout must round the same way.
@@ -221,12 +226,6 @@ __device__ __forceinline__ float add_product(float acc, float s, float d)
     return acc + p;
 }
 
-__device__ __forceinline__ long long wave_sum_i64(long long v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
 
 // ---------------------------------------------------------------- LDS layout
 struct LigL {
@@ -455,7 +454,7 @@ __device__ inline float3 atom_position(const LigL &L, const WaveL &S, int a)
                        o.z + r2.x * loc.x + r2.y * loc.y + r2.z * loc.z);
 }
 
-// Energy of `pose` (LDS, wave-uniform) and, if grad != nullptr, its gradient in
+// Energy of `pose` (LDS, wave-uniform) and its gradient in
 // the tangent coordinates written to grad[0..D) (LDS).  Coordinates are left in
 // S.xyz.  Every lane returns the same values.
 template <int PPL, int NBW>
@@ -530,10 +529,11 @@ __device__ Energy eval_pose(const LigL &L, const WaveL &S, const IntraRegs<PPL, 
     // (4) intra-ligand terms.  Pair lists: PPL pairs per lane held in registers
     //     (pair lane + 64 k), each pair's force stored once for the atoms to
     //     gather.  Atom lists: every pair of the lane's atom (or half of them),
-    //     evaluated from the atom's side, the force kept in registers.  Energies
-    //     are summed in fixed point (each pair once), forces per atom in the
-    //     same order with the same roundings, so both layouts give the same bits.
-    long long e_fix = 0;
+    //     evaluated from the atom's side, the force kept in registers.  Both
+    //     layouts add, per atom lane and in the order of the atom's list, the
+    //     pair forces and (at the lower-numbered atom) the pair energies, with
+    //     the same roundings, so they give the same bits.
+    float e_lane = 0.f;   // atom lists: this lane's share of the intra energy
     float3 fnb = make_float3(0.f, 0.f, 0.f);
     if constexpr (PPL > 0) {
         const int slots = (L.np + 63) >> 6;
@@ -545,14 +545,14 @@ __device__ Energy eval_pose(const LigL &L, const WaveL &S, const IntraRegs<PPL, 
                 const float4 xi = S.xyz[i], xj = S.xyz[j];
                 const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
                 const float r2 = pair_r2(dx, dy, dz);
-                float sp = 0.f;
+                float sp = 0.f, ep = 0.f;
                 if (!(pw & kPairNone) && r2 < kCutoff2) {
                     const float2 es = pair_term(r2, pr.rs[k], pw >> 16);
-                    e_fix += to_fixed(es.x);
+                    ep = es.x;
                     sp = es.y;
                 }
-                if (grad != nullptr && !(pw & kPairNone))
-                    S.pf[lane + 64 * k] = make_float4(mul_rounded(sp, dx), mul_rounded(sp, dy), mul_rounded(sp, dz), 0.f);
+                if (!(pw & kPairNone))
+                    S.pf[lane + 64 * k] = make_float4(mul_rounded(sp, dx), mul_rounded(sp, dy), mul_rounded(sp, dz), ep);
             }
         }
     } else {
@@ -572,7 +572,7 @@ __device__ Energy eval_pose(const LigL &L, const WaveL &S, const IntraRegs<PPL, 
                         const float r2 = pair_r2(dx, dy, dz);
                         if (r2 < kCutoff2) {
                             const float2 es = pair_term(r2, xa.w + xj.w, e >> 6);
-                            if (a < j) e_fix += to_fixed(es.x);
+                            if (a < j) e_lane += es.x;
                             fnb.x = add_product(fnb.x, es.y, dx);
                             fnb.y = add_product(fnb.y, es.y, dy);
                             fnb.z = add_product(fnb.z, es.y, dz);
@@ -606,16 +606,10 @@ __device__ Energy eval_pose(const LigL &L, const WaveL &S, const IntraRegs<PPL, 
         e_atom = E + w_atom;
     }
     const float e_inter = wave_sum(e_atom);
-    const float e_intra = from_fixed(wave_sum_i64(e_fix));
     const float wall = wave_sum(w_atom);
-    Energy out;
-    out.inter = e_inter;
-    out.intra = e_intra;
-    out.wall = wall;
-    out.total = e_inter + e_intra;
-    if (grad == nullptr) return out;
     wave_sync();
 
+    float e_intra = 0.f;
     // (6) pair lists: pair forces gathered per atom from its list (8 entries per
     //     16-byte chunk); atom lists: the lane's own sum.  Two lanes per atom when
     //     there are at most 32 atoms.  Then the atom's total
@@ -633,20 +627,18 @@ __device__ Energy eval_pose(const LigL &L, const WaveL &S, const IntraRegs<PPL, 
                 for (int t = 0; t < 8; t++) v[t] = S.pf[e[t] & 0x7fffu];
 #pragma unroll
                 for (int t = 0; t < 8; t++) {
-                    if (e[t] & 0x8000u) {
-                        fp.x = __fsub_rn(fp.x, v[t].x);
-                        fp.y = __fsub_rn(fp.y, v[t].y);
-                        fp.z = __fsub_rn(fp.z, v[t].z);
-                    } else {
-                        fp.x = __fadd_rn(fp.x, v[t].x);
-                        fp.y = __fadd_rn(fp.y, v[t].y);
-                        fp.z = __fadd_rn(fp.z, v[t].z);
-                    }
+                    // sg * v is exact, so this rounds once, as fp +/- v does;
+                    // the pair's energy counts at its first (lower-numbered) atom
+                    const bool second = (e[t] & 0x8000u) != 0;
+                    const float sg = second ? -1.f : 1.f;
+                    fp = fp + sg * f3(v[t]);
+                    e_lane += second ? 0.f : v[t].w;
                 }
             }
         } else {
             fp = fnb;
         }
+        e_intra = wave_sum(e_lane);
         if (L.lanes_per_atom == 2) {
             fp.x += __shfl_xor(fp.x, 32, 64);
             fp.y += __shfl_xor(fp.y, 32, 64);
@@ -721,6 +713,11 @@ __device__ Energy eval_pose(const LigL &L, const WaveL &S, const IntraRegs<PPL, 
         }
     }
     wave_sync();
+    Energy out;
+    out.inter = e_inter;
+    out.intra = e_intra;
+    out.wall = wall;
+    out.total = e_inter + e_intra;
     return out;
 }
 
