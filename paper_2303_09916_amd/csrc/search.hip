@@ -250,8 +250,7 @@ struct WaveL {
     float4 *xyz;
     float4 *pf;            // [np + 1] force of each pair on its first atom; slot np stays 0
     float4 *af, *at;       // [na] total force and torque (about the fragment origin) per atom
-    float *ft;             // [6][nf4] per-fragment force and torque (planes)
-    int nf4;
+    float4 *ft;            // [2][nf]: per-fragment force, then torque about the fragment origin
     float4 *R;       // [nf][4]: rows of R_k, then origin o_k
     float4 *Q;       // [nf][3]: rotation of fragment k relative to its parent (root: R(q))
     float *trial;    // [NXp]: this wave's trial pose
@@ -274,7 +273,7 @@ constexpr int kMiscGp = 40;      // slot of g.p in misc
 __host__ __device__ inline int rup4(int v) { return (v + 3) & ~3; }
 
 struct Layout {
-    int xyz, pf, af, at, R, Q, FT, nf4, trial, gt, wave_words;  // per-wave offsets
+    int xyz, pf, af, at, R, Q, FT, trial, gt, wave_words;  // per-wave offsets
     int vec, H, hs, pose, et, misc, chain_words, Dp, NXp;     // per-chain offsets
 };
 __host__ __device__ inline Layout make_layout(int na, int nf, int np, int D, int nx)
@@ -289,8 +288,7 @@ __host__ __device__ inline Layout make_layout(int na, int nf, int np, int D, int
     c.at = w; w += 4 * na;
     c.R = w; w += 16 * nf;
     c.Q = w; w += 12 * nf;
-    c.nf4 = rup4(nf);
-    c.FT = w; w += 6 * c.nf4;
+    c.FT = w; w += 8 * nf;
     c.trial = w; w += c.NXp;
     c.gt = w; w += c.Dp;
     c.wave_words = w;
@@ -314,8 +312,7 @@ __device__ inline WaveL make_wave(float *base, const Layout &c)
     S.at = reinterpret_cast<float4 *>(base + c.at);
     S.R = reinterpret_cast<float4 *>(base + c.R);
     S.Q = reinterpret_cast<float4 *>(base + c.Q);
-    S.ft = base + c.FT;
-    S.nf4 = c.nf4;
+    S.ft = reinterpret_cast<float4 *>(base + c.FT);
     S.trial = base + c.trial;
     S.gt = base + c.gt;
     return S;
@@ -653,63 +650,57 @@ __device__ Energy eval_pose(const LigL &L, const WaveL &S, const IntraRegs<PPL, 
         }
     }
     wave_sync();
+    // per-fragment sums over the fragment's contiguous atom range, in atom order;
+    // the loads of four atoms are issued together
     if (lane < L.nf) {
         float3 F = make_float3(0.f, 0.f, 0.f), Tq = make_float3(0.f, 0.f, 0.f);
         const int a0 = L.frag_start[lane], a1 = L.frag_start[lane + 1];
-        for (int a = a0; a < a1; a++) {
-            F = F + f3(S.af[a]);
-            Tq = Tq + f3(S.at[a]);
+        for (int a = a0; a < a1; a += 4) {
+            float4 fv[4], tv[4];
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const int b = min(a + q, a1 - 1);
+                fv[q] = S.af[b];
+                tv[q] = S.at[b];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; q++)
+                if (a + q < a1) {
+                    F = F + f3(fv[q]);
+                    Tq = Tq + f3(tv[q]);
+                }
         }
-        S.ft[lane] = F.x;
-        S.ft[S.nf4 + lane] = F.y;
-        S.ft[2 * S.nf4 + lane] = F.z;
-        S.ft[3 * S.nf4 + lane] = Tq.x;
-        S.ft[4 * S.nf4 + lane] = Tq.y;
-        S.ft[5 * S.nf4 + lane] = Tq.z;
+        S.ft[lane] = make_float4(F.x, F.y, F.z, 0.f);
+        S.ft[L.nf + lane] = make_float4(Tq.x, Tq.y, Tq.z, 0.f);
     }
     wave_sync();
 
-    // (7) subtree sums, deepest level first: each fragment adds its force and its
-    //     torque moved to the parent's origin, tau + (o_k - o_parent) x F, into
-    //     its parent; afterwards fragment k holds F_sub(k) and tau_sub(k) about o_k.
+    // (7) subtree sums from the subtree masks: fragment k's force and its torque
+    //     about o_k over every fragment m of its subtree (its descendants and
+    //     itself), F_sub(k) = sum F_m and tau_sub(k) = sum tau_m + (o_m - o_k) x F_m.
     //     dE/dp = F_sub(0), dE/dw = tau_sub(0) (o_0 = p), dE/dtheta_k = u_k . tau_sub(k)
-    {
-        int my_depth = -1, my_parent = -1;
-        if (lane < L.nf) {
-            const uint32_t pw = __float_as_uint(L.fu[lane].w);
-            my_parent = (int)(pw & 0xffffu) - 1;
-            my_depth = (int)(pw >> 16);
-        }
-        for (int d = L.maxdepth; d >= 1; d--) {
-            if (my_depth == d) {
-                const float3 Fk = make_float3(S.ft[lane], S.ft[S.nf4 + lane], S.ft[2 * S.nf4 + lane]);
-                const float3 Tk = make_float3(S.ft[3 * S.nf4 + lane], S.ft[4 * S.nf4 + lane], S.ft[5 * S.nf4 + lane]);
-                const float3 lever = f3(S.R[4 * lane + 3]) - f3(S.R[4 * my_parent + 3]);
-                const float3 Tp = Tk + cross3(lever, Fk);
-                float *fp = S.ft + my_parent;
-                atomicAdd(fp, Fk.x);
-                atomicAdd(fp + S.nf4, Fk.y);
-                atomicAdd(fp + 2 * S.nf4, Fk.z);
-                atomicAdd(fp + 3 * S.nf4, Tp.x);
-                atomicAdd(fp + 4 * S.nf4, Tp.y);
-                atomicAdd(fp + 5 * S.nf4, Tp.z);
+    if (lane < L.nf) {
+        const uint32_t mask = __float_as_uint(L.foff[lane].w);
+        const float3 ok = f3(S.R[4 * lane + 3]);
+        float3 F = make_float3(0.f, 0.f, 0.f), Tq = make_float3(0.f, 0.f, 0.f);
+#pragma unroll 4
+        for (int m = 0; m < L.nf; m++) {
+            if (mask & (1u << m)) {
+                const float3 Fm = f3(S.ft[m]), Tm = f3(S.ft[L.nf + m]);
+                F = F + Fm;
+                Tq = Tq + Tm + cross3(f3(S.R[4 * m + 3]) - ok, Fm);
             }
-            wave_sync();
         }
-        if (lane < L.nf) {
-            const float3 F = make_float3(S.ft[lane], S.ft[S.nf4 + lane], S.ft[2 * S.nf4 + lane]);
-            const float3 Tq = make_float3(S.ft[3 * S.nf4 + lane], S.ft[4 * S.nf4 + lane], S.ft[5 * S.nf4 + lane]);
-            if (lane == 0) {
-                grad[0] = F.x; grad[1] = F.y; grad[2] = F.z;
-                grad[3] = Tq.x; grad[4] = Tq.y; grad[5] = Tq.z;
-            } else {
-                const float4 uref = L.fu[lane];
-                const float4 r0 = S.R[4 * lane], r1 = S.R[4 * lane + 1], r2 = S.R[4 * lane + 2];
-                const float3 u = make_float3(r0.x * uref.x + r0.y * uref.y + r0.z * uref.z,
-                                             r1.x * uref.x + r1.y * uref.y + r1.z * uref.z,
-                                             r2.x * uref.x + r2.y * uref.y + r2.z * uref.z);
-                grad[6 + lane - 1] = dot3(u, Tq);
-            }
+        if (lane == 0) {
+            grad[0] = F.x; grad[1] = F.y; grad[2] = F.z;
+            grad[3] = Tq.x; grad[4] = Tq.y; grad[5] = Tq.z;
+        } else {
+            const float4 uref = L.fu[lane];
+            const float4 r0 = S.R[4 * lane], r1 = S.R[4 * lane + 1], r2 = S.R[4 * lane + 2];
+            const float3 u = make_float3(r0.x * uref.x + r0.y * uref.y + r0.z * uref.z,
+                                         r1.x * uref.x + r1.y * uref.y + r1.z * uref.z,
+                                         r2.x * uref.x + r2.y * uref.y + r2.z * uref.z);
+            grad[6 + lane - 1] = dot3(u, Tq);
         }
     }
     wave_sync();
