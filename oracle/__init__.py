@@ -32,7 +32,11 @@ _up = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
 class Params(C.Structure):
     _fields_ = [("temperature", C.c_double), ("wall_slope", C.c_double), ("rmsd_cluster", C.c_double),
                 ("trans_amp", C.c_double), ("bfgs_iters", C.c_int), ("ls_trials", C.c_int),
-                ("ls_shrink", C.c_double), ("armijo_c1", C.c_double)]
+                ("ls_shrink", C.c_double), ("armijo_c1", C.c_double), ("optimizer", C.c_int),
+                ("bb_iters", C.c_int), ("bb_step0", C.c_double), ("bb_step_max", C.c_double)]
+
+
+OPT_BFGS, OPT_BB = 0, 1
 
 
 OBJECTIVE = C.CFUNCTYPE(C.c_double, C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double))
@@ -75,6 +79,8 @@ def lib():
                                      C.POINTER(C.c_double)]),
         "orc_bfgs_plain": (C.c_long, [OBJECTIVE, C.c_int, _dp, C.POINTER(C.c_double), _dp, C.c_int, C.c_int,
                                       C.c_double, C.c_double]),
+        "orc_bb_plain": (C.c_long, [OBJECTIVE, C.c_int, _dp, C.POINTER(C.c_double), _dp, C.c_int, C.c_double,
+                                    C.c_double]),
         "orc_philox": (None, [_up, _up, _up]),
         "orc_ball": (None, [C.c_double, C.c_double, C.c_double, _dp]),
         "orc_shoemake": (None, [C.c_double, C.c_double, C.c_double, _dp]),
@@ -367,3 +373,23 @@ def score(e_inter, n_tors):
 
 def max_threads():
     return lib().orc_max_threads()
+
+
+def bb_plain(fun, x0, iters=100, step0=1e-2, step_max=1.0):
+    """Oracle Barzilai-Borwein on a plain function fun(x) -> (f, grad) (textbook pins).
+    Returns (best x, best f, gradient there, evaluations)."""
+    D = len(x0)
+
+    def cb(_ctx, xp, gp):
+        x = np.ctypeslib.as_array(xp, shape=(D,)).copy()
+        f, g = fun(x)
+        ga = np.ctypeslib.as_array(gp, shape=(D,))
+        ga[:] = g
+        return float(f)
+
+    cfun = OBJECTIVE(cb)
+    x = np.array(x0, dtype=np.float64)
+    fx = C.c_double()
+    g = np.zeros(D)
+    n = lib().orc_bb_plain(cfun, D, x, C.byref(fx), g, int(iters), float(step0), float(step_max))
+    return x, fx.value, g, n

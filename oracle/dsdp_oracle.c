@@ -798,10 +798,17 @@ void orc_pose_step(const orc_ligand *L, const double *pose, const double *step, 
 /* BFGS with Armijo backtracking (Nocedal & Wright, ref. [36]).               */
 /* ------------------------------------------------------------------------- */
 
+#define ORC_OPT_BFGS 0
+#define ORC_OPT_BB 1
+
 typedef struct {
     double temperature, wall_slope, rmsd_cluster, trans_amp;
     int bfgs_iters, ls_trials;
     double ls_shrink, armijo_c1;
+    int optimizer;            /* ORC_OPT_BFGS or ORC_OPT_BB */
+    int bb_iters;             /* Barzilai-Borwein iterations */
+    double bb_step0;          /* first BB step length (and the one used when s.y <= 0) */
+    double bb_step_max;       /* largest BB step length */
 } orc_params;
 
 void orc_params_default(orc_params *p)
@@ -814,6 +821,10 @@ void orc_params_default(orc_params *p)
     p->ls_trials = 10;
     p->ls_shrink = 0.1;
     p->armijo_c1 = 1e-4;
+    p->optimizer = ORC_OPT_BFGS;
+    p->bb_iters = 100;        /* the paper finds 100-150 BB iterations enough (Section 2, Figure 2) */
+    p->bb_step0 = 1e-2;
+    p->bb_step_max = 1.0;
 }
 
 /* generic objective: returns f(x), writes g = grad f(x) (dimension D) */
@@ -900,6 +911,58 @@ long orc_bfgs(void *ctx, orc_objective f, orc_retract retract, int nx, int D, do
     return evals;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Barzilai-Borwein gradient method (Section 2, "Binding pose search", second */
+/* modification; ref. [37]): no line search, the step length from the last   */
+/* step and gradient change.                                                  */
+/* ------------------------------------------------------------------------- */
+
+/*
+ *   g = grad f(x); a = step0; best = (f(x), x)
+ *   repeat `iters` times:
+ *     s = -a g;  x <- x (+) s;  g_new = grad f(x);  y = g_new - g;  g <- g_new
+ *     a = s.s / s.y if s.y > 0 (capped at step_max), else step0
+ *     best <- (f(x), x) if f(x) < best energy
+ *   return best (the method does not decrease f monotonically).
+ * Returns the number of objective evaluations (iters + 1).  g receives the
+ * gradient at the returned point.
+ */
+long orc_bb(void *ctx, orc_objective f, orc_retract retract, int nx, int D, double *x, double *fx, double *g,
+            int iters, double step0, double step_max)
+{
+    double s[ORC_MAXD], gn[ORC_MAXD], xn[ORC_MAXX], xb[ORC_MAXX], gb[ORC_MAXD];
+    long evals = 0;
+    double E = f(ctx, x, g);
+    evals++;
+    double Eb = E;
+    memcpy(xb, x, sizeof(double) * nx);
+    memcpy(gb, g, sizeof(double) * D);
+    double a = step0;
+    for (int it = 0; it < iters; it++) {
+        for (int r = 0; r < D; r++) s[r] = -a * g[r];
+        retract(ctx, x, s, xn);
+        double En = f(ctx, xn, gn);
+        evals++;
+        double sy = 0, ss = 0;
+        for (int r = 0; r < D; r++) {
+            sy += s[r] * (gn[r] - g[r]);
+            ss += s[r] * s[r];
+        }
+        a = sy > 0 ? fmin(ss / sy, step_max) : step0;
+        memcpy(x, xn, sizeof(double) * nx);
+        memcpy(g, gn, sizeof(double) * D);
+        if (En < Eb) {
+            Eb = En;
+            memcpy(xb, xn, sizeof(double) * nx);
+            memcpy(gb, gn, sizeof(double) * D);
+        }
+    }
+    memcpy(x, xb, sizeof(double) * nx);
+    memcpy(g, gb, sizeof(double) * D);
+    *fx = Eb;
+    return evals;
+}
+
 typedef struct {
     const orc_ligand *L;
     const orc_grid *g;
@@ -928,8 +991,15 @@ long orc_local_opt(const orc_ligand *L, const orc_grid *g, const orc_params *prm
 {
     pose_ctx c = {L, g, NULL, ORC_MODE_EQ4, prm->wall_slope};
     double gl[ORC_MAXD];
-    long n = orc_bfgs(&c, pose_objective, pose_retract, 7 + L->n_tors, 6 + L->n_tors, pose, E, gl,
-                      prm->bfgs_iters, prm->ls_trials, prm->ls_shrink, prm->armijo_c1, margin);
+    long n;
+    if (prm->optimizer == ORC_OPT_BB) {
+        n = orc_bb(&c, pose_objective, pose_retract, 7 + L->n_tors, 6 + L->n_tors, pose, E, gl, prm->bb_iters,
+                   prm->bb_step0, prm->bb_step_max);
+        if (margin) *margin = DBL_MAX;
+    } else {
+        n = orc_bfgs(&c, pose_objective, pose_retract, 7 + L->n_tors, 6 + L->n_tors, pose, E, gl,
+                     prm->bfgs_iters, prm->ls_trials, prm->ls_shrink, prm->armijo_c1, margin);
+    }
     if (grad) memcpy(grad, gl, sizeof(double) * (6 + L->n_tors));
     return n;
 }
@@ -951,6 +1021,13 @@ long orc_bfgs_plain(orc_objective f, int D, double *x, double *fx, double *g, in
 {
     plain_ctx c = {f, D};
     return orc_bfgs(&c, plain_objective, plain_retract, D, D, x, fx, g, iters, trials, shrink, c1, NULL);
+}
+
+/* generic Barzilai-Borwein over a ctypes callback, for textbook-function pins */
+long orc_bb_plain(orc_objective f, int D, double *x, double *fx, double *g, int iters, double step0, double step_max)
+{
+    plain_ctx c = {f, D};
+    return orc_bb(&c, plain_objective, plain_retract, D, D, x, fx, g, iters, step0, step_max);
 }
 
 /* ------------------------------------------------------------------------- */
