@@ -106,7 +106,17 @@ typedef struct {
     int32_t intra_form;      /* layout of the intra-ligand term on the device: DSDP_INTRA_AUTO
                                 (chosen by the library for the launch), DSDP_INTRA_PAIRS or
                                 DSDP_INTRA_ATOMS.  Results do not depend on it (0) */
+    int32_t optimizer;       /* local optimiser: DSDP_OPT_BFGS (bfgs_iters, ls_*, armijo_c1) or
+                                DSDP_OPT_BB, the paper's Barzilai-Borwein method (Section 2,
+                                second modification): bb_iters gradient steps of length
+                                s.s/s.y, no line search, lowest iterate kept (DSDP_OPT_BFGS) */
+    int32_t bb_iters;        /* Barzilai-Borwein iterations; the paper finds 100-150 enough (100) */
+    float bb_step0;          /* first step length, and the one used after a step with s.y <= 0 (0.01) */
+    float bb_step_max;       /* largest step length (1.0) */
 } dsdp_params;
+
+#define DSDP_OPT_BFGS 0
+#define DSDP_OPT_BB 1
 
 #define DSDP_INTRA_AUTO 0
 #define DSDP_INTRA_PAIRS 1   /* each pair evaluated once, its force stored and gathered per atom */

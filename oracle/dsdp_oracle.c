@@ -928,10 +928,11 @@ long orc_bfgs(void *ctx, orc_objective f, orc_retract retract, int nx, int D, do
  * gradient at the returned point.
  */
 long orc_bb(void *ctx, orc_objective f, orc_retract retract, int nx, int D, double *x, double *fx, double *g,
-            int iters, double step0, double step_max)
+            int iters, double step0, double step_max, double *margin)
 {
     double s[ORC_MAXD], gn[ORC_MAXD], xn[ORC_MAXX], xb[ORC_MAXX], gb[ORC_MAXD];
     long evals = 0;
+    double mmin = DBL_MAX;
     double E = f(ctx, x, g);
     evals++;
     double Eb = E;
@@ -943,12 +944,19 @@ long orc_bb(void *ctx, orc_objective f, orc_retract retract, int nx, int D, doub
         retract(ctx, x, s, xn);
         double En = f(ctx, xn, gn);
         evals++;
-        double sy = 0, ss = 0;
+        double sy = 0, ss = 0, yy = 0;
         for (int r = 0; r < D; r++) {
             sy += s[r] * (gn[r] - g[r]);
             ss += s[r] * s[r];
+            yy += (gn[r] - g[r]) * (gn[r] - g[r]);
         }
         a = sy > 0 ? fmin(ss / sy, step_max) : step0;
+        /* closeness of each decision to its threshold: the sign of s.y, the cap,
+           and the best-iterate comparison */
+        double m = fabs(sy) / (sqrt(ss * yy) + 1e-300);
+        if (sy > 0) m = fmin(m, fabs(ss / sy - step_max) / step_max);
+        m = fmin(m, fabs(En - Eb) / (fabs(En) + fabs(Eb) + 1e-12));
+        if (m < mmin) mmin = m;
         memcpy(x, xn, sizeof(double) * nx);
         memcpy(g, gn, sizeof(double) * D);
         if (En < Eb) {
@@ -960,6 +968,7 @@ long orc_bb(void *ctx, orc_objective f, orc_retract retract, int nx, int D, doub
     memcpy(x, xb, sizeof(double) * nx);
     memcpy(g, gb, sizeof(double) * D);
     *fx = Eb;
+    if (margin) *margin = mmin;
     return evals;
 }
 
@@ -994,8 +1003,7 @@ long orc_local_opt(const orc_ligand *L, const orc_grid *g, const orc_params *prm
     long n;
     if (prm->optimizer == ORC_OPT_BB) {
         n = orc_bb(&c, pose_objective, pose_retract, 7 + L->n_tors, 6 + L->n_tors, pose, E, gl, prm->bb_iters,
-                   prm->bb_step0, prm->bb_step_max);
-        if (margin) *margin = DBL_MAX;
+                   prm->bb_step0, prm->bb_step_max, margin);
     } else {
         n = orc_bfgs(&c, pose_objective, pose_retract, 7 + L->n_tors, 6 + L->n_tors, pose, E, gl,
                      prm->bfgs_iters, prm->ls_trials, prm->ls_shrink, prm->armijo_c1, margin);
@@ -1027,7 +1035,7 @@ long orc_bfgs_plain(orc_objective f, int D, double *x, double *fx, double *g, in
 long orc_bb_plain(orc_objective f, int D, double *x, double *fx, double *g, int iters, double step0, double step_max)
 {
     plain_ctx c = {f, D};
-    return orc_bb(&c, plain_objective, plain_retract, D, D, x, fx, g, iters, step0, step_max);
+    return orc_bb(&c, plain_objective, plain_retract, D, D, x, fx, g, iters, step0, step_max, NULL);
 }
 
 /* ------------------------------------------------------------------------- */

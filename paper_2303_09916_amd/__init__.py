@@ -24,6 +24,7 @@ DSDP_ERR_WORKSPACE_TOO_SMALL = -3
 DSDP_ERR_DEVICE = -4
 DSDP_ERR_BUSY = -5
 DSDP_INTRA_AUTO, DSDP_INTRA_PAIRS, DSDP_INTRA_ATOMS = 0, 1, 2
+DSDP_OPT_BFGS, DSDP_OPT_BB = 0, 1
 DSDP_REQ_QUEUED, DSDP_REQ_RUNNING, DSDP_REQ_DONE, DSDP_REQ_CANCELLED = 0, 1, 2, 3
 MAX_ATOMS = 64
 MAX_TORSIONS = 31
@@ -54,7 +55,8 @@ class dsdp_params(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("temperature", C.c_float), ("wall_slope", C.c_float),
                 ("rmsd_cluster", C.c_float), ("trans_amp", C.c_float), ("bfgs_iters", C.c_int32),
                 ("ls_trials", C.c_int32), ("ls_shrink", C.c_float), ("armijo_c1", C.c_float),
-                ("waves_per_chain", C.c_int32), ("intra_form", C.c_int32)]
+                ("waves_per_chain", C.c_int32), ("intra_form", C.c_int32), ("optimizer", C.c_int32),
+                ("bb_iters", C.c_int32), ("bb_step0", C.c_float), ("bb_step_max", C.c_float)]
 
 
 class dsdp_pose(C.Structure):

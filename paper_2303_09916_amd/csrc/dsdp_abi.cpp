@@ -391,6 +391,10 @@ SearchParams to_search(const dsdp_params *p)
     s.ls_trials = p->ls_trials;
     s.ls_shrink = p->ls_shrink;
     s.armijo_c1 = p->armijo_c1;
+    s.optimizer = p->optimizer;
+    s.bb_iters = p->bb_iters;
+    s.bb_step0 = p->bb_step0;
+    s.bb_step_max = p->bb_step_max;
     return s;
 }
 
@@ -401,7 +405,8 @@ dsdp_status check_params(const dsdp_params *p)
     if (!(p->temperature > 0) || !(p->wall_slope >= 0) || !(p->rmsd_cluster >= 0) || !(p->trans_amp >= 0) ||
         p->bfgs_iters < 0 || p->ls_trials < 1 || !(p->ls_shrink > 0 && p->ls_shrink < 1) || !(p->armijo_c1 >= 0) ||
         p->waves_per_chain < 0 || p->waves_per_chain > 4 || p->intra_form < DSDP_INTRA_AUTO ||
-        p->intra_form > DSDP_INTRA_ATOMS)
+        p->intra_form > DSDP_INTRA_ATOMS || (p->optimizer != DSDP_OPT_BFGS && p->optimizer != DSDP_OPT_BB) ||
+        p->bb_iters < 0 || !(p->bb_step0 > 0) || !(p->bb_step_max >= p->bb_step0))
         return fail(DSDP_ERR_INVALID_ARG, "search parameter out of range");
     return DSDP_OK;
 }
@@ -485,6 +490,8 @@ size_t device_max_lds()
 dsdp_status pick_waves(const dsdp_params *prm, const LigHeader &h, int n_chains, int &waves)
 {
     int w = (prm && prm->waves_per_chain > 0) ? prm->waves_per_chain : 0;
+    // Barzilai-Borwein evaluates one point per iteration: more waves would idle
+    if (w == 0 && prm && prm->optimizer == DSDP_OPT_BB) w = 1;
     if (w == 0) {
         const long slots = 8L * device_cus();
         w = (int)std::max(1L, std::min(4L, slots / std::max(1, n_chains)));
@@ -605,6 +612,10 @@ void dsdp_params_default(dsdp_params *p)
     p->armijo_c1 = 1e-4f;
     p->waves_per_chain = 0;
     p->intra_form = DSDP_INTRA_AUTO;
+    p->optimizer = DSDP_OPT_BFGS;
+    p->bb_iters = 100;
+    p->bb_step0 = 1e-2f;
+    p->bb_step_max = 1.0f;
 }
 
 dsdp_status dsdp_grid_dims(const dsdp_box *box, int32_t *n, float *origin)

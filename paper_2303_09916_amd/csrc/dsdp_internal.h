@@ -140,6 +140,8 @@ struct SearchParams {
     float temperature, wall_slope, rmsd_cluster, trans_amp;
     int bfgs_iters, ls_trials;
     float ls_shrink, armijo_c1;
+    int optimizer, bb_iters;     // DSDP_OPT_*; Barzilai-Borwein iterations
+    float bb_step0, bb_step_max;
 };
 
 // Launchers (defined in the .hip files).

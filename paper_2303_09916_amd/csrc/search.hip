@@ -269,6 +269,7 @@ struct ChainL {
 
 constexpr int kMaxWaves = 4;     // waves per chain (concurrent line-search trials)
 constexpr int kMiscGp = 40;      // slot of g.p in misc
+constexpr int kOptBB = 1;        // SearchParams::optimizer value of Barzilai-Borwein
 
 __host__ __device__ inline int rup4(int v) { return (v + 3) & ~3; }
 
@@ -750,6 +751,11 @@ __device__ inline Energy get_energy(const float *slot)
     return e;
 }
 
+// Local optimisation of the chain's pose x (LDS, in place), run by all W waves of
+// the workgroup together: BFGS with Armijo backtracking, or the Barzilai-Borwein
+// gradient method (no line search: wave 0 alone evaluates one point per
+// iteration; the lowest-energy iterate is returned).
+//
 // BFGS with Armijo backtracking on the chain's pose x (LDS, in place), run by all
 // W waves of the workgroup together.  The line search evaluates W consecutive
 // trials at once (alpha_t = shrink^t, one per wave) and accepts the first that
@@ -765,11 +771,15 @@ __device__ Energy local_opt_group(const LigL &L, const Layout &lay, float *wave_
 {
     const int lane = lane_id(), w = wave_id(), D = L.D;
     const WaveL S = make_wave(wave_base + w * lay.wave_words, lay);
-    Energy Ex;
+    const bool bb = P.optimizer == kOptBB;
+    const int iters = bb ? P.bb_iters : P.bfgs_iters;
+    Energy Ex, Eb;
     float gp = 0.f;
-    int it = 0;           // BFGS iterations done
+    int it = 0;           // iterations done
     int t0 = -1;          // first line-search trial of this round; -1: the start evaluation
     float alpha0 = 1.f;   // alpha of the round's first trial
+    float bb_a = P.bb_step0;   // Barzilai-Borwein step length (wave 0)
+    float *xb = C.H;           // Barzilai-Borwein: lowest-energy iterate (the matrix is unused)
     // Every evaluation of the local optimisation goes through the one call below
     // (the start pose by wave 0, then one line-search trial per wave per round),
     // so the kernel holds a single copy of the evaluation code.
@@ -778,6 +788,9 @@ __device__ Energy local_opt_group(const LigL &L, const Layout &lay, float *wave_
         if (t0 < 0) {
             active = (w == 0);
             if (active && lane < L.nx) S.trial[lane] = x[lane];
+        } else if (bb) {
+            active = (w == 0);
+            if (active) pose_step(L, x, bb_a, C.p, S.trial);
         } else {
             active = t0 + w < P.ls_trials;
             if (active) {
@@ -796,8 +809,34 @@ __device__ Energy local_opt_group(const LigL &L, const Layout &lay, float *wave_
             evals++;
             if (w == 0 && lane < D) {
                 C.g[lane] = S.gt[lane];
-                for (int c = 0; c < D; c++) C.H[lane * C.hs + c] = (c == lane) ? 1.f : 0.f;
+                if (!bb)
+                    for (int c = 0; c < D; c++) C.H[lane * C.hs + c] = (c == lane) ? 1.f : 0.f;
             }
+            if (bb) {
+                Eb = Ex;
+                if (w == 0 && lane < L.nx) xb[lane] = x[lane];
+            }
+        } else if (bb) {
+            // s = a p (p = -g), y = g_new - g; the next length is s.s / s.y when
+            // s.y > 0 (capped), else the first length; keep the lowest iterate
+            const Energy En = get_energy(C.et);
+            evals++;
+            if (w == 0) {
+                float sl = 0.f, yl = 0.f;
+                if (lane < D) {
+                    sl = bb_a * C.p[lane];
+                    yl = S.gt[lane] - C.g[lane];
+                    C.g[lane] = S.gt[lane];
+                }
+                const float sy = wave_sum(sl * yl), ss = wave_sum(sl * sl);
+                bb_a = sy > 0.f ? fminf(ss / sy, P.bb_step_max) : P.bb_step0;
+                if (lane < L.nx) {
+                    x[lane] = S.trial[lane];
+                    if (En.total < Eb.total) xb[lane] = S.trial[lane];
+                }
+            }
+            if (En.total < Eb.total) Eb = En;
+            it++;
         } else {
             int acc_slot = -1;
             float a = alpha0, alpha_acc = 0.f;
@@ -856,9 +895,13 @@ __device__ Energy local_opt_group(const LigL &L, const Layout &lay, float *wave_
             Ex = Et;
             it++;
         }
-        if (it >= P.bfgs_iters) break;
-        // direction of the next iteration, p = -H g (wave 0, which also wrote g and H)
-        if (w == 0) {
+        if (it >= iters) break;
+        // direction of the next iteration: p = -g (Barzilai-Borwein) or p = -H g
+        // (BFGS; wave 0, which also wrote g and H)
+        if (w == 0 && bb) {
+            wave_sync();
+            if (lane < D) C.p[lane] = -C.g[lane];
+        } else if (w == 0) {
             wave_sync();
             float pl = 0.f, gl = 0.f;
             if (lane < D) {
@@ -876,6 +919,10 @@ __device__ Energy local_opt_group(const LigL &L, const Layout &lay, float *wave_
         gp = C.misc[kMiscGp];
         t0 = 0;
         alpha0 = 1.f;
+    }
+    if (bb) {
+        if (w == 0 && lane < L.nx) x[lane] = xb[lane];
+        Ex = Eb;
     }
     __syncthreads();
     return Ex;
