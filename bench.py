@@ -26,7 +26,10 @@ Printed JSON line (one):
                per request, 128 chains x 1000 steps): the serving scheduler fed
                at the workload's 200 requests/s (saturation throughput, whether
                the queue was stable) and at a rate below saturation; p50/p99
-               latency from scheduled arrival to result.
+               latency from scheduled arrival to result;
+  optimizers   the DSDP-shaped request docked with the paper's Barzilai-Borwein
+               local optimiser and with BFGS: evaluations per step, throughput,
+               best energies.
 """
 import argparse
 import json
@@ -207,6 +210,42 @@ def batch_leg(D, torch, cfg, n_plain):
     }
 
 
+def optimizer_leg(D, torch, cfg, n_steps):
+    """The paper's Barzilai-Borwein local optimiser against BFGS on the
+    DSDP-shaped request (same chains, steps and seed)."""
+    rec, box, lig = cfg["receptor"], cfg["box"], cfg["ligands"][0]
+    types = cfg["map_types"]
+    n_chains, top_k, seed = cfg["n_chains"], cfg["top_k"], cfg["seed"]
+    maps = torch.empty(D.dsdp_grids_bytes(box, len(types)), dtype=torch.uint8, device="cuda")
+    gws = torch.empty(D.dsdp_build_grids_workspace_bytes(rec.n, box), dtype=torch.uint8, device="cuda")
+    g = D.dsdp_build_grids(rec.xyz, rec.types, box, types, maps, gws)
+    L = D.Ligand.from_synth(lig)
+    ws = torch.empty(D.dsdp_dock_workspace_bytes(L, n_chains), dtype=torch.uint8, device="cuda")
+    out = {"workload": "the DSDP-shaped request above, same chains, steps and seed"}
+    for name, prm in (("bfgs", D.dsdp_params_default()),
+                      ("barzilai_borwein", D.dsdp_params_default(optimizer=D.DSDP_OPT_BB))):
+        D.dsdp_dock(g, L, n_chains, 2, seed, top_k, ws, prm, want_xyz=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        poses, _, chains, st = D.dsdp_dock(g, L, n_chains, n_steps, seed, top_k, ws, prm, want_xyz=False,
+                                           want_chains=True)
+        dt = time.perf_counter() - t0
+        best = np.array([c.e_total for c in chains])
+        out[name] = {
+            "iterations": prm.bb_iters if prm.optimizer == D.DSDP_OPT_BB else prm.bfgs_iters,
+            "dock_s": dt,
+            "pose_evals_per_s": st.pose_evals / (st.search_ms * 1e-3),
+            "evals_per_step": st.pose_evals / st.local_opts,
+            "best_e_total": poses[0].e_total,
+            "chain_best_e_median": float(np.median(best)),
+            "chain_best_e_p10": float(np.quantile(best, 0.1)),
+        }
+        print(f"[bench] optimizer {name}: {dt:.2f}s, {st.pose_evals / st.local_opts:.1f} evals/step, "
+              f"best {poses[0].e_total:.3f}, median chain best {np.median(best):.3f}", file=sys.stderr, flush=True)
+    D.dsdp_grids_release(g)
+    return out
+
+
 def serve_leg(D, torch, cfg, first, count, rate, slots, spt, label):
     """Feed requests first..first+count of the served workload to the scheduler
     at `rate` requests/s (the workload's Poisson gaps rescaled), ticking
@@ -315,8 +354,10 @@ def main():
     ap.add_argument("--serve-requests-below", type=int, default=240,
                     help="requests fed at --serve-below x the measured saturation throughput")
     ap.add_argument("--serve-below", type=float, default=0.7)
-    ap.add_argument("--serve-slots", type=int, default=8192, help="scheduler chain slots")
-    ap.add_argument("--serve-steps-per-tick", type=int, default=50)
+    ap.add_argument("--serve-slots", type=int, default=16384, help="scheduler chain slots")
+    ap.add_argument("--serve-steps-per-tick", type=int, default=100)
+    ap.add_argument("--no-optimizer-leg", action="store_true",
+                    help="skip the Barzilai-Borwein vs BFGS comparison")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one plain device copy of this size (for counter calibration)")
     args = ap.parse_args()
@@ -438,7 +479,11 @@ def main():
         "cpu_baseline": None,
         "batched": None,
         "served": None,
+        "optimizers": None,
     }
+
+    if not args.no_optimizer_leg:
+        out["optimizers"] = optimizer_leg(D, torch, cfg, n_steps)
 
     if "cfg4" in inp:
         out["batched"] = batch_leg(D, torch, inp["cfg4"], args.plain_sample)
