@@ -29,7 +29,9 @@ Printed JSON line (one):
                latency from scheduled arrival to result;
   optimizers   the DSDP-shaped request docked with the paper's Barzilai-Borwein
                local optimiser and with BFGS: evaluations per step, throughput,
-               best energies.
+               best energies;
+  table1_shapes re-docking time per system in the copies x steps shapes of
+               the paper's timing table, with the fixed + per-copy-step fit.
 """
 import argparse
 import json
@@ -246,6 +248,64 @@ def optimizer_leg(D, torch, cfg, n_steps):
     return out
 
 
+# copies x MC steps of the paper's re-docking timing table (Table 1)
+TABLE1_SHAPES = ((128, 20), (384, 40), (512, 40), (512, 200), (1024, 200), (2048, 200))
+
+
+def table1_leg(D, torch, cfg, n_ligands, optimizers):
+    """Re-docking per system in the paper's copies x steps shapes: each system is
+    one synthetic ligand placed at the receptor's pocket, its box the ligand's
+    extent +/- 4 A per axis (the paper's re-docking rule, Section 3); time per
+    system = map build + dock + ranked poses back on the host."""
+    from synth import make_ligand, PALETTE_T9
+    rec = cfg["receptor"]
+    types = list(PALETTE_T9)
+    rng = np.random.default_rng([cfg["seed"], 7])
+    systems = []
+    for i in range(n_ligands):
+        lig = make_ligand(int(rng.integers(10, 61)), int(rng.integers(0, 16)), seed=7000 + i, palette=PALETTE_T9)
+        lig.xyz = (lig.xyz - lig.xyz.mean(axis=0) + rec.pocket).astype(np.float32)
+        lo, hi = lig.xyz.min(axis=0), lig.xyz.max(axis=0)
+        box = {"centre": (lo + hi) / 2.0, "size": (hi - lo) + 8.0, "spacing": 0.375}
+        systems.append((lig, D.Ligand.from_synth(lig), box))
+    out = {"workload": (f"{n_ligands} synthetic ligands of 10-60 atoms and 0-15 rotatable bonds at the pocket of "
+                        f"the {rec.n}-atom receptor, box = ligand extent +/- 4 A per axis at 0.375 A, 9 maps; "
+                        f"time per system = map build + dock + top {cfg['top_k']} on the host"),
+           "shapes": [list(x) for x in TABLE1_SHAPES]}
+    big_ws = max(D.dsdp_dock_workspace_bytes(L, 2048) for _, L, _ in systems)
+    ws = torch.empty(big_ws, dtype=torch.uint8, device="cuda")
+    mb = max(D.dsdp_grids_bytes(b, len(types)) for _, _, b in systems)
+    maps = torch.empty(mb, dtype=torch.uint8, device="cuda")
+    gws = torch.empty(max(D.dsdp_build_grids_workspace_bytes(rec.n, b) for _, _, b in systems), dtype=torch.uint8,
+                      device="cuda")
+    for name, prm in optimizers:
+        times = []
+        for copies, steps in TABLE1_SHAPES:
+            tot = 0.0
+            for k, (lig, L, box) in enumerate(systems):
+                if k == 0:   # first-use costs of this shape outside the timing
+                    g = D.dsdp_build_grids(rec.xyz, rec.types, box, types, maps, gws)
+                    D.dsdp_dock(g, L, copies, 2, 1, cfg["top_k"], ws, prm, want_xyz=False)
+                    D.dsdp_grids_release(g)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                g = D.dsdp_build_grids(rec.xyz, rec.types, box, types, maps, gws)
+                D.dsdp_dock(g, L, copies, steps, 1 + k, cfg["top_k"], ws, prm, want_xyz=False)
+                D.dsdp_grids_release(g)
+                tot += time.perf_counter() - t0
+            times.append(tot / len(systems))
+        work = np.array([c * s for c, s in TABLE1_SHAPES], dtype=np.float64)
+        A = np.stack([np.ones_like(work), work], axis=1)
+        (fixed, per), *_ = np.linalg.lstsq(A, np.array(times), rcond=None)
+        out[name] = {"s_per_system": times, "fit_fixed_s": float(fixed),
+                     "fit_us_per_copy_step": float(per * 1e6),
+                     "copy_steps_per_s_marginal": float(1.0 / per) if per > 0 else None}
+        print(f"[bench] table-1 shapes ({name}): " + ", ".join(f"{c}x{s} {t * 1e3:.1f} ms"
+                                                            for (c, s), t in zip(TABLE1_SHAPES, times)),
+              file=sys.stderr, flush=True)
+    return out
+
+
 def serve_leg(D, torch, cfg, first, count, rate, slots, spt, label):
     """Feed requests first..first+count of the served workload to the scheduler
     at `rate` requests/s (the workload's Poisson gaps rescaled), ticking
@@ -356,6 +416,8 @@ def main():
     ap.add_argument("--serve-below", type=float, default=0.7)
     ap.add_argument("--serve-slots", type=int, default=16384, help="scheduler chain slots")
     ap.add_argument("--serve-steps-per-tick", type=int, default=100)
+    ap.add_argument("--table1-ligands", type=int, default=4,
+                    help="systems per shape of the paper-shaped re-docking table (0: skip)")
     ap.add_argument("--no-optimizer-leg", action="store_true",
                     help="skip the Barzilai-Borwein vs BFGS comparison")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -484,6 +546,10 @@ def main():
 
     if not args.no_optimizer_leg:
         out["optimizers"] = optimizer_leg(D, torch, cfg, n_steps)
+    if args.table1_ligands > 0:
+        out["table1_shapes"] = table1_leg(D, torch, cfg, args.table1_ligands,
+                                          (("bfgs", D.dsdp_params_default()),
+                                           ("barzilai_borwein", D.dsdp_params_default(optimizer=D.DSDP_OPT_BB))))
 
     if "cfg4" in inp:
         out["batched"] = batch_leg(D, torch, inp["cfg4"], args.plain_sample)
