@@ -62,6 +62,8 @@ def lib():
                                   C.c_double]),
         "orc_grid_create": (vp, [vp, vp, vp, _ip, _dp, C.c_double, _ip, C.c_int]),
         "orc_grid_free": (None, [vp]),
+        "orc_grid_set_site": (None, [vp, _dp, C.c_int, C.c_double]),
+        "orc_site_term": (C.c_double, [vp, _dp, C.c_double, _dp]),
         "orc_interp": (None, [vp, C.c_int, _dp, C.c_int, C.c_double, _dp]),
         "orc_ligand_create": (vp, [C.c_int, _fp, _ip, C.c_int, _ip, _ip, _ip, C.c_int, _ip]),
         "orc_ligand_free": (None, [vp]),
@@ -175,6 +177,19 @@ class Grid:
             lib().orc_receptor_free(self.receptor)
         except Exception:
             pass
+
+    def set_site(self, points, radius=7.0):
+        """Adaptive search space: the box intersected with balls of `radius` around
+        the site points ([n, 3]); an empty array restores the plain box."""
+        pts = np.ascontiguousarray(np.asarray(points, dtype=np.float64).reshape(-1, 3))
+        self._site = pts
+        lib().orc_grid_set_site(self.handle, pts.reshape(-1), len(pts), float(radius))
+
+    def site_term(self, p, wall_slope=10.0):
+        """(energy, gradient on the root position) of the search-space restraint."""
+        g = np.zeros(3)
+        e = lib().orc_site_term(self.handle, np.ascontiguousarray(p, dtype=np.float64), float(wall_slope), g)
+        return e, g
 
     def interp(self, t, x, mode=MODE_EQ4, wall_slope=10.0):
         out = np.zeros(4)

@@ -329,6 +329,11 @@ typedef struct {
     double h;
     int T;
     int map_of_type[ORC_NXS];
+    /* adaptive search space (Section 2, third modification): the box intersected
+       with the union of balls of radius site_r around the site points */
+    int n_site;
+    double *site;         /* [n_site][3] */
+    double site_r;
 } orc_grid;
 
 orc_grid *orc_grid_create(const double *maps, const double *mass, const double *tie, const int *n,
@@ -343,7 +348,48 @@ orc_grid *orc_grid_create(const double *maps, const double *mass, const double *
     return g;
 }
 
-void orc_grid_free(orc_grid *g) { free(g); }
+void orc_grid_free(orc_grid *g)
+{
+    if (g) free(g->site);
+    free(g);
+}
+
+/* Site points of the adaptive search space; n = 0 restores the plain box. */
+void orc_grid_set_site(orc_grid *g, const double *pts, int n, double radius)
+{
+    free(g->site);
+    g->site = NULL;
+    g->n_site = 0;
+    if (n <= 0) return;
+    g->site = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    memcpy(g->site, pts, sizeof(double) * 3 * (size_t)n);
+    g->n_site = n;
+    g->site_r = radius;
+}
+
+/*
+ * Restraint of the ligand's root position p to the adaptive search space
+ * (reading of Section 2, third modification, and Figure 3): with site points,
+ * the nearest one c (lowest index on ties) at distance d; outside its ball
+ * (d > r) the pose pays wall_slope * (d - r), with gradient
+ * wall_slope * (p - c) / d on p.  Returns the energy; adds the gradient to g3.
+ */
+double orc_site_term(const orc_grid *g, const double *p, double wall_slope, double *g3)
+{
+    if (g->n_site <= 0) return 0.0;
+    int m = 0;
+    double best = DBL_MAX;
+    for (int i = 0; i < g->n_site; i++) {
+        double d2 = 0;
+        for (int a = 0; a < 3; a++) d2 += (p[a] - g->site[3 * i + a]) * (p[a] - g->site[3 * i + a]);
+        if (d2 < best) { best = d2; m = i; }
+    }
+    double d = sqrt(best);
+    if (d <= g->site_r) return 0.0;
+    if (g3)
+        for (int a = 0; a < 3; a++) g3[a] += wall_slope * (p[a] - g->site[3 * m + a]) / d;
+    return wall_slope * (d - g->site_r);
+}
 
 enum { ORC_MODE_EQ4 = 0, ORC_MODE_EQ3 = 1, ORC_MODE_DIRECT = 2 };
 
@@ -657,7 +703,8 @@ void orc_receptor_free(orc_receptor *r) { free(r); }
 /*
  * Energy of a pose and its gradient in the tangent coordinates
  *   (dp[3], rotation vector w[3] applied as q <- quat(w) * q, dtheta[n_tors]).
- * e_total = E_inter + E_intra, where E_inter includes the wall.
+ * e_total = E_inter + E_intra, where E_inter includes the wall (and, with site
+ * points, the restraint of the root position to the adaptive search space).
  *   mode EQ4 / EQ3: inter-molecular part from the maps (eq. 2 energy; eq. 4 or
  *   eq. 3 gradient).  mode DIRECT: from the receptor atoms by direct summation
  *   (grid-free), with the same wall; used to check gradients by finite differences.
@@ -725,9 +772,15 @@ double orc_eval(const orc_ligand *L, const orc_grid *g, const orc_receptor *rec,
         if (r > 1e-9)
             for (int c = 0; c < 3; c++) { f[i][c] += dd * d[c] / r; f[j][c] -= dd * d[c] / r; }
     }
+    double gsite[3] = {0, 0, 0};
+    const double e_site = orc_site_term(g, pose, wall_slope, gsite);
+    e_inter += e_site;
+    wall += e_site;
+    me += e_site;
+    if (e_site > 0) mg += wall_slope;
     double E = e_inter + e_intra;
     if (grad) {
-        double F[3] = {0, 0, 0}, tq[3] = {0, 0, 0};
+        double F[3] = {gsite[0], gsite[1], gsite[2]}, tq[3] = {0, 0, 0};
         for (int i = 0; i < L->n_atoms; i++) {
             double rel[3] = {x[i][0] - pose[0], x[i][1] - pose[1], x[i][2] - pose[2]}, c[3];
             cross(rel, f[i], c);
@@ -1067,7 +1120,8 @@ void orc_philox(const uint32_t *ctr_in, const uint32_t *key_in, uint32_t *out)
 static double unif(uint32_t x) { return (double)(x >> 8) * (1.0 / 16777216.0); }
 
 /* random-number streams of one chain: counter = (chain, step, stream, block), key = seed */
-enum { ORC_TAG_INIT = 0, ORC_TAG_MUTATE = 1, ORC_TAG_METROPOLIS = 2 };
+enum { ORC_TAG_INIT = 0, ORC_TAG_MUTATE = 1, ORC_TAG_METROPOLIS = 2, ORC_TAG_SITE = 3 };
+#define ORC_SITE_ATTEMPTS 64
 
 static void draw(uint64_t seed, uint32_t chain, uint32_t step, uint32_t tag, uint32_t block, uint32_t *out)
 {
@@ -1102,6 +1156,27 @@ void orc_initial_pose(const orc_ligand *L, const orc_grid *g, uint64_t seed, uin
         for (int c = 0; c < 4 && w + c < nw; c++) u[w + c] = unif(r[c]);
     }
     for (int a = 0; a < 3; a++) pose[a] = g->origin[a] + u[a] * (g->n[a] - 1) * g->h;
+    if (g->n_site > 0) {
+        /* adaptive search space: the first of up to ORC_SITE_ATTEMPTS uniform points
+           of the box (one Philox block each) that lies in a site ball; none: the
+           first site point */
+        int ok = 0;
+        for (uint32_t k = 0; k < ORC_SITE_ATTEMPTS && !ok; k++) {
+            uint32_t r[4];
+            draw(seed, chain, 0, ORC_TAG_SITE, k, r);
+            double c[3];
+            for (int a = 0; a < 3; a++) c[a] = g->origin[a] + unif(r[a]) * (g->n[a] - 1) * g->h;
+            for (int i = 0; i < g->n_site && !ok; i++) {
+                double d2 = 0;
+                for (int a = 0; a < 3; a++) d2 += (c[a] - g->site[3 * i + a]) * (c[a] - g->site[3 * i + a]);
+                if (d2 <= g->site_r * g->site_r) ok = 1;
+            }
+            if (ok)
+                for (int a = 0; a < 3; a++) pose[a] = c[a];
+        }
+        if (!ok)
+            for (int a = 0; a < 3; a++) pose[a] = g->site[a];
+    }
     orc_shoemake(u[3], u[4], u[5], pose + 3);
     for (int k = 0; k < L->n_tors; k++) pose[7 + k] = -ORC_PI + 2 * ORC_PI * u[6 + k];
 }

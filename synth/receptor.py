@@ -161,3 +161,22 @@ def make_receptor(n_atoms, radius=10.0, seed=0, min_dist=2.8, density=0.025,
                     pocket=pocket, seed=seed,
                     info={"attempts": attempt + 1, "requested_radius": radius,
                           "counts": counts})
+
+
+def make_site_points(rec, n=200, radius=9.0, clearance=3.0, seed=0):
+    """Synthetic binding-site points (stand-ins for a site predictor's top-scored
+    voxels): ``n`` points drawn uniformly in the ball of ``radius`` around the
+    receptor's pocket point, keeping those at least ``clearance`` A from every
+    receptor atom (the cavity).  Returns (n, 3) float32."""
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng([int(seed), 17])
+    tree = cKDTree(np.asarray(rec.xyz, dtype=np.float64))
+    out = []
+    for _ in range(1000):
+        c = rng.uniform(-radius, radius, size=(4 * n, 3))
+        c = c[np.einsum("ij,ij->i", c, c) <= radius * radius] + rec.pocket
+        d, _ = tree.query(c)
+        out.extend(c[d >= clearance])
+        if len(out) >= n:
+            return np.asarray(out[:n], dtype=np.float32)
+    raise ValueError("no room for site points around the pocket")
