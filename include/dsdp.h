@@ -194,6 +194,19 @@ dsdp_status dsdp_build_grids(const dsdp_atom *rec, int32_t n_rec, const dsdp_box
 void dsdp_grids_release(dsdp_grids g);
 
 /*
+ * Adaptive search space (Section 2, "Binding pose search", third modification;
+ * Figure 3): searches on these maps are restricted to the box intersected with
+ * the union of balls of `radius` (the paper uses 7 A) around the site points
+ * (host float[n_points][3], copied; n_points <= 256; 0 restores the plain box).
+ * Chains start at a uniform point of that space (the first of 64 uniform box
+ * points falling in a ball, else the first site point), and outside it the
+ * ligand's root position pays wall_slope per A of its distance to the nearest
+ * ball.  Applies to dsdp_eval_poses, dsdp_local_opt, dsdp_dock and
+ * dsdp_dock_batch on this handle (the serving scheduler uses plain boxes).
+ */
+dsdp_status dsdp_grids_set_site(dsdp_grids g, const float *points, int32_t n_points, float radius);
+
+/*
  * Derived sizes of a ligand: the number of intra-ligand pairs the energy sums
  * (atoms in different rigid fragments, more than three bonds apart) and the
  * depth of its torsion tree.  Either output may be NULL.

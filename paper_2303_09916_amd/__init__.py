@@ -102,6 +102,7 @@ _SIGS = {
                                     C.POINTER(C.c_uint64), C.POINTER(dsdp_params), C.c_int32, C.c_int32, _vp,
                                     C.c_size_t, _vp, C.POINTER(dsdp_pose), C.POINTER(C.c_int32),
                                     C.POINTER(dsdp_dock_stats)]),
+    "dsdp_grids_set_site": (C.c_int32, [_vp, C.POINTER(C.c_float), C.c_int32, C.c_float]),
     "dsdp_sched_fixed_bytes": (C.c_size_t, [C.c_int32]),
     "dsdp_sched_create": (C.c_int32, [_vp, C.c_size_t, C.c_int32, C.c_int32, C.POINTER(dsdp_params), _vp,
                                       C.POINTER(_vp)]),
@@ -330,6 +331,13 @@ def dsdp_dock_batch(grids, ligs, n_chains, n_steps, seeds, top_k, d_ws, params=N
                                  _ptr(d_ws), _nbytes(d_ws), _stream(stream), out, n_out, C.byref(stats)))
     res = [[out[l * top_k + q] for q in range(n_out[l])] for l in range(n)]
     return res, stats
+
+
+def dsdp_grids_set_site(grids, points, radius=7.0):
+    """Restrict searches on these maps to the box intersected with balls of `radius`
+    around the site points ([n, 3]; empty: the plain box)."""
+    pts = np.ascontiguousarray(np.asarray(points, dtype=np.float32).reshape(-1, 3))
+    _check(lib().dsdp_grids_set_site(grids, pts.ctypes.data_as(C.POINTER(C.c_float)), len(pts), float(radius)))
 
 
 # ---------------------------------------------------------------- serving scheduler

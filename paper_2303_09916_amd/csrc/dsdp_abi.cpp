@@ -414,7 +414,7 @@ dsdp_status check_params(const dsdp_params *p)
 // Workspace layout of the search calls.  The host-written sections (blob arena,
 // tasks, grid views, ranking segments) come first and are uploaded in one copy.
 struct SearchWs {
-    size_t arena, tasks, grids, segs, host_end, state, records, xyz, sel, total;
+    size_t arena, tasks, grids, site, segs, host_end, state, records, xyz, sel, total;
 };
 SearchWs search_ws(size_t arena_words, long n_slots, int n_grids, int n_segs)
 {
@@ -423,6 +423,7 @@ SearchWs search_ws(size_t arena_words, long n_slots, int n_grids, int n_segs)
     w.arena = o; o += align256(arena_words * 4);
     w.tasks = o; o += align256((size_t)n_slots * sizeof(ChainTask));
     w.grids = o; o += align256((size_t)n_grids * sizeof(GridView));
+    w.site = o; o += align256((size_t)kMaxSite * sizeof(float4));
     w.segs = o; o += align256((size_t)n_segs * sizeof(RankSeg));
     w.host_end = o;
     w.state = o; o += align256((size_t)n_slots * kStWords * 4);
@@ -433,6 +434,27 @@ SearchWs search_ws(size_t arena_words, long n_slots, int n_grids, int n_segs)
     return w;
 }
 SearchWs search_ws(const LigHeader &h, int n) { return search_ws((size_t)h.total_words, n, 1, 1); }
+
+// The grids' device view for a workspace whose site section (at ws + w.site)
+// receives the search-space points; `host` (nullable) is the host image of the
+// workspace's host-written part, else the points are copied on `stream`.
+dsdp_status device_view(const dsdp_grids_s *g, char *ws, const SearchWs &w, unsigned char *host, hipStream_t stream,
+                        GridView &view)
+{
+    view = g->view;
+    view.n_site = (int)g->site.size();
+    view.site_r = g->site_r;
+    view.site = view.n_site ? (const float4 *)(ws + w.site) : nullptr;
+    if (!view.n_site) return DSDP_OK;
+    const size_t bytes = g->site.size() * sizeof(float4);
+    if (host) {
+        std::memcpy(host + w.site, g->site.data(), bytes);
+        return DSDP_OK;
+    }
+    HIP_TRY(hipMemcpyAsync(ws + w.site, g->site.data(), bytes, hipMemcpyHostToDevice, stream), "site upload");
+    HIP_TRY(hipStreamSynchronize(stream), "site upload");
+    return DSDP_OK;
+}
 
 dsdp_status upload_blob(const Prepared &pl, char *d_ws, hipStream_t stream)
 {
@@ -735,6 +757,9 @@ dsdp_status dsdp_build_grids(const dsdp_atom *rec, int32_t n_rec, const dsdp_box
     g->view.h = box->spacing;
     g->view.inv_h = 1.0f / box->spacing;
     g->view.T = n_types;
+    g->view.site = nullptr;
+    g->view.n_site = 0;
+    g->view.site_r = 0.f;
     for (int t = 0; t < kNXS; t++) g->map_of_type[t] = -1;
     for (int t = 0; t < n_types; t++) {
         g->map_of_type[tl[t]] = t;
@@ -750,6 +775,24 @@ dsdp_status dsdp_build_grids(const dsdp_atom *rec, int32_t n_rec, const dsdp_box
 }
 
 void dsdp_grids_release(dsdp_grids g) { delete g; }
+
+dsdp_status dsdp_grids_set_site(dsdp_grids g, const float *points, int32_t n_points, float radius)
+{
+    if (!g) return fail(DSDP_ERR_INVALID_ARG, "grids handle is NULL");
+    if (n_points < 0 || n_points > kMaxSite) return fail(DSDP_ERR_INVALID_ARG, "n_points %d outside 0..%d", n_points, kMaxSite);
+    if (n_points > 0 && (!points || !(radius > 0.f) || !std::isfinite(radius)))
+        return fail(DSDP_ERR_INVALID_ARG, "site points missing or radius not positive");
+    std::vector<float4> site((size_t)n_points);
+    for (int i = 0; i < n_points; i++) {
+        const float x = points[3 * i], y = points[3 * i + 1], z = points[3 * i + 2];
+        if (!std::isfinite(x) || !std::isfinite(y) || !std::isfinite(z))
+            return fail(DSDP_ERR_INVALID_ARG, "site point %d is not finite", i);
+        site[(size_t)i] = make_float4(x, y, z, 0.f);
+    }
+    g->site.swap(site);
+    g->site_r = n_points ? radius : 0.f;
+    return DSDP_OK;
+}
 
 dsdp_status dsdp_ligand_info(const dsdp_ligand *lig, int32_t *n_pairs, int32_t *tree_depth)
 {
@@ -788,7 +831,10 @@ dsdp_status dsdp_eval_poses(dsdp_grids g, const dsdp_ligand *lig, const float *d
     char *ws = (char *)d_ws;
     st = upload_blob(pl, ws + w.arena, s);
     if (st) return st;
-    HIP_TRY(launch_eval((const uint32_t *)(ws + w.arena), pl.h.total_words, pl.h, g->view, to_search(prm), d_poses,
+    GridView view;
+    st = device_view(g, ws, w, nullptr, s, view);
+    if (st) return st;
+    HIP_TRY(launch_eval((const uint32_t *)(ws + w.arena), pl.h.total_words, pl.h, view, to_search(prm), d_poses,
                         n_poses, d_energy, d_grad, d_xyz, s),
             "eval launch");
     return DSDP_OK;
@@ -818,7 +864,10 @@ dsdp_status dsdp_local_opt(dsdp_grids g, const dsdp_ligand *lig, const float *d_
     int waves = 1;
     st = pick_waves(prm, pl.h, n_poses, waves);
     if (st) return st;
-    HIP_TRY(launch_local_opt((const uint32_t *)(ws + w.arena), pl.h.total_words, pl.h, g->view, to_search(prm), waves,
+    GridView view;
+    st = device_view(g, ws, w, nullptr, s, view);
+    if (st) return st;
+    HIP_TRY(launch_local_opt((const uint32_t *)(ws + w.arena), pl.h.total_words, pl.h, view, to_search(prm), waves,
                              d_poses_in, n_poses, d_poses_out, d_energy, d_evals, s),
             "local-opt launch");
     return DSDP_OK;
@@ -866,7 +915,12 @@ dsdp_status dsdp_dock(dsdp_grids g, const dsdp_ligand *lig, int32_t n_chains, in
         t.slot = c;
         t.fresh = 1;
     }
-    *img.at<GridView>(w.grids) = g->view;
+    {
+        GridView view;
+        st = device_view(g, ws, w, img.bytes.data(), s, view);
+        if (st) return st;
+        *img.at<GridView>(w.grids) = view;
+    }
     RankSeg *seg = img.at<RankSeg>(w.segs);
     seg->slot0 = 0;
     seg->n_chains = n_chains;
@@ -1026,7 +1080,12 @@ dsdp_status dsdp_dock_batch(dsdp_grids g, const dsdp_ligand *ligs, int32_t n_lig
             t.slot = (int)((long)l * n_chains + c);
             t.fresh = 0;
         }
-    *img.at<GridView>(w.grids) = g->view;
+    {
+        GridView view;
+        st = device_view(g, ws, w, img.bytes.data(), s, view);
+        if (st) return st;
+        *img.at<GridView>(w.grids) = view;
+    }
     RankSeg *segs = img.at<RankSeg>(w.segs);
     for (int l = 0; l < n_ligs; l++) {
         segs[l].slot0 = l * n_chains;

@@ -14,6 +14,8 @@ struct dsdp_grids_s {
     int types[dsdp::kNXS];
     int map_of_type[dsdp::kNXS];   // XS type -> map index or -1
     size_t bytes;
+    std::vector<float4> site;      // adaptive search space (host copy)
+    float site_r = 0.f;
 };
 
 namespace dsdp {

@@ -54,7 +54,15 @@ struct GridView {
     float origin[3];
     float h, inv_h;
     int T;
+    // adaptive search space: the box intersected with balls of radius site_r
+    // around n_site points (n_site = 0: the box)
+    const float4 *site;
+    int n_site;
+    float site_r;
 };
+constexpr int kMaxSite = 256;
+constexpr uint32_t kTagSite = 3;       // Philox stream of the initial positions in the search space
+constexpr int kSiteAttempts = 64;      // uniform box points tried (one per lane)
 
 // Ligand blob: 32-bit words, built on the host per (ligand, grids), copied to the
 // device, then staged into LDS by every search workgroup.  Section offsets are in
@@ -134,7 +142,7 @@ struct RankSeg {
 };
 
 // Random-number streams (Philox4x32-10 counter = chain, step, stream, block; key = seed).
-constexpr uint32_t kTagInit = 0, kTagMutate = 1, kTagMetropolis = 2;
+constexpr uint32_t kTagInit = 0, kTagMutate = 1, kTagMetropolis = 2;   // kTagSite = 3 above
 
 struct SearchParams {
     float temperature, wall_slope, rmsd_cluster, trans_amp;

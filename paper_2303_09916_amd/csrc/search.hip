@@ -603,8 +603,34 @@ __device__ Energy eval_pose(const LigL &L, const WaveL &S, const IntraRegs<PPL, 
         f = make_float3(gx + wg.x, gy + wg.y, gz + wg.z);
         e_atom = E + w_atom;
     }
-    const float e_inter = wave_sum(e_atom);
-    const float wall = wave_sum(w_atom);
+    float e_inter = wave_sum(e_atom);
+    float wall = wave_sum(w_atom);
+    // adaptive search space: outside every site ball the root position pays
+    // wall_slope per A of its distance to the nearest ball (lowest index on ties)
+    float3 g_site = make_float3(0.f, 0.f, 0.f);
+    if (G.n_site > 0) {
+        const float px = pose[0], py = pose[1], pz = pose[2];
+        uint64_t key = ~0ull;   // (squared distance bits, site index), minimised
+        for (int i = lane; i < G.n_site; i += 64) {
+            const float4 q = G.site[i];
+            const float dx = px - q.x, dy = py - q.y, dz = pz - q.z;
+            const uint64_t k = ((uint64_t)__float_as_uint(dx * dx + dy * dy + dz * dz) << 32) | (uint32_t)i;
+            key = k < key ? k : key;
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const uint64_t other = __shfl_xor(key, o, 64);
+            key = other < key ? other : key;
+        }
+        const float d = sqrtf(__uint_as_float((uint32_t)(key >> 32)));
+        if (d > G.site_r) {
+            const float4 q = G.site[(int)(key & 0xffffffffu)];
+            const float e = wall_slope * (d - G.site_r), k = wall_slope / d;
+            e_inter += e;
+            wall += e;
+            g_site = make_float3(k * (px - q.x), k * (py - q.y), k * (pz - q.z));
+        }
+    }
     wave_sync();
 
     float e_intra = 0.f;
@@ -693,7 +719,7 @@ __device__ Energy eval_pose(const LigL &L, const WaveL &S, const IntraRegs<PPL, 
             }
         }
         if (lane == 0) {
-            grad[0] = F.x; grad[1] = F.y; grad[2] = F.z;
+            grad[0] = F.x + g_site.x; grad[1] = F.y + g_site.y; grad[2] = F.z + g_site.z;
             grad[3] = Tq.x; grad[4] = Tq.y; grad[5] = Tq.z;
         } else {
             const float4 uref = L.fu[lane];
@@ -1063,7 +1089,33 @@ __global__ __launch_bounds__(256) void tick_kernel(const uint32_t *arena, const 
                 C.cur[lane] = -kPi + 2 * kPi * C.misc[6 + lane - 7];
             }
             wave_sync();
-            copy_pose(L, C.cur, C.best);
+            if (G.n_site > 0) {
+                // adaptive search space: the first of kSiteAttempts uniform box
+                // points (lane k draws attempt k) that lies in a site ball, else
+                // the first site point
+                const uint4 r = draw(seed, c, 0u, kTagSite, (uint32_t)lane);
+                const float px = G.origin[0] + unif(r.x) * ((float)(G.n[0] - 1) * G.h);
+                const float py = G.origin[1] + unif(r.y) * ((float)(G.n[1] - 1) * G.h);
+                const float pz = G.origin[2] + unif(r.z) * ((float)(G.n[2] - 1) * G.h);
+                const float r2 = G.site_r * G.site_r;
+                bool in = false;
+                for (int i = 0; i < G.n_site; i++) {
+                    const float4 q = G.site[i];
+                    const float dx = px - q.x, dy = py - q.y, dz = pz - q.z;
+                    in = in || (dx * dx + dy * dy + dz * dz <= r2);
+                }
+                const uint64_t hit = __ballot(lane < kSiteAttempts && in);
+                if (hit) {
+                    const int k = __ffsll((unsigned long long)hit) - 1;
+                    const float sx = read_lane(px, k), sy = read_lane(py, k), sz = read_lane(pz, k);
+                    if (lane < 3) C.cur[lane] = lane == 0 ? sx : (lane == 1 ? sy : sz);
+                } else if (lane < 3) {
+                    const float4 q = G.site[0];
+                    C.cur[lane] = lane == 0 ? q.x : (lane == 1 ? q.y : q.z);
+                }
+                wave_sync();
+                copy_pose(L, C.cur, C.best);
+            }
         }
         Ex.total = 0.f; Ex.inter = 0.f; Ex.intra = 0.f; Ex.wall = 0.f;
         Eb.total = __int_as_float(0x7f800000); Eb.inter = Eb.intra = Eb.wall = 0.f;
