@@ -31,7 +31,10 @@ Printed JSON line (one):
                local optimiser and with BFGS: evaluations per step, throughput,
                best energies;
   table1_shapes re-docking time per system in the copies x steps shapes of
-               the paper's timing table, with the fixed + per-copy-step fit.
+               the paper's timing table, with the fixed + per-copy-step fit;
+  adaptive_space the DSDP-shaped request in the paper's adaptive search space
+               (box intersected with 7 A balls around synthetic site points)
+               against the plain box.
 """
 import argparse
 import json
@@ -248,6 +251,46 @@ def optimizer_leg(D, torch, cfg, n_steps):
     return out
 
 
+def adaptive_leg(D, torch, cfg, n_steps):
+    """The DSDP-shaped request in the paper's adaptive search space (the box
+    intersected with 7 A balls around 200 synthetic site points in the pocket)
+    against the plain box: the space's volume fraction, throughput, energies."""
+    from synth import make_site_points
+    rec, box, lig = cfg["receptor"], cfg["box"], cfg["ligands"][0]
+    types = cfg["map_types"]
+    n_chains, top_k, seed = cfg["n_chains"], cfg["top_k"], cfg["seed"]
+    pts = make_site_points(rec, n=200)
+    c = np.asarray(box["centre"], dtype=np.float64)
+    size = np.broadcast_to(np.asarray(box["size"], dtype=np.float64), (3,))
+    rng = np.random.default_rng(1)
+    P = c - size / 2 + rng.random((400000, 3)) * size
+    from scipy.spatial import cKDTree
+    frac = float(np.mean(cKDTree(pts).query(P)[0] <= 7.0))
+    maps = torch.empty(D.dsdp_grids_bytes(box, len(types)), dtype=torch.uint8, device="cuda")
+    gws = torch.empty(D.dsdp_build_grids_workspace_bytes(rec.n, box), dtype=torch.uint8, device="cuda")
+    g = D.dsdp_build_grids(rec.xyz, rec.types, box, types, maps, gws)
+    L = D.Ligand.from_synth(lig)
+    ws = torch.empty(D.dsdp_dock_workspace_bytes(L, n_chains), dtype=torch.uint8, device="cuda")
+    out = {"workload": "the DSDP-shaped request; space = 30 A box intersected with 7 A balls around 200 synthetic "
+                       "site points drawn in the pocket cavity",
+           "volume_fraction_of_box": frac}
+    for name, sites in (("box", None), ("adaptive", pts)):
+        D.dsdp_grids_set_site(g, sites if sites is not None else np.zeros((0, 3)), 7.0)
+        D.dsdp_dock(g, L, n_chains, 2, seed, top_k, ws, want_xyz=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        poses, _, chains, st = D.dsdp_dock(g, L, n_chains, n_steps, seed, top_k, ws, want_xyz=False,
+                                           want_chains=True)
+        dt = time.perf_counter() - t0
+        best = np.array([ch.e_total for ch in chains])
+        out[name] = {"dock_s": dt, "pose_evals_per_s": st.pose_evals / (st.search_ms * 1e-3),
+                     "best_e_total": poses[0].e_total, "chain_best_e_median": float(np.median(best))}
+        print(f"[bench] search space {name}: {dt:.2f}s, best {poses[0].e_total:.3f}, median chain best "
+              f"{np.median(best):.3f}", file=sys.stderr, flush=True)
+    D.dsdp_grids_release(g)
+    return out
+
+
 # copies x MC steps of the paper's re-docking timing table (Table 1)
 TABLE1_SHAPES = ((128, 20), (384, 40), (512, 40), (512, 200), (1024, 200), (2048, 200))
 
@@ -419,7 +462,7 @@ def main():
     ap.add_argument("--table1-ligands", type=int, default=4,
                     help="systems per shape of the paper-shaped re-docking table (0: skip)")
     ap.add_argument("--no-optimizer-leg", action="store_true",
-                    help="skip the Barzilai-Borwein vs BFGS comparison")
+                    help="skip the Barzilai-Borwein vs BFGS and search-space comparisons")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one plain device copy of this size (for counter calibration)")
     args = ap.parse_args()
@@ -546,6 +589,8 @@ def main():
 
     if not args.no_optimizer_leg:
         out["optimizers"] = optimizer_leg(D, torch, cfg, n_steps)
+    if not args.no_optimizer_leg:
+        out["adaptive_space"] = adaptive_leg(D, torch, cfg, n_steps)
     if args.table1_ligands > 0:
         out["table1_shapes"] = table1_leg(D, torch, cfg, args.table1_ligands,
                                           (("bfgs", D.dsdp_params_default()),

@@ -206,6 +206,28 @@ void dsdp_grids_release(dsdp_grids g);
  */
 dsdp_status dsdp_grids_set_site(dsdp_grids g, const float *points, int32_t n_points, float radius);
 
+/* Device workspace bytes for dsdp_site_points with top_n points (0 if top_n is out of range). */
+size_t dsdp_site_points_workspace_bytes(int32_t top_n);
+
+/*
+ * Binding-site points from a site predictor's score volume (Section 2,
+ * site-prediction paragraph: the score voxels are extracted and clustered and
+ * the top 200 points describe the site; the maximum-score position is the
+ * sampling centre).  d_scores: device float[dims[2]][dims[1]][dims[0]] (x
+ * fastest; finite values), voxel (i, j, k) centred at origin + (i, j, k) *
+ * spacing.  The top_n (1..1024) highest-scoring voxels, ties to the lower linear
+ * index, are returned in rank order: points host float[top_n][3] (voxel
+ * centres), labels host int32[top_n] = rank of the best point of the point's
+ * single-linkage cluster (two kept voxels link when their centres are within
+ * link_dist; <= 0 means sqrt(3) * spacing, the 26-neighbourhood), so the
+ * maximum's cluster has label 0; *n_out = min(top_n, voxels); centre (nullable)
+ * = the maximum's centre.  Feed the label-0 points to dsdp_grids_set_site and
+ * centre the box on `centre`.  Synchronous on `stream`.
+ */
+dsdp_status dsdp_site_points(const float *d_scores, const int32_t *dims, const float *origin, float spacing,
+                             int32_t top_n, float link_dist, void *d_ws, size_t ws_bytes, void *stream,
+                             float *points, int32_t *labels, int32_t *n_out, float *centre);
+
 /*
  * Derived sizes of a ligand: the number of intra-ligand pairs the energy sums
  * (atoms in different rigid fragments, more than three bonds apart) and the

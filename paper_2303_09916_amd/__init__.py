@@ -103,6 +103,10 @@ _SIGS = {
                                     C.c_size_t, _vp, C.POINTER(dsdp_pose), C.POINTER(C.c_int32),
                                     C.POINTER(dsdp_dock_stats)]),
     "dsdp_grids_set_site": (C.c_int32, [_vp, C.POINTER(C.c_float), C.c_int32, C.c_float]),
+    "dsdp_site_points_workspace_bytes": (C.c_size_t, [C.c_int32]),
+    "dsdp_site_points": (C.c_int32, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_float), C.c_float, C.c_int32,
+                                     C.c_float, _vp, C.c_size_t, _vp, C.POINTER(C.c_float), C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_int32), C.POINTER(C.c_float)]),
     "dsdp_sched_fixed_bytes": (C.c_size_t, [C.c_int32]),
     "dsdp_sched_create": (C.c_int32, [_vp, C.c_size_t, C.c_int32, C.c_int32, C.POINTER(dsdp_params), _vp,
                                       C.POINTER(_vp)]),
@@ -338,6 +342,26 @@ def dsdp_grids_set_site(grids, points, radius=7.0):
     around the site points ([n, 3]; empty: the plain box)."""
     pts = np.ascontiguousarray(np.asarray(points, dtype=np.float32).reshape(-1, 3))
     _check(lib().dsdp_grids_set_site(grids, pts.ctypes.data_as(C.POINTER(C.c_float)), len(pts), float(radius)))
+
+
+def dsdp_site_points_workspace_bytes(top_n):
+    return int(lib().dsdp_site_points_workspace_bytes(int(top_n)))
+
+
+def dsdp_site_points(d_scores, dims, origin, spacing, top_n, d_ws, link_dist=0.0, stream=None):
+    """(points [n, 3] float32, labels [n] int32, centre [3]) of a device score volume
+    (float32, shape [dims[2], dims[1], dims[0]])."""
+    dm = (C.c_int32 * 3)(*[int(v) for v in dims])
+    org = (C.c_float * 3)(*[float(v) for v in origin])
+    pts = np.zeros((int(top_n), 3), dtype=np.float32)
+    lab = np.zeros(int(top_n), dtype=np.int32)
+    n = C.c_int32()
+    cen = (C.c_float * 3)()
+    _check(lib().dsdp_site_points(_ptr(d_scores), dm, org, float(spacing), int(top_n), float(link_dist), _ptr(d_ws),
+                                  _nbytes(d_ws), _stream(stream), pts.ctypes.data_as(C.POINTER(C.c_float)),
+                                  lab.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(n), cen))
+    k = n.value
+    return pts[:k], lab[:k], np.array(list(cen), dtype=np.float32)
 
 
 # ---------------------------------------------------------------- serving scheduler

@@ -776,6 +776,50 @@ dsdp_status dsdp_build_grids(const dsdp_atom *rec, int32_t n_rec, const dsdp_box
 
 void dsdp_grids_release(dsdp_grids g) { delete g; }
 
+size_t dsdp_site_points_workspace_bytes(int32_t top_n)
+{
+    if (top_n < 1 || top_n > kMaxSitePoints) return 0;
+    return align256((size_t)top_n * 8);
+}
+
+dsdp_status dsdp_site_points(const float *d_scores, const int32_t *dims, const float *origin, float spacing,
+                             int32_t top_n, float link_dist, void *d_ws, size_t ws_bytes, void *stream,
+                             float *points, int32_t *labels, int32_t *n_out, float *centre)
+{
+    if (!d_scores || !dims || !origin || !points || !labels || !n_out)
+        return fail(DSDP_ERR_INVALID_ARG, "scores, dims, origin or an output is NULL");
+    if (top_n < 1 || top_n > kMaxSitePoints) return fail(DSDP_ERR_INVALID_ARG, "top_n %d outside 1..%d", top_n, kMaxSitePoints);
+    if (!(spacing > 0.f) || !std::isfinite(spacing)) return fail(DSDP_ERR_INVALID_ARG, "spacing must be positive");
+    long n = 1;
+    for (int a = 0; a < 3; a++) {
+        if (dims[a] < 1) return fail(DSDP_ERR_INVALID_ARG, "dims must be positive");
+        n *= dims[a];
+    }
+    if (n > (1L << 26)) return fail(DSDP_ERR_UNSUPPORTED, "more than 2^26 voxels");
+    const size_t need = dsdp_site_points_workspace_bytes(top_n);
+    if (!d_ws || ws_bytes < need) return fail(DSDP_ERR_WORKSPACE_TOO_SMALL, "workspace needs %zu bytes", need);
+    const int k = (int)std::min<long>(top_n, n);
+    const double link = link_dist > 0.f ? (double)link_dist : std::sqrt(3.0) * spacing;
+    const int lim = (int)std::floor(link * link / ((double)spacing * spacing) + 1e-9);
+    hipStream_t s = (hipStream_t)stream;
+    int *d_index = (int *)d_ws, *d_label = d_index + top_n;
+    const int dm[3] = {dims[0], dims[1], dims[2]};
+    HIP_TRY(launch_site_extract(d_scores, dm, k, lim, d_index, d_label, s), "site extraction launch");
+    std::vector<int> h((size_t)2 * top_n);
+    HIP_TRY(hipMemcpyAsync(h.data(), d_index, h.size() * 4, hipMemcpyDeviceToHost, s), "site copy");
+    HIP_TRY(hipStreamSynchronize(s), "site extraction");
+    for (int a = 0; a < k; a++) {
+        const int idx = h[(size_t)a];
+        const int ijk[3] = {idx % dims[0], (idx / dims[0]) % dims[1], idx / (dims[0] * dims[1])};
+        for (int c = 0; c < 3; c++) points[3 * a + c] = origin[c] + (float)ijk[c] * spacing;
+        labels[a] = h[(size_t)top_n + a];
+    }
+    if (centre)
+        for (int c = 0; c < 3; c++) centre[c] = points[c];
+    *n_out = k;
+    return DSDP_OK;
+}
+
 dsdp_status dsdp_grids_set_site(dsdp_grids g, const float *points, int32_t n_points, float radius)
 {
     if (!g) return fail(DSDP_ERR_INVALID_ARG, "grids handle is NULL");

@@ -61,6 +61,7 @@ struct GridView {
     float site_r;
 };
 constexpr int kMaxSite = 256;
+constexpr int kMaxSitePoints = 1024;   // points one site extraction can return
 constexpr uint32_t kTagSite = 3;       // Philox stream of the initial positions in the search space
 constexpr int kSiteAttempts = 64;      // uniform box points tried (one per lane)
 
@@ -174,5 +175,9 @@ hipError_t launch_rank(const float *records, const float4 *best_xyz, const RankS
 // slots per lane; 3 atom lists.
 constexpr int kNumClasses = 4;
 int search_class(const LigHeader &h);
+// Top-k voxels of a score volume (dims x, y, z) and their single-linkage labels
+// (squared integer voxel offset <= lim links two voxels); k <= kMaxSitePoints.
+hipError_t launch_site_extract(const float *scores, const int *dims, int k, int lim, int *out_index, int *out_label,
+                               hipStream_t stream);
 
 }  // namespace dsdp

@@ -14,12 +14,12 @@ heavy atoms.
 """
 from .xs import (XS_NAMES, XS_INDEX, PALETTE_T4, PALETTE_T8, PALETTE_T9,
                  PALETTE_FULL)
-from .receptor import make_receptor, Receptor, make_site_points
+from .receptor import make_receptor, Receptor, make_site_points, make_score_volume
 from .ligand import make_ligand, Ligand
 from .configs import make_config, CONFIG_NAMES, make_box, request_ligand, request_ligand_job
 
 __all__ = [
     "XS_NAMES", "XS_INDEX", "PALETTE_T4", "PALETTE_T8", "PALETTE_T9", "PALETTE_FULL",
-    "make_receptor", "Receptor", "make_site_points", "make_ligand", "Ligand", "make_config",
+    "make_receptor", "Receptor", "make_site_points", "make_score_volume", "make_ligand", "Ligand", "make_config",
     "CONFIG_NAMES", "make_box", "request_ligand", "request_ligand_job",
 ]

@@ -180,3 +180,21 @@ def make_site_points(rec, n=200, radius=9.0, clearance=3.0, seed=0):
         if len(out) >= n:
             return np.asarray(out[:n], dtype=np.float32)
     raise ValueError("no room for site points around the pocket")
+
+
+def make_score_volume(rec, n=36, spacing=2.0, seed=0, noise=0.05):
+    """Synthetic site-predictor output (stand-in for the paper's 36^3 score
+    voxels): a cube of n^3 voxels at ``spacing`` A centred on the receptor's
+    centre, scores = a Gaussian blob (2.5 A) on the pocket point, a weaker decoy
+    blob at a random surface point, and uniform noise, clipped to [0, 1].
+    Returns (scores [n, n, n] float32 indexed [z, y, x], origin (3,) of voxel 0)."""
+    rng = np.random.default_rng([int(seed), 36])
+    origin = np.asarray(rec.xyz, dtype=np.float64).mean(axis=0) - (n - 1) * spacing / 2.0
+    z, y, x = np.mgrid[0:n, 0:n, 0:n]
+    pts = origin + np.stack([x, y, z], axis=-1) * spacing
+    u = rng.normal(size=3)
+    decoy = np.asarray(rec.xyz, dtype=np.float64).mean(axis=0) + 0.8 * rec.radius * u / np.linalg.norm(u)
+    d1 = np.sum((pts - rec.pocket) ** 2, axis=-1)
+    d2 = np.sum((pts - decoy) ** 2, axis=-1)
+    s = np.exp(-d1 / (2 * 2.5 ** 2)) + 0.6 * np.exp(-d2 / (2 * 2.5 ** 2)) + noise * rng.random((n, n, n))
+    return np.clip(s, 0.0, 1.0).astype(np.float32), origin
