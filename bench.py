@@ -442,6 +442,26 @@ def serve_leg(D, torch, cfg, first, count, rate, slots, spt, label):
     return out
 
 
+def gather_probe(D, torch, rec, box, types, maps, gws, stream, n_chains):
+    """Attainable rate of the search's map gathers (the eight corners of a cell
+    per atom, around a ligand-sized cloud per wave) on the workload's maps: with
+    the device full of waves (the gather roofline) and with as many waves as the
+    search launches for this request (what its occupancy allows)."""
+    g = D.dsdp_build_grids(rec.xyz, rec.types, box, types, maps, gws, stream)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    waves = n_chains * min(4, max(1, 8 * cus // n_chains))
+    full_blocks = cus * 8           # 32 waves per CU
+    ws = torch.empty(D.dsdp_gather_probe_workspace_bytes(full_blocks), dtype=torch.uint8, device="cuda")
+    full = max(D.dsdp_gather_probe(g, full_blocks, 256, ws, seed=k + 1, stream=stream) for k in range(3))
+    same = max(D.dsdp_gather_probe(g, waves // 4, 256, ws, seed=k + 1, stream=stream) for k in range(3))
+    D.dsdp_grids_release(g)
+    del ws
+    print(f"[bench] gather probe: {full / 1e9:.0f} GB/s with {full_blocks * 4} waves, {same / 1e9:.0f} GB/s with "
+          f"the search's {waves} waves", file=sys.stderr, flush=True)
+    return {"full_GBps": full / 1e9, "full_waves": full_blocks * 4, "search_waves_GBps": same / 1e9,
+            "search_waves": waves, "bytes_per_gather": 128}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -528,6 +548,7 @@ def main():
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    probe = gather_probe(D, torch, rec, box, types, maps, gws, stream, n_chains)
     del maps, gws, dws
 
     value = evals / elapsed
@@ -580,6 +601,8 @@ def main():
             "flops_per_eval": fpe,
             "gather_GBps": gather_gbps,
             "gather_frac_of_hbm": gather_gbps / HBM_PEAK_GBPS,
+            "gather_probe": probe,
+            "gather_frac_of_probe": gather_gbps / probe["full_GBps"],
         },
         "cpu_baseline": None,
         "batched": None,

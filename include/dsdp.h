@@ -206,6 +206,20 @@ void dsdp_grids_release(dsdp_grids g);
  */
 dsdp_status dsdp_grids_set_site(dsdp_grids g, const float *points, int32_t n_points, float radius);
 
+/*
+ * Gather-throughput probe of a set of maps (a measurement entry, not part of the
+ * method): blocks x 256 threads each make `rounds` trilinear reads (the eight
+ * corners of a cell, 128 B) of the maps, every wave around its own random centre
+ * with per-lane offsets of up to 5 A, the access pattern of a pose evaluation;
+ * *bytes_per_s = gathered bytes / device time (HIP events).  d_ws: device
+ * workspace of dsdp_gather_probe_workspace_bytes(blocks).  blocks in [1, 2^20],
+ * rounds in [1, 2^16], else DSDP_ERR_INVALID_ARG.  Synchronous (waits for the
+ * stream).
+ */
+size_t dsdp_gather_probe_workspace_bytes(int32_t blocks);
+dsdp_status dsdp_gather_probe(dsdp_grids g, int32_t blocks, int32_t rounds, uint64_t seed, void *d_ws,
+                              size_t ws_bytes, void *stream, double *bytes_per_s);
+
 /* Device workspace bytes for dsdp_site_points with top_n points (0 if top_n is out of range). */
 size_t dsdp_site_points_workspace_bytes(int32_t top_n);
 

@@ -103,6 +103,9 @@ _SIGS = {
                                     C.c_size_t, _vp, C.POINTER(dsdp_pose), C.POINTER(C.c_int32),
                                     C.POINTER(dsdp_dock_stats)]),
     "dsdp_grids_set_site": (C.c_int32, [_vp, C.POINTER(C.c_float), C.c_int32, C.c_float]),
+    "dsdp_gather_probe_workspace_bytes": (C.c_size_t, [C.c_int32]),
+    "dsdp_gather_probe": (C.c_int32, [_vp, C.c_int32, C.c_int32, C.c_uint64, _vp, C.c_size_t, _vp,
+                                      C.POINTER(C.c_double)]),
     "dsdp_site_points_workspace_bytes": (C.c_size_t, [C.c_int32]),
     "dsdp_site_points": (C.c_int32, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_float), C.c_float, C.c_int32,
                                      C.c_float, _vp, C.c_size_t, _vp, C.POINTER(C.c_float), C.POINTER(C.c_int32),
@@ -342,6 +345,18 @@ def dsdp_grids_set_site(grids, points, radius=7.0):
     around the site points ([n, 3]; empty: the plain box)."""
     pts = np.ascontiguousarray(np.asarray(points, dtype=np.float32).reshape(-1, 3))
     _check(lib().dsdp_grids_set_site(grids, pts.ctypes.data_as(C.POINTER(C.c_float)), len(pts), float(radius)))
+
+
+def dsdp_gather_probe_workspace_bytes(blocks):
+    return int(lib().dsdp_gather_probe_workspace_bytes(int(blocks)))
+
+
+def dsdp_gather_probe(grids, blocks, rounds, d_ws, seed=1, stream=None):
+    """Attainable gather rate (bytes/s) of the search's access pattern on these maps."""
+    r = C.c_double()
+    _check(lib().dsdp_gather_probe(grids, int(blocks), int(rounds), C.c_uint64(int(seed)), _ptr(d_ws), _nbytes(d_ws),
+                                   _stream(stream), C.byref(r)))
+    return r.value
 
 
 def dsdp_site_points_workspace_bytes(top_n):

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdsdp.so")
-SOURCES = ["grid_build.hip", "search.hip", "site.hip", "dsdp_abi.cpp", "dsdp_sched.cpp"]
+SOURCES = ["grid_build.hip", "search.hip", "site.hip", "probe.hip", "dsdp_abi.cpp", "dsdp_sched.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

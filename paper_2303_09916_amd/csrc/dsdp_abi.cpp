@@ -776,6 +776,34 @@ dsdp_status dsdp_build_grids(const dsdp_atom *rec, int32_t n_rec, const dsdp_box
 
 void dsdp_grids_release(dsdp_grids g) { delete g; }
 
+size_t dsdp_gather_probe_workspace_bytes(int32_t blocks)
+{
+    return blocks < 1 ? 0 : align256((size_t)blocks * 256 * 4);
+}
+
+dsdp_status dsdp_gather_probe(dsdp_grids g, int32_t blocks, int32_t rounds, uint64_t seed, void *d_ws,
+                              size_t ws_bytes, void *stream, double *bytes_per_s)
+{
+    if (!g || !bytes_per_s) return fail(DSDP_ERR_INVALID_ARG, "grids or result is NULL");
+    if (blocks < 1 || blocks > (1 << 20) || rounds < 1 || rounds > (1 << 16))
+        return fail(DSDP_ERR_INVALID_ARG, "blocks must be in [1, 2^20] and rounds in [1, 2^16]");
+    const size_t need = dsdp_gather_probe_workspace_bytes(blocks);
+    if (!d_ws || ws_bytes < need) return fail(DSDP_ERR_WORKSPACE_TOO_SMALL, "workspace needs %zu bytes", need);
+    hipStream_t s = (hipStream_t)stream;
+    Events ev;
+    HIP_TRY(ev.create(), "event");
+    HIP_TRY(launch_gather_probe(g->view, blocks, 1, (uint32_t)seed, (float *)d_ws, s), "probe launch");
+    HIP_TRY(hipEventRecord(ev.e[0], s), "event");
+    HIP_TRY(launch_gather_probe(g->view, blocks, rounds, (uint32_t)(seed >> 32) ^ 0x5bd1e995u, (float *)d_ws, s),
+            "probe launch");
+    HIP_TRY(hipEventRecord(ev.e[1], s), "event");
+    HIP_TRY(hipEventSynchronize(ev.e[1]), "probe");
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, ev.e[0], ev.e[1]), "event");
+    *bytes_per_s = (double)blocks * 256.0 * rounds * 128.0 / (ms * 1e-3);
+    return DSDP_OK;
+}
+
 size_t dsdp_site_points_workspace_bytes(int32_t top_n)
 {
     if (top_n < 1 || top_n > kMaxSitePoints) return 0;

@@ -158,6 +158,10 @@ hipError_t launch_grid_build(const float4 *atoms, const int *cell_start, const i
                              float cell, const GridView &g, const int *map_types_host, float4 *maps,
                              hipStream_t stream);
 size_t search_lds_bytes(const LigHeader &h, int waves);
+// Gather-throughput probe: blocks x 256 threads, rounds of 8-corner gathers each;
+// sink: blocks * 256 floats.
+hipError_t launch_gather_probe(const GridView &g, int blocks, int rounds, uint32_t seed, float *sink,
+                               hipStream_t stream);
 hipError_t launch_eval(const uint32_t *blob, int blob_words, const LigHeader &h, const GridView &g,
                        const SearchParams &p, const float *poses, int n, float *energy, float *grad, float *xyz,
                        hipStream_t stream);
