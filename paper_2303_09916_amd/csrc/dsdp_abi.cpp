@@ -164,18 +164,48 @@ dsdp_status prepare_ligand(const dsdp_ligand *lig, const int *map_of_type, Prepa
     dsdp_status st = validate_ligand(lig);
     if (st) return st;
     const int na = lig->n_atoms, nf = lig->n_frags;
+    // atom slots: fragments in depth-first preorder (children by index), each
+    // fragment's atoms in the caller's order; a subtree's atoms are then the
+    // contiguous slots from its root fragment's first slot to its end
+    std::vector<int> slot_atom, atom_slot(na), fs(nf), fe(nf), se(nf);
+    {
+        std::vector<std::vector<int>> kids(nf);
+        for (int k = 1; k < nf; k++) kids[lig->frag_parent[k]].push_back(k);
+        std::vector<int> stack{0}, order;
+        while (!stack.empty()) {
+            const int f = stack.back();
+            stack.pop_back();
+            order.push_back(f);
+            for (auto it = kids[f].rbegin(); it != kids[f].rend(); ++it) stack.push_back(*it);
+        }
+        for (int f : order) {
+            fs[f] = (int)slot_atom.size();
+            for (int i = lig->frag_start[f]; i < lig->frag_start[f + 1]; i++) slot_atom.push_back(i);
+            fe[f] = (int)slot_atom.size();
+        }
+        for (int v = 0; v < na; v++) atom_slot[slot_atom[v]] = v;
+        // subtree ends: children follow their parent in the order, so a reverse
+        // pass over it sees every child before its parent
+        for (int f = 0; f < nf; f++) se[f] = fe[f];
+        for (auto it = order.rbegin(); it != order.rend(); ++it)
+            if (*it > 0) se[lig->frag_parent[*it]] = std::max(se[lig->frag_parent[*it]], se[*it]);
+    }
+    // from here on atoms are numbered by slot
     std::vector<int> frag_of(na);
     for (int k = 0; k < nf; k++)
-        for (int i = lig->frag_start[k]; i < lig->frag_start[k + 1]; i++) frag_of[i] = k;
+        for (int v = fs[k]; v < fe[k]; v++) frag_of[v] = k;
     std::vector<double> ref(3 * na);
-    for (int i = 0; i < na; i++) {
-        ref[3 * i] = lig->atoms[i].x;
-        ref[3 * i + 1] = lig->atoms[i].y;
-        ref[3 * i + 2] = lig->atoms[i].z;
+    std::vector<int> xs(na);
+    for (int v = 0; v < na; v++) {
+        const dsdp_atom &at = lig->atoms[slot_atom[v]];
+        ref[3 * v] = at.x;
+        ref[3 * v + 1] = at.y;
+        ref[3 * v + 2] = at.z;
+        xs[v] = at.xs_type;
     }
     // root centre and gyration radius
     double c0[3] = {0, 0, 0};
-    const int n0 = lig->frag_start[1];
+    const int n0 = fe[0];   // the root's atoms are slots [0, n0)
     for (int i = 0; i < n0; i++)
         for (int a = 0; a < 3; a++) c0[a] += ref[3 * i + a] / n0;
     double s2 = 0;
@@ -186,13 +216,14 @@ dsdp_status prepare_ligand(const dsdp_ligand *lig, const int *map_of_type, Prepa
         if (k == 0)
             for (int a = 0; a < 3; a++) o[a] = c0[a];
         else
-            for (int a = 0; a < 3; a++) o[a] = ref[3 * lig->axis[2 * k + 1] + a];
+            for (int a = 0; a < 3; a++) o[a] = ref[3 * atom_slot[lig->axis[2 * k + 1]] + a];
     };
     // bond-graph distances -> intra pairs (different fragments, > 3 bonds apart)
     std::vector<std::vector<int>> adj(na);
     for (int b = 0; b < lig->n_bonds; b++) {
-        adj[lig->bonds[2 * b]].push_back(lig->bonds[2 * b + 1]);
-        adj[lig->bonds[2 * b + 1]].push_back(lig->bonds[2 * b]);
+        const int u = atom_slot[lig->bonds[2 * b]], v = atom_slot[lig->bonds[2 * b + 1]];
+        adj[u].push_back(v);
+        adj[v].push_back(u);
     }
     // pairs ordered by (j - i, i): 64 consecutive pairs (one wave-wide step of the
     // kernel) then touch distinct atoms
@@ -217,7 +248,7 @@ dsdp_status prepare_ligand(const dsdp_ligand *lig, const int *map_of_type, Prepa
     std::vector<float> rsum;
     for (const auto &ij : plist) {
         const int i = ij.first, j = ij.second;
-        const int ti = lig->atoms[i].xs_type, tj = lig->atoms[j].xs_type;
+        const int ti = xs[i], tj = xs[j];
         pairs.push_back((uint32_t)i | ((uint32_t)j << 8) | (pair_flags(ti, tj) << 16));
         rsum.push_back(xs_radius(ti) + xs_radius(tj));
     }
@@ -252,7 +283,8 @@ dsdp_status prepare_ligand(const dsdp_ligand *lig, const int *map_of_type, Prepa
     h.off_frag_u = take(4 * nf, 4);
     h.off_frag_off = take(4 * nf, 4);
     h.off_atom_frag = take(na, 1);
-    h.off_frag_start = take(nf + 1, 1);
+    h.off_atom_ext = take(na, 1);
+    h.off_frag_range = take(nf, 1);
     const int lpa = na <= 32 ? 2 : 1;
     h.lanes_per_atom = lpa;
     h.intra_form = form == DSDP_INTRA_PAIRS ? kFormPairs
@@ -308,13 +340,14 @@ dsdp_status prepare_ligand(const dsdp_ligand *lig, const int *map_of_type, Prepa
     for (int i = 0; i < na; i++) {
         double o[3];
         frag_origin(frag_of[i], o);
-        const int t = lig->atoms[i].xs_type;
+        const int t = xs[i];
         const int mi = map_of_type ? map_of_type[t] : 0;
-        if (mi < 0) return fail(DSDP_ERR_INVALID_ARG, "no map for ligand atom %d of XS type %d", i, t);
-        out.map_index[i] = mi;
+        if (mi < 0) return fail(DSDP_ERR_INVALID_ARG, "no map for ligand atom %d of XS type %d", slot_atom[i], t);
+        out.map_index[slot_atom[i]] = mi;
         for (int a = 0; a < 3; a++) fput(h.off_atom + 4 * i + a, (float)(ref[3 * i + a] - o[a]));
         blob[(size_t)h.off_atom + 4 * i + 3] = (uint32_t)mi;
         blob[(size_t)h.off_atom_frag + i] = (uint32_t)frag_of[i];
+        blob[(size_t)h.off_atom_ext + i] = (uint32_t)slot_atom[i];
     }
     for (int k = 0; k < nf; k++) {
         if (k == 0) {
@@ -322,7 +355,7 @@ dsdp_status prepare_ligand(const dsdp_ligand *lig, const int *map_of_type, Prepa
             for (int a = 0; a < 3; a++) fput(h.off_frag_off + a, 0.f);
             blob[(size_t)h.off_frag_u + 3] = 0u;   // no parent, depth 0
         } else {
-            const int ia = lig->axis[2 * k], ib = lig->axis[2 * k + 1];
+            const int ia = atom_slot[lig->axis[2 * k]], ib = atom_slot[lig->axis[2 * k + 1]];
             double u[3], nrm = 0, op[3];
             for (int a = 0; a < 3; a++) {
                 u[a] = ref[3 * ib + a] - ref[3 * ia + a];
@@ -338,7 +371,8 @@ dsdp_status prepare_ligand(const dsdp_ligand *lig, const int *map_of_type, Prepa
         }
         blob[(size_t)h.off_frag_off + 4 * k + 3] = sub[k];
     }
-    for (int k = 0; k <= nf; k++) blob[(size_t)h.off_frag_start + k] = (uint32_t)lig->frag_start[k];
+    for (int k = 0; k < nf; k++)
+        blob[(size_t)h.off_frag_range + k] = (uint32_t)fs[k] | ((uint32_t)fe[k] << 8) | ((uint32_t)se[k] << 16);
     if (h.intra_form == kFormPairs) {
         for (int p = 0; p < np; p++) {
             blob[(size_t)h.off_pair + p] = pairs[p];
@@ -363,7 +397,7 @@ dsdp_status prepare_ligand(const dsdp_ligand *lig, const int *map_of_type, Prepa
                 }
                 blob[(size_t)h.off_nbr + (size_t)m * 64 + l] = word;
             }
-        for (int i = 0; i < na; i++) fput(h.off_atom_rad + i, xs_radius(lig->atoms[i].xs_type));
+        for (int i = 0; i < na; i++) fput(h.off_atom_rad + i, xs_radius(xs[i]));
     }
     out.h = h;
     out.blob.swap(blob);

@@ -72,11 +72,15 @@ struct LigHeader {
     int32_t n_atoms, n_frags, n_tors, n_pairs;
     int32_t max_depth;
     float rg;                // gyration radius about the root centre (rotation amplitude scale)
+    // Atoms are stored in depth-first order of the fragments (each fragment's
+    // atoms in the caller's order), so that every fragment and every subtree
+    // covers a contiguous range of atom slots.
     int32_t off_atom;        // float4[n_atoms]: local offset xyz from the fragment origin, w = map index bits
     int32_t off_frag_u;      // float4[n_frags]: unit torsion axis, w = (parent + 1) | depth << 16
     int32_t off_frag_off;    // float4[n_frags]: fragment origin in the parent frame, w = subtree mask bits
     int32_t off_atom_frag;   // int[n_atoms]
-    int32_t off_frag_start;  // int[n_frags + 1]
+    int32_t off_atom_ext;    // int[n_atoms]: the caller's index of the atom in each slot
+    int32_t off_frag_range;  // uint32[n_frags]: first slot | end slot << 8 | subtree end slot << 16
     int32_t off_pair;        // uint32[n_pairs]: i | j << 8 | flags << 16
     int32_t off_pair_rsum;   // float[n_pairs]: R_i + R_j
     int32_t off_plist;       // uint4[n_chunks][64]: per gather lane, 8 u16 entries (pair | sign << 15) per chunk

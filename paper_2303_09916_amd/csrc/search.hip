@@ -54,6 +54,27 @@ __device__ __forceinline__ float wave_sum(float v)
     return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
 }
 
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_rows(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, false));
+}
+// Inclusive prefix sum over the 64 lanes (lane i gets v_0 + ... + v_i) in a
+// fixed order: a Kogge-Stone scan within each row of 16 lanes (DPP row shifts,
+// zero shifted in), then the last lane of row 0 is added to row 1 and that of
+// row 2 to row 3, and the last lane of row 1 to rows 2 and 3 (DPP row
+// broadcasts; rows outside the mask add zero).
+__device__ __forceinline__ float wave_scan(float v)
+{
+    v += dpp<0x111>(v);                 // row_shr:1
+    v += dpp<0x112>(v);                 // row_shr:2
+    v += dpp<0x114>(v);                 // row_shr:4
+    v += dpp<0x118>(v);                 // row_shr:8
+    v += dpp_rows<0x142, 0xA>(v);       // row_bcast:15 into rows 1 and 3
+    v += dpp_rows<0x143, 0xC>(v);       // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
 // ---------------------------------------------------------------- Philox4x32-10
 // Salmon et al., SC'11: ten rounds of two 32x32->64 multiplies, Weyl key bumps.
 __device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1)
@@ -235,7 +256,8 @@ struct LigL {
     const float4 *fu;        // torsion axis in parent frame, w = (parent + 1) | depth << 16
     const float4 *foff;      // origin in parent frame, w = subtree mask
     const int *atom_frag;
-    const int *frag_start;
+    const int *atom_ext;         // caller's index of the atom in each slot
+    const uint32_t *frag_range;  // first slot | end slot << 8 | subtree end slot << 16
     const uint32_t *pair;
     const float *rsum;
     const uint4 *plist;      // [n_chunks][64] gather lists (pair lists)
@@ -249,8 +271,7 @@ struct LigL {
 struct WaveL {
     float4 *xyz;
     float4 *pf;            // [np + 1] force of each pair on its first atom; slot np stays 0
-    float4 *af, *at;       // [na] total force and torque (about the fragment origin) per atom
-    float4 *ft;            // [2][nf]: per-fragment force, then torque about the fragment origin
+    float4 *af, *at;       // [na] prefix sums over atoms of force and of torque about the root origin
     float4 *R;       // [nf][4]: rows of R_k, then origin o_k
     float4 *Q;       // [nf][3]: rotation of fragment k relative to its parent (root: R(q))
     float *trial;    // [NXp]: this wave's trial pose
@@ -260,7 +281,8 @@ struct WaveL {
 // State of one chain, shared by the waves that work on it.
 struct ChainL {
     float *g, *p, *s, *y, *Hy;   // [Dp] BFGS vectors (tangent coordinates)
-    float *H;                    // [D][hs] inverse-Hessian estimate, row j owned by lane j
+    float *H;                    // [D][hs] inverse-Hessian estimate, row j owned by lane j; columns
+                                 // D..hs-1 stay zero; hs is a multiple of 4 (float4 rows)
     int hs;
     float *cur, *cand, *best;    // [NXp] poses
     float *et;                   // [4 * kMaxWaves]: energies (total, inter, intra, wall) per trial slot
@@ -274,7 +296,7 @@ constexpr int kOptBB = 1;        // SearchParams::optimizer value of Barzilai-Bo
 __host__ __device__ inline int rup4(int v) { return (v + 3) & ~3; }
 
 struct Layout {
-    int xyz, pf, af, at, R, Q, FT, trial, gt, wave_words;  // per-wave offsets
+    int xyz, pf, af, at, R, Q, trial, gt, wave_words;      // per-wave offsets
     int vec, H, hs, pose, et, misc, chain_words, Dp, NXp;     // per-chain offsets
 };
 __host__ __device__ inline Layout make_layout(int na, int nf, int np, int D, int nx)
@@ -289,14 +311,13 @@ __host__ __device__ inline Layout make_layout(int na, int nf, int np, int D, int
     c.at = w; w += 4 * na;
     c.R = w; w += 16 * nf;
     c.Q = w; w += 12 * nf;
-    c.FT = w; w += 8 * nf;
     c.trial = w; w += c.NXp;
     c.gt = w; w += c.Dp;
     c.wave_words = w;
     w = 0;
     c.vec = w; w += 5 * c.Dp;
-    c.hs = D + 1;
-    c.H = w; w += rup4(D * c.hs);
+    c.hs = c.Dp + 4;   // row stride off a multiple of the bank count
+    c.H = w; w += D * c.hs;
     c.pose = w; w += 3 * c.NXp;
     c.et = w; w += 4 * kMaxWaves;
     c.misc = w; w += 48;
@@ -313,7 +334,6 @@ __device__ inline WaveL make_wave(float *base, const Layout &c)
     S.at = reinterpret_cast<float4 *>(base + c.at);
     S.R = reinterpret_cast<float4 *>(base + c.R);
     S.Q = reinterpret_cast<float4 *>(base + c.Q);
-    S.ft = reinterpret_cast<float4 *>(base + c.FT);
     S.trial = base + c.trial;
     S.gt = base + c.gt;
     return S;
@@ -348,7 +368,8 @@ __device__ inline LigL make_lig(const uint32_t *blob, const uint32_t *hdr)
     L.fu = reinterpret_cast<const float4 *>(blob + h->off_frag_u);
     L.foff = reinterpret_cast<const float4 *>(blob + h->off_frag_off);
     L.atom_frag = reinterpret_cast<const int *>(blob + h->off_atom_frag);
-    L.frag_start = reinterpret_cast<const int *>(blob + h->off_frag_start);
+    L.atom_ext = reinterpret_cast<const int *>(blob + h->off_atom_ext);
+    L.frag_range = blob + h->off_frag_range;
     L.pair = blob + h->off_pair;
     L.rsum = reinterpret_cast<const float *>(blob + h->off_pair_rsum);
     L.plist = reinterpret_cast<const uint4 *>(blob + h->off_plist);
@@ -636,9 +657,7 @@ __device__ Energy eval_pose(const LigL &L, const WaveL &S, const IntraRegs<PPL, 
     float e_intra = 0.f;
     // (6) pair lists: pair forces gathered per atom from its list (8 entries per
     //     16-byte chunk); atom lists: the lane's own sum.  Two lanes per atom when
-    //     there are at most 32 atoms.  Then the atom's total
-    //     force and its torque about the fragment origin; per-fragment sums over
-    //     the fragment's contiguous atom range
+    //     there are at most 32 atoms.  Then the atom's total force
     {
         float3 fp = make_float3(0.f, 0.f, 0.f);
         if constexpr (PPL > 0) {
@@ -668,67 +687,59 @@ __device__ Energy eval_pose(const LigL &L, const WaveL &S, const IntraRegs<PPL, 
             fp.y += __shfl_xor(fp.y, 32, 64);
             fp.z += __shfl_xor(fp.z, 32, 64);
         }
-        if (lane < L.na) {
-            f = f + fp;
-            const float3 o = f3(S.R[4 * frag + 3]);
-            const float3 tq = cross3(x - o, f);
-            S.af[lane] = make_float4(f.x, f.y, f.z, 0.f);
-            S.at[lane] = make_float4(tq.x, tq.y, tq.z, 0.f);
-        }
+        if (lane < L.na) f = f + fp;
     }
-    wave_sync();
-    // per-fragment sums over the fragment's contiguous atom range, in atom order;
-    // the loads of four atoms are issued together
-    if (lane < L.nf) {
-        float3 F = make_float3(0.f, 0.f, 0.f), Tq = make_float3(0.f, 0.f, 0.f);
-        const int a0 = L.frag_start[lane], a1 = L.frag_start[lane + 1];
-        for (int a = a0; a < a1; a += 4) {
-            float4 fv[4], tv[4];
-#pragma unroll
-            for (int q = 0; q < 4; q++) {
-                const int b = min(a + q, a1 - 1);
-                fv[q] = S.af[b];
-                tv[q] = S.at[b];
-            }
-#pragma unroll
-            for (int q = 0; q < 4; q++)
-                if (a + q < a1) {
-                    F = F + f3(fv[q]);
-                    Tq = Tq + f3(tv[q]);
-                }
-        }
-        S.ft[lane] = make_float4(F.x, F.y, F.z, 0.f);
-        S.ft[L.nf + lane] = make_float4(Tq.x, Tq.y, Tq.z, 0.f);
-    }
-    wave_sync();
 
-    // (7) subtree sums from the subtree masks: fragment k's force and its torque
-    //     about o_k over every fragment m of its subtree (its descendants and
-    //     itself), F_sub(k) = sum F_m and tau_sub(k) = sum tau_m + (o_m - o_k) x F_m.
-    //     dE/dp = F_sub(0), dE/dw = tau_sub(0) (o_0 = p), dE/dtheta_k = u_k . tau_sub(k)
+    // (7) gradient in the tangent coordinates.  With the root origin p, atom
+    //     forces f_a and t_a = (x_a - p) x f_a, summed as lane prefix sums in
+    //     slot order: the subtree of fragment k (its descendants and itself)
+    //     covers the slots from k's first one to its subtree end, so its sums
+    //     F_sub(k), T_sub(k) are differences of two prefix sums, and its torque
+    //     about o_k is T_sub(k) - (o_k - p) x F_sub(k).
+    //     dE/dp = F_sub(0), dE/dw = T_sub(0), dE/dtheta_k = u_k . torque about o_k.
+    //     Fragment data are loaded first so that their latency hides under the scan.
+    const float3 o0 = make_float3(pose[0], pose[1], pose[2]);
+    uint32_t range = 0u;
+    float4 okv = make_float4(0.f, 0.f, 0.f, 0.f), uref = okv, rr0 = okv, rr1 = okv, rr2 = okv;
     if (lane < L.nf) {
-        const uint32_t mask = __float_as_uint(L.foff[lane].w);
-        const float3 ok = f3(S.R[4 * lane + 3]);
-        float3 F = make_float3(0.f, 0.f, 0.f), Tq = make_float3(0.f, 0.f, 0.f);
-#pragma unroll 4
-        for (int m = 0; m < L.nf; m++) {
-            if (mask & (1u << m)) {
-                const float3 Fm = f3(S.ft[m]), Tm = f3(S.ft[L.nf + m]);
-                F = F + Fm;
-                Tq = Tq + Tm + cross3(f3(S.R[4 * m + 3]) - ok, Fm);
-            }
+        range = L.frag_range[lane];
+        uref = L.fu[lane];
+        rr0 = S.R[4 * lane];
+        rr1 = S.R[4 * lane + 1];
+        rr2 = S.R[4 * lane + 2];
+        okv = S.R[4 * lane + 3];
+    }
+    {
+        const float3 tq = lane < L.na ? cross3(x - o0, f) : make_float3(0.f, 0.f, 0.f);
+        const float sfx = wave_scan(f.x), sfy = wave_scan(f.y), sfz = wave_scan(f.z);
+        const float stx = wave_scan(tq.x), sty = wave_scan(tq.y), stz = wave_scan(tq.z);
+        if (lane < L.na) {
+            S.af[lane] = make_float4(sfx, sfy, sfz, 0.f);
+            S.at[lane] = make_float4(stx, sty, stz, 0.f);
         }
-        if (lane == 0) {
-            grad[0] = F.x + g_site.x; grad[1] = F.y + g_site.y; grad[2] = F.z + g_site.z;
-            grad[3] = Tq.x; grad[4] = Tq.y; grad[5] = Tq.z;
-        } else {
-            const float4 uref = L.fu[lane];
-            const float4 r0 = S.R[4 * lane], r1 = S.R[4 * lane + 1], r2 = S.R[4 * lane + 2];
-            const float3 u = make_float3(r0.x * uref.x + r0.y * uref.y + r0.z * uref.z,
-                                         r1.x * uref.x + r1.y * uref.y + r1.z * uref.z,
-                                         r2.x * uref.x + r2.y * uref.y + r2.z * uref.z);
-            grad[6 + lane - 1] = dot3(u, Tq);
+    }
+    wave_sync();
+    float3 F = make_float3(0.f, 0.f, 0.f), Tq = F;
+    if (lane < L.nf) {
+        const int first = (int)(range & 255u), send = (int)((range >> 16) & 255u);
+        const float4 fe = S.af[send - 1], te = S.at[send - 1];
+        const float4 fb = S.af[max(first - 1, 0)], tb = S.at[max(first - 1, 0)];
+        F = f3(fe);
+        Tq = f3(te);
+        if (first > 0) {
+            F = F - f3(fb);
+            Tq = Tq - f3(tb);
         }
+    }
+    if (lane == 0) {
+        grad[0] = F.x + g_site.x; grad[1] = F.y + g_site.y; grad[2] = F.z + g_site.z;
+        grad[3] = Tq.x; grad[4] = Tq.y; grad[5] = Tq.z;
+    } else if (lane < L.nf) {
+        const float3 tk = Tq - cross3(f3(okv) - o0, F);
+        const float3 u = make_float3(rr0.x * uref.x + rr0.y * uref.y + rr0.z * uref.z,
+                                     rr1.x * uref.x + rr1.y * uref.y + rr1.z * uref.z,
+                                     rr2.x * uref.x + rr2.y * uref.y + rr2.z * uref.z);
+        grad[6 + lane - 1] = dot3(u, tk);
     }
     wave_sync();
     Energy out;
@@ -777,6 +788,129 @@ __device__ inline Energy get_energy(const float *slot)
     return e;
 }
 
+// Wave 0 of a chain: the BFGS inverse-Hessian update with s, y (when `upd`, i.e.
+// s.y = ys > 0), H <- H - rho (s (Hy)^T + (Hy) s^T) + (rho + rho^2 y.Hy) s s^T with
+// rho = 1 / ys, then the next direction p = -H g; returns g.p.  Lane j holds
+// s_j, y_j, g_j in sl, yl, gl (zero for j >= D) and owns row j of H, which is
+// read once as NQ float4 chunks, updated in registers and used for p before it
+// is written back.  C.s, C.y, C.g hold the same vectors, zero-padded to 4 NQ.
+template <int NQ>
+__device__ inline float bfgs_step(const ChainL &C, int D, bool upd, float ys, float sl, float yl, float gl)
+{
+    const int lane = lane_id();
+    const bool own = lane < D;
+    float4 *row = reinterpret_cast<float4 *>(C.H + (own ? lane : 0) * C.hs);
+    const float4 *s4 = reinterpret_cast<const float4 *>(C.s), *y4 = reinterpret_cast<const float4 *>(C.y);
+    const float4 *g4 = reinterpret_cast<const float4 *>(C.g), *hy4 = reinterpret_cast<const float4 *>(C.Hy);
+    wave_sync();
+    float4 h[NQ], gv[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; q++) {
+        h[q] = row[q];
+        gv[q] = g4[q];
+        if (!own) h[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    if (upd) {
+        float hy = 0.f;
+#pragma unroll
+        for (int q = 0; q < NQ; q++) {
+            const float4 yv = y4[q];
+            hy = fmaf(h[q].x, yv.x, hy);
+            hy = fmaf(h[q].y, yv.y, hy);
+            hy = fmaf(h[q].z, yv.z, hy);
+            hy = fmaf(h[q].w, yv.w, hy);
+        }
+        if (lane < 4 * NQ) C.Hy[lane] = hy;
+        const float yHy = wave_sum(yl * hy);
+        wave_sync();
+        const float rho = 1.f / ys;
+        const float aa = rho * (1.f + rho * yHy) * sl, bb = rho * sl, cc = rho * hy;
+#pragma unroll
+        for (int q = 0; q < NQ; q++) {
+            const float4 sv = s4[q], hv = hy4[q];
+            h[q].x += aa * sv.x - bb * hv.x - cc * sv.x;
+            h[q].y += aa * sv.y - bb * hv.y - cc * sv.y;
+            h[q].z += aa * sv.z - bb * hv.z - cc * sv.z;
+            h[q].w += aa * sv.w - bb * hv.w - cc * sv.w;
+        }
+        // the padding columns stay zero whatever the update's values
+        if (4 * NQ - 3 >= D) h[NQ - 1].y = 0.f;
+        if (4 * NQ - 2 >= D) h[NQ - 1].z = 0.f;
+        if (4 * NQ - 1 >= D) h[NQ - 1].w = 0.f;
+        if (own) {
+#pragma unroll
+            for (int q = 0; q < NQ; q++) row[q] = h[q];
+        }
+    }
+    float acc = 0.f;
+#pragma unroll
+    for (int q = 0; q < NQ; q++) {
+        acc = fmaf(h[q].x, gv[q].x, acc);
+        acc = fmaf(h[q].y, gv[q].y, acc);
+        acc = fmaf(h[q].z, gv[q].z, acc);
+        acc = fmaf(h[q].w, gv[q].w, acc);
+    }
+    const float pl = own ? -acc : 0.f;
+    if (lane < 4 * NQ) C.p[lane] = pl;
+    return wave_sum(pl * gl);
+}
+
+// The same step for any D, with H kept in LDS (D > 16: ligands with more than ten
+// torsions, where the registers of the step above would lower occupancy).
+__device__ inline float bfgs_step_any(const ChainL &C, int D, int nq, bool upd, float ys, float sl, float yl,
+                                      float gl)
+{
+    const int lane = lane_id();
+    const bool own = lane < D;
+    float4 *row = reinterpret_cast<float4 *>(C.H + (own ? lane : 0) * C.hs);
+    const float4 *s4 = reinterpret_cast<const float4 *>(C.s), *y4 = reinterpret_cast<const float4 *>(C.y);
+    const float4 *g4 = reinterpret_cast<const float4 *>(C.g), *hy4 = reinterpret_cast<const float4 *>(C.Hy);
+    wave_sync();
+    if (upd) {
+        float hy = 0.f;
+        for (int q = 0; q < nq; q++) {
+            const float4 hq = own ? row[q] : make_float4(0.f, 0.f, 0.f, 0.f), yv = y4[q];
+            hy = fmaf(hq.x, yv.x, hy);
+            hy = fmaf(hq.y, yv.y, hy);
+            hy = fmaf(hq.z, yv.z, hy);
+            hy = fmaf(hq.w, yv.w, hy);
+        }
+        if (lane < 4 * nq) C.Hy[lane] = hy;
+        const float yHy = wave_sum(yl * hy);
+        wave_sync();
+        const float rho = 1.f / ys;
+        const float aa = rho * (1.f + rho * yHy) * sl, bb = rho * sl, cc = rho * hy;
+        if (own) {
+            for (int q = 0; q < nq; q++) {
+                const float4 sv = s4[q], hv = hy4[q];
+                float4 hq = row[q];
+                hq.x += aa * sv.x - bb * hv.x - cc * sv.x;
+                hq.y += aa * sv.y - bb * hv.y - cc * sv.y;
+                hq.z += aa * sv.z - bb * hv.z - cc * sv.z;
+                hq.w += aa * sv.w - bb * hv.w - cc * sv.w;
+                if (q == nq - 1) {
+                    if (4 * nq - 3 >= D) hq.y = 0.f;
+                    if (4 * nq - 2 >= D) hq.z = 0.f;
+                    if (4 * nq - 1 >= D) hq.w = 0.f;
+                }
+                row[q] = hq;
+            }
+        }
+        wave_sync();
+    }
+    float acc = 0.f;
+    for (int q = 0; q < nq; q++) {
+        const float4 hq = own ? row[q] : make_float4(0.f, 0.f, 0.f, 0.f), gq = g4[q];
+        acc = fmaf(hq.x, gq.x, acc);
+        acc = fmaf(hq.y, gq.y, acc);
+        acc = fmaf(hq.z, gq.z, acc);
+        acc = fmaf(hq.w, gq.w, acc);
+    }
+    const float pl = own ? -acc : 0.f;
+    if (lane < 4 * nq) C.p[lane] = pl;
+    return wave_sum(pl * gl);
+}
+
 // Local optimisation of the chain's pose x (LDS, in place), run by all W waves of
 // the workgroup together: BFGS with Armijo backtracking, or the Barzilai-Borwein
 // gradient method (no line search: wave 0 alone evaluates one point per
@@ -806,6 +940,8 @@ __device__ Energy local_opt_group(const LigL &L, const Layout &lay, float *wave_
     float alpha0 = 1.f;   // alpha of the round's first trial
     float bb_a = P.bb_step0;   // Barzilai-Borwein step length (wave 0)
     float *xb = C.H;           // Barzilai-Borwein: lowest-energy iterate (the matrix is unused)
+    const int Dp = lay.Dp;
+    float s_l = 0.f, y_l = 0.f, g_l = 0.f, ys = 0.f;   // wave 0: this iteration's s, y, new g; s.y
     // Every evaluation of the local optimisation goes through the one call below
     // (the start pose by wave 0, then one line-search trial per wave per round),
     // so the kernel holds a single copy of the evaluation code.
@@ -833,10 +969,17 @@ __device__ Energy local_opt_group(const LigL &L, const Layout &lay, float *wave_
         if (t0 < 0) {
             Ex = get_energy(C.et);
             evals++;
-            if (w == 0 && lane < D) {
-                C.g[lane] = S.gt[lane];
-                if (!bb)
-                    for (int c = 0; c < D; c++) C.H[lane * C.hs + c] = (c == lane) ? 1.f : 0.f;
+            if (w == 0 && lane < Dp) {
+                g_l = lane < D ? S.gt[lane] : 0.f;
+                C.g[lane] = g_l;
+                if (!bb && lane < D) {
+                    float4 *row = reinterpret_cast<float4 *>(C.H + lane * C.hs);
+                    for (int q = 0; q < (Dp >> 2); q++) {
+                        const int c = 4 * q;
+                        row[q] = make_float4(c == lane ? 1.f : 0.f, c + 1 == lane ? 1.f : 0.f,
+                                             c + 2 == lane ? 1.f : 0.f, c + 3 == lane ? 1.f : 0.f);
+                    }
+                }
             }
             if (bb) {
                 Eb = Ex;
@@ -866,9 +1009,14 @@ __device__ Energy local_opt_group(const LigL &L, const Layout &lay, float *wave_
         } else {
             int acc_slot = -1;
             float a = alpha0, alpha_acc = 0.f;
+            float et[kMaxWaves];
+#pragma unroll
+            for (int q = 0; q < kMaxWaves; q++) et[q] = C.et[4 * q];
             int v = 0;
-            for (; v < W && t0 + v < P.ls_trials; v++) {
-                if (C.et[4 * v] <= Ex.total + P.armijo_c1 * a * gp) {
+#pragma unroll
+            for (; v < kMaxWaves; v++) {
+                if (v >= W || t0 + v >= P.ls_trials) break;
+                if (et[v] <= Ex.total + P.armijo_c1 * a * gp) {
                     acc_slot = v;
                     alpha_acc = a;
                     break;
@@ -886,59 +1034,48 @@ __device__ Energy local_opt_group(const LigL &L, const Layout &lay, float *wave_
             const Energy Et = get_energy(C.et + 4 * acc_slot);
             if (w == 0) {
                 const WaveL A = make_wave(wave_base + acc_slot * lay.wave_words, lay);
-                float sl = 0.f, yl = 0.f;
+                s_l = 0.f;
+                y_l = 0.f;
                 if (lane < D) {
-                    const float gl = C.g[lane];
-                    sl = alpha_acc * C.p[lane];
-                    yl = A.gt[lane] - gl;
-                    C.s[lane] = sl;
-                    C.y[lane] = yl;
-                    C.g[lane] = A.gt[lane];
+                    const float gn = A.gt[lane];
+                    s_l = alpha_acc * C.p[lane];
+                    y_l = gn - g_l;
+                    g_l = gn;
+                }
+                if (lane < Dp) {
+                    C.s[lane] = s_l;
+                    C.y[lane] = y_l;
+                    C.g[lane] = g_l;
                 }
                 if (lane < L.nx) x[lane] = A.trial[lane];
-                const float ys = wave_sum(sl * yl);
-                wave_sync();
-                if (ys > 0.f) {
-                    const float rho = 1.f / ys;
-                    float hy = 0.f;
-                    if (lane < D) {
-#pragma unroll 4
-                        for (int c = 0; c < D; c++) hy += C.H[lane * C.hs + c] * C.y[c];
-                        C.Hy[lane] = hy;
-                    }
-                    const float yHy = wave_sum(yl * hy);
-                    wave_sync();
-                    if (lane < D) {
-                        const float aa = rho * (1.f + rho * yHy) * sl, bb = rho * sl, cc = rho * hy;
-#pragma unroll 4
-                        for (int c = 0; c < D; c++) {
-                            const float sc = C.s[c], hc = C.Hy[c];
-                            C.H[lane * C.hs + c] += aa * sc - bb * hc - cc * sc;
-                        }
-                    }
-                }
+                ys = wave_sum(s_l * y_l);
             }
             Ex = Et;
             it++;
         }
         if (it >= iters) break;
-        // direction of the next iteration: p = -g (Barzilai-Borwein) or p = -H g
-        // (BFGS; wave 0, which also wrote g and H)
-        if (w == 0 && bb) {
+        // direction of the next iteration: p = -g (Barzilai-Borwein; after the
+        // start evaluation of BFGS, where H = I), else the BFGS update of H with
+        // this iteration's s, y when s.y > 0 and p = -H g (wave 0, which owns g and H)
+        if (w == 0 && (bb || t0 < 0)) {
             wave_sync();
-            if (lane < D) C.p[lane] = -C.g[lane];
-        } else if (w == 0) {
-            wave_sync();
-            float pl = 0.f, gl = 0.f;
-            if (lane < D) {
-                float acc = 0.f;
-#pragma unroll 4
-                for (int c = 0; c < D; c++) acc += C.H[lane * C.hs + c] * C.g[c];
-                pl = -acc;
-                gl = C.g[lane];
-                C.p[lane] = pl;
+            if (bb) {
+                if (lane < D) C.p[lane] = -C.g[lane];
+            } else {
+                const float pl = -g_l;
+                if (lane < Dp) C.p[lane] = pl;
+                const float g_p = wave_sum(pl * g_l);
+                if (lane == 0) C.misc[kMiscGp] = g_p;
             }
-            const float g_p = wave_sum(pl * gl);
+        } else if (w == 0) {
+            const bool upd = ys > 0.f;
+            float g_p;
+            switch (Dp >> 2) {
+            case 2: g_p = bfgs_step<2>(C, D, upd, ys, s_l, y_l, g_l); break;
+            case 3: g_p = bfgs_step<3>(C, D, upd, ys, s_l, y_l, g_l); break;
+            case 4: g_p = bfgs_step<4>(C, D, upd, ys, s_l, y_l, g_l); break;
+            default: g_p = bfgs_step_any(C, D, Dp >> 2, upd, ys, s_l, y_l, g_l); break;
+            }
             if (lane == 0) C.misc[kMiscGp] = g_p;
         }
         __syncthreads();
@@ -991,7 +1128,7 @@ __global__ __launch_bounds__(256) void eval_kernel(const uint32_t *__restrict__ 
     if (lane < L.D) grad[(long)idx * L.D + lane] = S.gt[lane];
     if (xyz && lane < L.na) {
         const float4 v = S.xyz[lane];
-        float *o = xyz + ((long)idx * L.na + lane) * 3;
+        float *o = xyz + ((long)idx * L.na + L.atom_ext[lane]) * 3;
         o[0] = v.x; o[1] = v.y; o[2] = v.z;
     }
 }
@@ -1203,7 +1340,7 @@ __global__ __launch_bounds__(256) void tick_kernel(const uint32_t *arena, const 
     }
     if (lane < L.na) {
         const float3 xb = atom_position(L, S, lane);
-        best_xyz[(long)t.slot * kXyzStride + lane] = make_float4(xb.x, xb.y, xb.z, 0.f);
+        best_xyz[(long)t.slot * kXyzStride + L.atom_ext[lane]] = make_float4(xb.x, xb.y, xb.z, 0.f);
     }
 }
 
