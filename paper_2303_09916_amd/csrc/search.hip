@@ -390,6 +390,9 @@ template <int PPL, int NBW>
 struct IntraRegs {
     uint32_t w[PPL > 0 ? PPL : 1];
     float rs[PPL > 0 ? PPL : 1];
+    uint4 pl[PPL == 8 ? 2 : 1];   // eight pairs per lane: the lane's first two gather chunks
+    float4 loc;       // the lane's atom: local offset, w = map index bits
+    int frag;         // the lane's atom: fragment
 };
 template <int PPL, int NBW>
 __device__ inline IntraRegs<PPL, NBW> load_intra(const LigL &L)
@@ -403,6 +406,19 @@ __device__ inline IntraRegs<PPL, NBW> load_intra(const LigL &L)
             pr.w[k] = p < L.np ? L.pair[p] : kPairNone;
             pr.rs[k] = p < L.np ? L.rsum[p] : 0.f;
         }
+        if constexpr (PPL == 8) {
+#pragma unroll
+            for (int c = 0; c < 2; c++) {
+                const uint32_t pad = (uint32_t)L.np | ((uint32_t)L.np << 16);
+                pr.pl[c] = c < L.n_chunks ? L.plist[c * 64 + lane] : make_uint4(pad, pad, pad, pad);
+            }
+        }
+    }
+    pr.loc = make_float4(0.f, 0.f, 0.f, 0.f);
+    pr.frag = 0;
+    if (lane < L.na) {
+        pr.loc = L.atom[lane];
+        pr.frag = L.atom_frag[lane];
     }
     return pr;
 }
@@ -493,8 +509,8 @@ __device__ Energy eval_pose(const LigL &L, const WaveL &S, const IntraRegs<PPL, 
     float4 c000, c100, c010, c110, c001, c101, c011, c111;
     int frag = 0;
     if (lane < L.na) {
-        frag = L.atom_frag[lane];
-        const float4 loc = L.atom[lane];
+        frag = pr.frag;
+        const float4 loc = pr.loc;
         const float4 r0 = S.R[4 * frag], r1 = S.R[4 * frag + 1], r2 = S.R[4 * frag + 2], o = S.R[4 * frag + 3];
         x = make_float3(o.x + r0.x * loc.x + r0.y * loc.y + r0.z * loc.z,
                         o.y + r1.x * loc.x + r1.y * loc.y + r1.z * loc.z,
@@ -555,23 +571,32 @@ __device__ Energy eval_pose(const LigL &L, const WaveL &S, const IntraRegs<PPL, 
     float e_lane = 0.f;   // atom lists: this lane's share of the intra energy
     float3 fnb = make_float3(0.f, 0.f, 0.f);
     if constexpr (PPL > 0) {
+        // groups of slots: the position loads first, then the pair terms
+        // without branches (out-of-cutoff and padding pairs select 0)
         const int slots = (L.np + 63) >> 6;
+        constexpr int kGroup = PPL == 8 ? 4 : 2;   // fewer registers for the larger lists
 #pragma unroll
-        for (int k = 0; k < PPL; k++) {
-            if (k < slots) {
-                const uint32_t pw = pr.w[k];
-                const int i = (int)(pw & 255u), j = (int)((pw >> 8) & 255u);
-                const float4 xi = S.xyz[i], xj = S.xyz[j];
-                const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
-                const float r2 = pair_r2(dx, dy, dz);
-                float sp = 0.f, ep = 0.f;
-                if (!(pw & kPairNone) && r2 < kCutoff2) {
-                    const float2 es = pair_term(r2, pr.rs[k], pw >> 16);
-                    ep = es.x;
-                    sp = es.y;
+        for (int g = 0; g < PPL; g += kGroup) {
+            if (g < slots) {
+                float4 xi[kGroup], xj[kGroup];
+#pragma unroll
+                for (int k = 0; k < kGroup; k++) {
+                    const uint32_t pw = pr.w[g + k];
+                    xi[k] = S.xyz[pw & 255u];
+                    xj[k] = S.xyz[(pw >> 8) & 255u];
                 }
-                if (!(pw & kPairNone))
-                    S.pf[lane + 64 * k] = make_float4(mul_rounded(sp, dx), mul_rounded(sp, dy), mul_rounded(sp, dz), ep);
+#pragma unroll
+                for (int k = 0; k < kGroup; k++) {
+                    const uint32_t pw = pr.w[g + k];
+                    const float dx = xi[k].x - xj[k].x, dy = xi[k].y - xj[k].y, dz = xi[k].z - xj[k].z;
+                    const float r2 = pair_r2(dx, dy, dz);
+                    const float2 es = pair_term(r2, pr.rs[g + k], pw >> 16);
+                    const bool in = r2 < kCutoff2;
+                    const float ep = in ? es.x : 0.f, sp = in ? es.y : 0.f;
+                    if (!(pw & kPairNone))
+                        S.pf[lane + 64 * (g + k)] =
+                            make_float4(mul_rounded(sp, dx), mul_rounded(sp, dy), mul_rounded(sp, dz), ep);
+                }
             }
         }
     } else {
@@ -661,7 +686,33 @@ __device__ Energy eval_pose(const LigL &L, const WaveL &S, const IntraRegs<PPL, 
     {
         float3 fp = make_float3(0.f, 0.f, 0.f);
         if constexpr (PPL > 0) {
-            for (int c = 0; c < L.n_chunks; c++) {
+            // eight pairs per lane: the first two chunks' lists are in registers
+            // and their sixteen loads are issued together (the entries are
+            // added in list order, as in the loop that takes any further chunks
+            // from LDS)
+            constexpr int kRegChunks = PPL == 8 ? 2 : 0;
+            if constexpr (kRegChunks > 0) {
+                float4 v[16];
+#pragma unroll
+                for (int t = 0; t < 16; t++) {
+                    const uint4 q = pr.pl[t >> 3];
+                    const uint32_t wv = (t & 7) < 2 ? q.x : (t & 7) < 4 ? q.y : (t & 7) < 6 ? q.z : q.w;
+                    const uint32_t e = (t & 1) ? (wv >> 16) : (wv & 0xffffu);
+                    v[t] = S.pf[e & 0x7fffu];
+                }
+#pragma unroll
+                for (int t = 0; t < 16; t++) {
+                    if (t == 8 && L.n_chunks < 2) break;
+                    const uint4 q = pr.pl[t >> 3];
+                    const uint32_t wv = (t & 7) < 2 ? q.x : (t & 7) < 4 ? q.y : (t & 7) < 6 ? q.z : q.w;
+                    const uint32_t e = (t & 1) ? (wv >> 16) : (wv & 0xffffu);
+                    const bool second = (e & 0x8000u) != 0;
+                    const float sg = second ? -1.f : 1.f;
+                    fp = fp + sg * f3(v[t]);
+                    e_lane += second ? 0.f : v[t].w;
+                }
+            }
+            for (int c = kRegChunks; c < L.n_chunks; c++) {
                 const uint4 q = L.plist[c * 64 + lane];
                 const uint32_t e[8] = {q.x & 0xffffu, q.x >> 16, q.y & 0xffffu, q.y >> 16,
                                        q.z & 0xffffu, q.z >> 16, q.w & 0xffffu, q.w >> 16};
@@ -1009,9 +1060,12 @@ __device__ Energy local_opt_group(const LigL &L, const Layout &lay, float *wave_
         } else {
             int acc_slot = -1;
             float a = alpha0, alpha_acc = 0.f;
+            float4 et4[kMaxWaves];
+#pragma unroll
+            for (int q = 0; q < kMaxWaves; q++) et4[q] = reinterpret_cast<const float4 *>(C.et)[q];
             float et[kMaxWaves];
 #pragma unroll
-            for (int q = 0; q < kMaxWaves; q++) et[q] = C.et[4 * q];
+            for (int q = 0; q < kMaxWaves; q++) et[q] = et4[q].x;
             int v = 0;
 #pragma unroll
             for (; v < kMaxWaves; v++) {
@@ -1031,7 +1085,15 @@ __device__ Energy local_opt_group(const LigL &L, const Layout &lay, float *wave_
                 __syncthreads();   // this round's energies are read before the next round writes
                 continue;
             }
-            const Energy Et = get_energy(C.et + 4 * acc_slot);
+            float4 e_acc = et4[0];
+#pragma unroll
+            for (int q = 1; q < kMaxWaves; q++)
+                if (acc_slot == q) e_acc = et4[q];
+            Energy Et;
+            Et.total = e_acc.x;
+            Et.inter = e_acc.y;
+            Et.intra = e_acc.z;
+            Et.wall = e_acc.w;
             if (w == 0) {
                 const WaveL A = make_wave(wave_base + acc_slot * lay.wave_words, lay);
                 s_l = 0.f;
