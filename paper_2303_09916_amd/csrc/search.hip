@@ -306,7 +306,9 @@ __host__ __device__ inline Layout make_layout(int na, int nf, int np, int D, int
     c.NXp = rup4(nx);
     int w = 0;
     c.xyz = w; w += 4 * na;
-    c.pf = w; w += 4 * (np + 1);   // np = -1: no pair-force scratch (atom lists)
+    // np = -1: no pair-force scratch (atom lists); else the pairs, the zero slot
+    // np, and entries up to a whole group of two 64-pair slots
+    c.pf = w; w += np < 0 ? 0 : 4 * max(np + 1, 128 * ((np + 127) / 128));
     c.af = w; w += 4 * na;
     c.at = w; w += 4 * na;
     c.R = w; w += 16 * nf;
@@ -574,7 +576,7 @@ __device__ Energy eval_pose(const LigL &L, const WaveL &S, const IntraRegs<PPL, 
         // groups of slots: the position loads first, then the pair terms
         // without branches (out-of-cutoff and padding pairs select 0)
         const int slots = (L.np + 63) >> 6;
-        constexpr int kGroup = PPL == 8 ? 4 : 2;   // fewer registers for the larger lists
+        constexpr int kGroup = 2;
 #pragma unroll
         for (int g = 0; g < PPL; g += kGroup) {
             if (g < slots) {
@@ -591,11 +593,19 @@ __device__ Energy eval_pose(const LigL &L, const WaveL &S, const IntraRegs<PPL, 
                     const float dx = xi[k].x - xj[k].x, dy = xi[k].y - xj[k].y, dz = xi[k].z - xj[k].z;
                     const float r2 = pair_r2(dx, dy, dz);
                     const float2 es = pair_term(r2, pr.rs[g + k], pw >> 16);
-                    const bool in = r2 < kCutoff2;
+                    const bool none = (pw & kPairNone) != 0;
+                    const bool in = !none && r2 < kCutoff2;
                     const float ep = in ? es.x : 0.f, sp = in ? es.y : 0.f;
-                    if (!(pw & kPairNone))
-                        S.pf[lane + 64 * (g + k)] =
-                            make_float4(mul_rounded(sp, dx), mul_rounded(sp, dy), mul_rounded(sp, dz), ep);
+                    const float4 v = make_float4(mul_rounded(sp, dx), mul_rounded(sp, dy), mul_rounded(sp, dz), ep);
+                    if constexpr (PPL == 8) {
+                        // a padding lane (both indices 0, so dx = dy = dz = +0)
+                        // stores +0 into its own entry, at or past the zero slot np
+                        // (the array is padded to whole groups): no branch, so the
+                        // group's pair terms interleave
+                        S.pf[lane + 64 * (g + k)] = v;
+                    } else if (!none) {
+                        S.pf[lane + 64 * (g + k)] = v;   // fewer registers live for the larger lists
+                    }
                 }
             }
         }
