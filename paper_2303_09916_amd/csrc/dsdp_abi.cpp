@@ -285,6 +285,7 @@ dsdp_status prepare_ligand(const dsdp_ligand *lig, const int *map_of_type, Prepa
     h.off_atom_frag = take(na, 1);
     h.off_atom_ext = take(na, 1);
     h.off_frag_range = take(nf, 1);
+    h.off_frag_anc = take(nf, 1);
     const int lpa = na <= 32 ? 2 : 1;
     h.lanes_per_atom = lpa;
     h.intra_form = form == DSDP_INTRA_PAIRS ? kFormPairs
@@ -371,8 +372,14 @@ dsdp_status prepare_ligand(const dsdp_ligand *lig, const int *map_of_type, Prepa
         }
         blob[(size_t)h.off_frag_off + 4 * k + 3] = sub[k];
     }
-    for (int k = 0; k < nf; k++)
+    for (int k = 0; k < nf; k++) {
         blob[(size_t)h.off_frag_range + k] = (uint32_t)fs[k] | ((uint32_t)fe[k] << 8) | ((uint32_t)se[k] << 16);
+        uint32_t anc = 0;
+        int b = 0;
+        for (int m = k > 0 ? lig->frag_parent[k] : 0; m > 0 && b < 4; m = lig->frag_parent[m], b++)
+            anc |= (uint32_t)m << (8 * b);
+        blob[(size_t)h.off_frag_anc + k] = anc;
+    }
     if (h.intra_form == kFormPairs) {
         for (int p = 0; p < np; p++) {
             blob[(size_t)h.off_pair + p] = pairs[p];

@@ -81,6 +81,8 @@ struct LigHeader {
     int32_t off_atom_frag;   // int[n_atoms]
     int32_t off_atom_ext;    // int[n_atoms]: the caller's index of the atom in each slot
     int32_t off_frag_range;  // uint32[n_frags]: first slot | end slot << 8 | subtree end slot << 16
+    int32_t off_frag_anc;    // uint32[n_frags]: up to four ancestors below the root, nearest first, one
+                             // byte each, 0 after the last
     int32_t off_pair;        // uint32[n_pairs]: i | j << 8 | flags << 16
     int32_t off_pair_rsum;   // float[n_pairs]: R_i + R_j
     int32_t off_plist;       // uint4[n_chunks][64]: per gather lane, 8 u16 entries (pair | sign << 15) per chunk

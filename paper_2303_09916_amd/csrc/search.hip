@@ -153,14 +153,15 @@ __device__ __forceinline__ float3 operator-(float3 a, float3 b) { return make_fl
 __device__ __forceinline__ float3 operator*(float s, float3 a) { return make_float3(s * a.x, s * a.y, s * a.z); }
 __device__ __forceinline__ float dot3(float3 a, float3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
 
-// unit quaternion of rotation vector v (angle |v| about v/|v|)
+// unit quaternion of rotation vector v (angle |v| about v/|v|), (w, x, y, z);
+// the identity for v = 0 (selected, no branch)
 __device__ __forceinline__ float4 quat_of_rotvec(float vx, float vy, float vz)
 {
     const float a = sqrtf(vx * vx + vy * vy + vz * vz);
-    if (a == 0.0f) return make_float4(1.f, 0.f, 0.f, 0.f);   // (w, x, y, z)
     const float s = __sinf(0.5f * a), c = __cosf(0.5f * a);
     const float k = s / a;
-    return make_float4(c, k * vx, k * vy, k * vz);
+    const bool z = a == 0.0f;
+    return make_float4(z ? 1.f : c, z ? 0.f : k * vx, z ? 0.f : k * vy, z ? 0.f : k * vz);
 }
 // Hamilton product a * b, (w, x, y, z) in (x, y, z, w) slots of float4 as w=x-slot
 __device__ __forceinline__ float4 quat_mul(float4 a, float4 b)
@@ -176,13 +177,22 @@ __device__ __forceinline__ float4 quat_normalize(float4 q)
     return make_float4(q.x * k, q.y * k, q.z * k, q.w * k);
 }
 // into (-pi, pi]; non-finite values pass through, huge ones are reduced first
-__device__ __forceinline__ float wrap_angle(float t)
+__device__ __forceinline__ float wrap_angle_loop(float t)
 {
     if (!(fabsf(t) < 3.0e38f)) return t;
     if (fabsf(t) > 1.0e4f) t = fmodf(t, 2 * kPi);
     while (t > kPi) t -= 2 * kPi;
     while (t <= -kPi) t += 2 * kPi;
     return t;
+}
+// The same values: at most one turn off (the usual case) takes one correction
+// without a branch; anything else takes the loop above.
+__device__ __forceinline__ float wrap_angle(float t)
+{
+    float u = t > kPi ? t - 2 * kPi : t;
+    u = u <= -kPi ? u + 2 * kPi : u;
+    if (!(u > -kPi && u <= kPi)) u = wrap_angle_loop(t);
+    return u;
 }
 // point in the unit ball: direction (z = 2u1 - 1, phi = 2 pi u2), radius u3^(1/3)
 __device__ __forceinline__ float3 ball(float u1, float u2, float u3)
@@ -258,6 +268,7 @@ struct LigL {
     const int *atom_frag;
     const int *atom_ext;         // caller's index of the atom in each slot
     const uint32_t *frag_range;  // first slot | end slot << 8 | subtree end slot << 16
+    const uint32_t *frag_anc;    // up to four ancestors below the root, nearest first, a byte each
     const uint32_t *pair;
     const float *rsum;
     const uint4 *plist;      // [n_chunks][64] gather lists (pair lists)
@@ -273,7 +284,6 @@ struct WaveL {
     float4 *pf;            // [np + 1] force of each pair on its first atom; slot np stays 0
     float4 *af, *at;       // [na] prefix sums over atoms of force and of torque about the root origin
     float4 *R;       // [nf][4]: rows of R_k, then origin o_k
-    float4 *Q;       // [nf][3]: rotation of fragment k relative to its parent (root: R(q))
     float *trial;    // [NXp]: this wave's trial pose
     float *gt;       // [Dp]: gradient at the trial pose
 };
@@ -296,7 +306,7 @@ constexpr int kOptBB = 1;        // SearchParams::optimizer value of Barzilai-Bo
 __host__ __device__ inline int rup4(int v) { return (v + 3) & ~3; }
 
 struct Layout {
-    int xyz, pf, af, at, R, Q, trial, gt, wave_words;      // per-wave offsets
+    int xyz, pf, af, at, R, trial, gt, wave_words;         // per-wave offsets
     int vec, H, hs, pose, et, misc, chain_words, Dp, NXp;     // per-chain offsets
 };
 __host__ __device__ inline Layout make_layout(int na, int nf, int np, int D, int nx)
@@ -312,7 +322,6 @@ __host__ __device__ inline Layout make_layout(int na, int nf, int np, int D, int
     c.af = w; w += 4 * na;
     c.at = w; w += 4 * na;
     c.R = w; w += 16 * nf;
-    c.Q = w; w += 12 * nf;
     c.trial = w; w += c.NXp;
     c.gt = w; w += c.Dp;
     c.wave_words = w;
@@ -335,7 +344,6 @@ __device__ inline WaveL make_wave(float *base, const Layout &c)
     S.af = reinterpret_cast<float4 *>(base + c.af);
     S.at = reinterpret_cast<float4 *>(base + c.at);
     S.R = reinterpret_cast<float4 *>(base + c.R);
-    S.Q = reinterpret_cast<float4 *>(base + c.Q);
     S.trial = base + c.trial;
     S.gt = base + c.gt;
     return S;
@@ -372,6 +380,7 @@ __device__ inline LigL make_lig(const uint32_t *blob, const uint32_t *hdr)
     L.atom_frag = reinterpret_cast<const int *>(blob + h->off_atom_frag);
     L.atom_ext = reinterpret_cast<const int *>(blob + h->off_atom_ext);
     L.frag_range = blob + h->off_frag_range;
+    L.frag_anc = blob + h->off_frag_anc;
     L.pair = blob + h->off_pair;
     L.rsum = reinterpret_cast<const float *>(blob + h->off_pair_rsum);
     L.plist = reinterpret_cast<const uint4 *>(blob + h->off_plist);
@@ -395,6 +404,7 @@ struct IntraRegs {
     uint4 pl[PPL == 8 ? 2 : 1];   // eight pairs per lane: the lane's first two gather chunks
     float4 loc;       // the lane's atom: local offset, w = map index bits
     int frag;         // the lane's atom: fragment
+    uint32_t anc;     // the lane's fragment: ancestors below the root (LigL::frag_anc)
 };
 template <int PPL, int NBW>
 __device__ inline IntraRegs<PPL, NBW> load_intra(const LigL &L)
@@ -418,6 +428,7 @@ __device__ inline IntraRegs<PPL, NBW> load_intra(const LigL &L)
     }
     pr.loc = make_float4(0.f, 0.f, 0.f, 0.f);
     pr.frag = 0;
+    pr.anc = lane < L.nf ? L.frag_anc[lane] : 0u;
     if (lane < L.na) {
         pr.loc = L.atom[lane];
         pr.frag = L.atom_frag[lane];
@@ -430,54 +441,63 @@ struct Energy {
     float total, inter, intra, wall;
 };
 
-// World frame (rotation rows and origin) of every fragment for `pose`, in S.R;
-// the relative rotations are left in S.Q.
-__device__ inline void frames(const LigL &L, const WaveL &S, const float *pose)
+// World frame (rotation rows and origin) of every fragment for `pose`, in S.R:
+// R_k = R_0 Q_a1 .. Q_k and o_k = p + R_0 (off_a1 + Q_a1 (off_a2 + ... off_k)) over
+// k's ancestors a1, a2, .. below the root, with R_0 = R(q) and Q_m the rotation
+// of fragment m about its torsion axis.  Lane k forms its frame alone: the loads
+// for k and its first two ancestors (from anc, a per-lane list) are issued
+// together and every lane computes the rotations it needs; deeper ancestors, if
+// any, follow the parent links.
+__device__ inline void frames(const LigL &L, const WaveL &S, uint32_t anc, const float *pose)
 {
     const int lane = lane_id();
-    // (1) rotation of every fragment relative to its parent (root: R(q)); clear
-    //     the fragment force/torque accumulators
-    if (lane < L.nf) {
-        M3 Q;
-        if (lane == 0) {
-            const float4 q = quat_normalize(make_float4(pose[3], pose[4], pose[5], pose[6]));
-            Q = quat_to_mat(q.x, q.y, q.z, q.w);
-        } else {
-            const float4 u = L.fu[lane];
-            Q = axis_angle(u.x, u.y, u.z, pose[7 + lane - 1]);
+    const float4 q = quat_normalize(make_float4(pose[3], pose[4], pose[5], pose[6]));
+    const M3 R0 = quat_to_mat(q.x, q.y, q.z, q.w);
+    M3 R = R0;
+    float3 o = make_float3(pose[0], pose[1], pose[2]);
+    if (lane > 0 && lane < L.nf) {
+        constexpr int kAhead = 3;   // the fragment and two ancestors
+        int mm[kAhead];
+        mm[0] = lane;
+#pragma unroll
+        for (int j = 1; j < kAhead; j++) mm[j] = (int)((anc >> (8 * (j - 1))) & 255u);
+        float4 u[kAhead], off[kAhead];
+        float th[kAhead];
+#pragma unroll
+        for (int j = 0; j < kAhead; j++) {
+            const int m = mm[j] > 0 ? mm[j] : 1;   // an unused entry loads fragment 1's data
+            u[j] = L.fu[m];
+            off[j] = L.foff[m];
+            th[j] = pose[6 + m];
         }
-        S.Q[3 * lane + 0] = make_float4(Q.a[0], Q.a[1], Q.a[2], 0.f);
-        S.Q[3 * lane + 1] = make_float4(Q.a[3], Q.a[4], Q.a[5], 0.f);
-        S.Q[3 * lane + 2] = make_float4(Q.a[6], Q.a[7], Q.a[8], 0.f);
-    }
-    wave_sync();
-
-    // (2) world frame of fragment k: compose along its ancestry (bottom-up)
-    //     R_k = R_0 Q_a1 .. Q_k,  o_k = p + R_0 (off_a1 + Q_a1 (off_a2 + ... off_k))
-    if (lane < L.nf) {
-        const M3 R0 = load_m3(S.Q);
-        M3 R = R0;
-        float3 o = make_float3(pose[0], pose[1], pose[2]);
-        if (lane > 0) {
-            M3 M = load_m3(S.Q + 3 * lane);
-            float3 v = f3(L.foff[lane]);
-            int m = (int)(__float_as_uint(L.fu[lane].w) & 0xffffu) - 1;
-            while (m > 0) {
-                const M3 Qm = load_m3(S.Q + 3 * m);
-                v = f3(L.foff[m]) + mv(Qm, v);
+        M3 M = axis_angle(u[0].x, u[0].y, u[0].z, th[0]);
+        float3 v = f3(off[0]);
+#pragma unroll
+        for (int j = 1; j < kAhead; j++) {
+            if (mm[j] > 0) {
+                const M3 Qm = axis_angle(u[j].x, u[j].y, u[j].z, th[j]);
+                v = f3(off[j]) + mv(Qm, v);
                 M = mul(Qm, M);
-                m = (int)(__float_as_uint(L.fu[m].w) & 0xffffu) - 1;
             }
-            R = mul(R0, M);
-            o = o + mv(R0, v);
         }
+        int m = mm[kAhead - 1] > 0 ? (int)(__float_as_uint(u[kAhead - 1].w) & 0xffffu) - 1 : 0;
+        while (m > 0) {
+            const float4 um = L.fu[m];
+            const M3 Qm = axis_angle(um.x, um.y, um.z, pose[6 + m]);
+            v = f3(L.foff[m]) + mv(Qm, v);
+            M = mul(Qm, M);
+            m = (int)(__float_as_uint(um.w) & 0xffffu) - 1;
+        }
+        R = mul(R0, M);
+        o = o + mv(R0, v);
+    }
+    if (lane < L.nf) {
         S.R[4 * lane + 0] = make_float4(R.a[0], R.a[1], R.a[2], 0.f);
         S.R[4 * lane + 1] = make_float4(R.a[3], R.a[4], R.a[5], 0.f);
         S.R[4 * lane + 2] = make_float4(R.a[6], R.a[7], R.a[8], 0.f);
         S.R[4 * lane + 3] = make_float4(o.x, o.y, o.z, 0.f);
     }
     wave_sync();
-
 }
 
 // Position of ligand atom `a` (< n_atoms) after frames().
@@ -500,7 +520,7 @@ __device__ Energy eval_pose(const LigL &L, const WaveL &S, const IntraRegs<PPL, 
 {
     const int lane = lane_id();
 
-    frames(L, S, pose);
+    frames(L, S, pr.anc, pose);
 
     // (3) atom coordinates; issue the eight corner gathers of the inter-molecular
     //     term now and consume them after the intra-ligand pairs
@@ -811,15 +831,20 @@ __device__ Energy eval_pose(const LigL &L, const WaveL &S, const IntraRegs<PPL, 
     return out;
 }
 
-// trial = x (+) alpha * dir   (p += a dp; q <- normalise(quat(a w) q); theta <- wrap(theta + a dtheta))
+// trial = x (+) alpha * dir   (p += a dp; q <- normalise(quat(a w) q); theta <- wrap(theta + a dtheta)).
+// Lane l writes coordinate l; the three kinds are selected per lane, no branch.
 __device__ inline void pose_step(const LigL &L, const float *x, float alpha, const float *dir, float *out)
 {
     const int lane = lane_id();
     const float4 dq = quat_of_rotvec(alpha * dir[3], alpha * dir[4], alpha * dir[5]);
     const float4 q = quat_normalize(quat_mul(dq, make_float4(x[3], x[4], x[5], x[6])));
-    if (lane < 3) out[lane] = x[lane] + alpha * dir[lane];
-    else if (lane < 7) out[lane] = lane == 3 ? q.x : (lane == 4 ? q.y : (lane == 5 ? q.z : q.w));
-    else if (lane < L.nx) out[lane] = wrap_angle(x[lane] + alpha * dir[lane - 1]);
+    const bool tors = lane >= 7 && lane < L.nx;
+    const int xi = lane < L.nx ? lane : 0, di = lane < 3 ? lane : (tors ? lane - 1 : 0);
+    const float lin = x[xi] + alpha * dir[di];
+    const float qc = lane == 3 ? q.x : (lane == 4 ? q.y : (lane == 5 ? q.z : q.w));
+    const float th = wrap_angle(tors ? lin : 0.f);
+    const float v = lane < 3 ? lin : (lane < 7 ? qc : th);
+    if (lane < L.nx) out[lane] = v;
     wave_sync();
 }
 
@@ -1398,7 +1423,7 @@ __global__ __launch_bounds__(256) void tick_kernel(const uint32_t *arena, const 
     if (step < t.n_steps) return;
     // finished: record, and the coordinates of the best pose for RMSD clustering
     const WaveL S = make_wave(wbase, lay);
-    frames(L, S, C.best);
+    frames(L, S, pr.anc, C.best);
     float *rec = records + (long)t.slot * kRecWords;
     if (lane < L.nx) rec[kRecPose + lane] = C.best[lane];
     if (lane == 0) {
