@@ -58,7 +58,11 @@ typedef struct {
     int32_t xs_type;     /* 0 .. DSDP_N_XS-1 */
 } dsdp_atom;
 
-/* Search box: nodes per axis n = floor(size/spacing) + 1, centred on centre. */
+/*
+ * Search box: nodes per axis n = floor(size/spacing) + 1, centred on centre.
+ * Limits: spacing in [0.05, 4] A, at most 2048 nodes per axis and fewer than
+ * 2^31 nodes in all (DSDP_ERR_UNSUPPORTED beyond them).
+ */
 typedef struct {
     float centre[3];
     float size[3];
@@ -156,7 +160,8 @@ void dsdp_params_default(dsdp_params *p);
 
 /*
  * Grid geometry of a box: n[3] nodes per axis, origin[3] = centre - (n-1)*spacing/2.
- * DSDP_ERR_INVALID_ARG for non-positive or non-finite sizes/spacing.
+ * DSDP_ERR_INVALID_ARG for non-positive or non-finite sizes/spacing,
+ * DSDP_ERR_UNSUPPORTED beyond the box limits above.
  */
 dsdp_status dsdp_grid_dims(const dsdp_box *box, int32_t *n, float *origin);
 

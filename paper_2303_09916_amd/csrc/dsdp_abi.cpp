@@ -60,6 +60,8 @@ dsdp_status geometry(const dsdp_box *box, int n[3], double origin[3])
         n[a] = (int)nn;
         origin[a] = (double)box->centre[a] - 0.5 * (n[a] - 1) * (double)box->spacing;
     }
+    if ((double)n[0] * n[1] * n[2] >= 2147483648.0)
+        return fail(DSDP_ERR_UNSUPPORTED, "2^31 or more nodes per map");
     return DSDP_OK;
 }
 

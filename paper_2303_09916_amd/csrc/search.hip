@@ -98,6 +98,12 @@ __device__ __forceinline__ uint4 draw(uint64_t seed, uint32_t chain, uint32_t st
 // top 24 bits -> [0, 1), exact in float
 __device__ __forceinline__ float unif(uint32_t x) { return (float)(x >> 8) * (1.0f / 16777216.0f); }
 
+// A float4 in global memory, read through an address-space-1 pointer: the load
+// is then a global (not flat) one and is counted on the vector-memory counter only.
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) v4f global_f4;
+__device__ __forceinline__ float4 as_float4(v4f v) { return make_float4(v.x, v.y, v.z, v.w); }
+
 // ---------------------------------------------------------------- small geometry
 struct M3 {
     float a[9];
@@ -541,7 +547,7 @@ __device__ Energy eval_pose(const LigL &L, const WaveL &S, const IntraRegs<PPL, 
 
         // wall and clamping: a coordinate outside the box is clamped onto the face;
         // the atom pays wall_slope per Angstrom outside and the map gradient along
-        // a clamped axis is dropped
+        // a clamped axis is dropped (selected per axis, no branches)
         int ci[3];
         float u[3];
         const float xs[3] = {x.x, x.y, x.z};
@@ -551,21 +557,13 @@ __device__ Energy eval_pose(const LigL &L, const WaveL &S, const IntraRegs<PPL, 
         for (int a = 0; a < 3; a++) {
             const float lo = G.origin[a];
             const float hi = G.origin[a] + (float)(G.n[a] - 1) * G.h;
-            float xa = xs[a];
-            wgs[a] = 0.f;
-            cls[a] = false;
-            if (xa < lo) {
-                w_atom += wall_slope * (lo - xa);
-                wgs[a] = -wall_slope;
-                xa = lo;
-                cls[a] = true;
-            } else if (xa > hi) {
-                w_atom += wall_slope * (xa - hi);
-                wgs[a] = wall_slope;
-                xa = hi;
-                cls[a] = true;
-            }
-            u[a] = (xa - lo) * G.inv_h;
+            const float xa = xs[a];
+            const bool below = xa < lo, above = xa > hi;
+            w_atom += below ? wall_slope * (lo - xa) : (above ? wall_slope * (xa - hi) : 0.f);
+            wgs[a] = below ? -wall_slope : (above ? wall_slope : 0.f);
+            cls[a] = below || above;
+            const float xc = below ? lo : (above ? hi : xa);
+            u[a] = (xc - lo) * G.inv_h;
             int i = (int)floorf(u[a]);
             i = min(i, G.n[a] - 2);
             i = max(i, 0);
@@ -575,11 +573,15 @@ __device__ Energy eval_pose(const LigL &L, const WaveL &S, const IntraRegs<PPL, 
         wg = make_float3(wgs[0], wgs[1], wgs[2]);
         clx = cls[0]; cly = cls[1]; clz = cls[2];
         px = u[0]; py = u[1]; pz = u[2];
+        // the maps are read as global memory (not flat), so that waiting for LDS
+        // results below does not also wait for these loads; node offsets are
+        // 32-bit (a map holds fewer than 2^31 nodes)
         const int t = __float_as_int(loc.w);
-        const long sy = G.n[0], sz = (long)G.n[0] * G.n[1];
-        const float4 *m0 = G.maps + (long)t * sz * G.n[2] + ci[2] * sz + ci[1] * sy + ci[0];
-        c000 = m0[0]; c100 = m0[1]; c010 = m0[sy]; c110 = m0[sy + 1];
-        c001 = m0[sz]; c101 = m0[sz + 1]; c011 = m0[sz + sy]; c111 = m0[sz + sy + 1];
+        const int sy = G.n[0], sz = G.n[0] * G.n[1];
+        const global_f4 *m0 = (const global_f4 *)(G.maps + (long)t * sz * G.n[2]) + (ci[2] * sz + ci[1] * sy + ci[0]);
+        c000 = as_float4(m0[0]); c100 = as_float4(m0[1]); c010 = as_float4(m0[sy]); c110 = as_float4(m0[sy + 1]);
+        c001 = as_float4(m0[sz]); c101 = as_float4(m0[sz + 1]);
+        c011 = as_float4(m0[sz + sy]); c111 = as_float4(m0[sz + sy + 1]);
     }
     wave_sync();
 
