@@ -517,6 +517,46 @@ __device__ inline float3 atom_position(const LigL &L, const WaveL &S, int a)
                        o.z + r2.x * loc.x + r2.y * loc.y + r2.z * loc.z);
 }
 
+// Trilinear energy and force of one atom from its eight gathered corners (eq. 2
+// and eq. 4); the map gradient along a clamped axis is dropped, the wall added.
+// Written with explicit fused multiply-adds and no others formed, so that every
+// place it is inlined rounds alike (the two intra-ligand layouts use it at
+// different points of the evaluation).
+__device__ __forceinline__ float corner_sum(const float (&w)[8], float v0, float v1, float v2, float v3, float v4,
+                                            float v5, float v6, float v7)
+{
+#pragma clang fp contract(off)
+    float acc = w[0] * v0;
+    acc = fmaf(w[1], v1, acc);
+    acc = fmaf(w[2], v2, acc);
+    acc = fmaf(w[3], v3, acc);
+    acc = fmaf(w[4], v4, acc);
+    acc = fmaf(w[5], v5, acc);
+    acc = fmaf(w[6], v6, acc);
+    acc = fmaf(w[7], v7, acc);
+    return acc;
+}
+__device__ __forceinline__ void trilinear(const float4 &c000, const float4 &c100, const float4 &c010,
+                                          const float4 &c110, const float4 &c001, const float4 &c101,
+                                          const float4 &c011, const float4 &c111, float px, float py, float pz,
+                                          bool clx, bool cly, bool clz, float3 wg, float w_atom, float &e_atom,
+                                          float3 &f)
+{
+#pragma clang fp contract(off)
+    const float qx = 1.f - px, qy = 1.f - py, qz = 1.f - pz;
+    const float w[8] = {qx * qy * qz, px * qy * qz, qx * py * qz, px * py * qz,
+                        qx * qy * pz, px * qy * pz, qx * py * pz, px * py * pz};
+    const float E = corner_sum(w, c000.x, c100.x, c010.x, c110.x, c001.x, c101.x, c011.x, c111.x);
+    float gx = corner_sum(w, c000.y, c100.y, c010.y, c110.y, c001.y, c101.y, c011.y, c111.y);
+    float gy = corner_sum(w, c000.z, c100.z, c010.z, c110.z, c001.z, c101.z, c011.z, c111.z);
+    float gz = corner_sum(w, c000.w, c100.w, c010.w, c110.w, c001.w, c101.w, c011.w, c111.w);
+    if (clx) gx = 0.f;
+    if (cly) gy = 0.f;
+    if (clz) gz = 0.f;
+    f = make_float3(gx + wg.x, gy + wg.y, gz + wg.z);
+    e_atom = E + w_atom;
+}
+
 // Energy of `pose` (LDS, wave-uniform) and its gradient in
 // the tangent coordinates written to grad[0..D) (LDS).  Coordinates are left in
 // S.xyz.  Every lane returns the same values.
@@ -535,6 +575,8 @@ __device__ Energy eval_pose(const LigL &L, const WaveL &S, const IntraRegs<PPL, 
     float px = 0.f, py = 0.f, pz = 0.f;
     bool clx = false, cly = false, clz = false;
     float4 c000, c100, c010, c110, c001, c101, c011, c111;
+    float e_atom = 0.f;
+    float3 f = make_float3(0.f, 0.f, 0.f);
     int frag = 0;
     if (lane < L.na) {
         frag = pr.frag;
@@ -582,6 +624,12 @@ __device__ Energy eval_pose(const LigL &L, const WaveL &S, const IntraRegs<PPL, 
         c000 = as_float4(m0[0]); c100 = as_float4(m0[1]); c010 = as_float4(m0[sy]); c110 = as_float4(m0[sy + 1]);
         c001 = as_float4(m0[sz]); c101 = as_float4(m0[sz + 1]);
         c011 = as_float4(m0[sz + sy]); c111 = as_float4(m0[sz + sy + 1]);
+        // atom lists: the corners are used at once, so that their registers are
+        // free for the intra-ligand loop (the launches that use this layout run
+        // several waves per SIMD, which hide the wait)
+        if constexpr (PPL == 0)
+            trilinear(c000, c100, c010, c110, c001, c101, c011, c111, px, py, pz, clx, cly, clz, wg, w_atom, e_atom,
+                      f);
     }
     wave_sync();
 
@@ -638,22 +686,26 @@ __device__ Energy eval_pose(const LigL &L, const WaveL &S, const IntraRegs<PPL, 
 #pragma unroll 1
             for (int m = 0; m < L.nbr_words; m++) {
                 const uint32_t word = L.nbr[m * 64 + lane];
+                // the word's four partners loaded at once (an empty byte reads the
+                // lane's own atom), then evaluated without branches
+                float4 xj[4];
 #pragma unroll
                 for (int b = 0; b < 4; b++) {
                     const uint32_t e = (word >> (8 * b)) & 255u;
-                    if (e != kNbrNone) {
-                        const int j = (int)(e & 63u);
-                        const float4 xj = S.xyz[j];
-                        const float dx = xa.x - xj.x, dy = xa.y - xj.y, dz = xa.z - xj.z;
-                        const float r2 = pair_r2(dx, dy, dz);
-                        if (r2 < kCutoff2) {
-                            const float2 es = pair_term(r2, xa.w + xj.w, e >> 6);
-                            if (a < j) e_lane += es.x;
-                            fnb.x = add_product(fnb.x, es.y, dx);
-                            fnb.y = add_product(fnb.y, es.y, dy);
-                            fnb.z = add_product(fnb.z, es.y, dz);
-                        }
-                    }
+                    xj[b] = S.xyz[e != kNbrNone ? (int)(e & 63u) : a];
+                }
+#pragma unroll
+                for (int b = 0; b < 4; b++) {
+                    const uint32_t e = (word >> (8 * b)) & 255u;
+                    const int j = (int)(e & 63u);
+                    const float dx = xa.x - xj[b].x, dy = xa.y - xj[b].y, dz = xa.z - xj[b].z;
+                    const float r2 = pair_r2(dx, dy, dz);
+                    const float2 es = pair_term(r2, xa.w + xj[b].w, e >> 6);
+                    const bool use = e != kNbrNone && r2 < kCutoff2;
+                    e_lane += (use && a < j) ? es.x : 0.f;
+                    fnb.x = use ? add_product(fnb.x, es.y, dx) : fnb.x;
+                    fnb.y = use ? add_product(fnb.y, es.y, dy) : fnb.y;
+                    fnb.z = use ? add_product(fnb.z, es.y, dz) : fnb.z;
                 }
             }
         }
@@ -661,25 +713,10 @@ __device__ Energy eval_pose(const LigL &L, const WaveL &S, const IntraRegs<PPL, 
 
     // (5) inter-molecular energy and force from the gathered corners: eq. 2 for
     //     the energy and eq. 4 (the same weights on the stored gradients)
-    float e_atom = 0.f;
-    float3 f = make_float3(0.f, 0.f, 0.f);
-    if (lane < L.na) {
-        const float qx = 1.f - px, qy = 1.f - py, qz = 1.f - pz;
-        const float w000 = qx * qy * qz, w100 = px * qy * qz, w010 = qx * py * qz, w110 = px * py * qz;
-        const float w001 = qx * qy * pz, w101 = px * qy * pz, w011 = qx * py * pz, w111 = px * py * pz;
-        const float E = w000 * c000.x + w100 * c100.x + w010 * c010.x + w110 * c110.x + w001 * c001.x +
-                        w101 * c101.x + w011 * c011.x + w111 * c111.x;
-        float gx = w000 * c000.y + w100 * c100.y + w010 * c010.y + w110 * c110.y + w001 * c001.y + w101 * c101.y +
-                   w011 * c011.y + w111 * c111.y;
-        float gy = w000 * c000.z + w100 * c100.z + w010 * c010.z + w110 * c110.z + w001 * c001.z + w101 * c101.z +
-                   w011 * c011.z + w111 * c111.z;
-        float gz = w000 * c000.w + w100 * c100.w + w010 * c010.w + w110 * c110.w + w001 * c001.w + w101 * c101.w +
-                   w011 * c011.w + w111 * c111.w;
-        if (clx) gx = 0.f;
-        if (cly) gy = 0.f;
-        if (clz) gz = 0.f;
-        f = make_float3(gx + wg.x, gy + wg.y, gz + wg.z);
-        e_atom = E + w_atom;
+    if constexpr (PPL > 0) {
+        if (lane < L.na)
+            trilinear(c000, c100, c010, c110, c001, c101, c011, c111, px, py, pz, clx, cly, clz, wg, w_atom, e_atom,
+                      f);
     }
     float e_inter = wave_sum(e_atom);
     float wall = wave_sum(w_atom);
