@@ -288,7 +288,9 @@ struct LigL {
 struct WaveL {
     float4 *xyz;
     float4 *pf;            // [np + 1] force of each pair on its first atom; slot np stays 0
-    float4 *af, *at;       // [na] prefix sums over atoms of force and of torque about the root origin
+    float4 *af, *at;       // [64]: per lane, the forces the energy half leaves for the gradient
+                           // half, then prefix sums over atoms of force and of torque about the
+                           // root origin
     float4 *R;       // [nf][4]: rows of R_k, then origin o_k
     float *trial;    // [NXp]: this wave's trial pose
     float *gt;       // [Dp]: gradient at the trial pose
@@ -325,8 +327,8 @@ __host__ __device__ inline Layout make_layout(int na, int nf, int np, int D, int
     // np = -1: no pair-force scratch (atom lists); else the pairs, the zero slot
     // np, and entries up to a whole group of two 64-pair slots
     c.pf = w; w += np < 0 ? 0 : 4 * max(np + 1, 128 * ((np + 127) / 128));
-    c.af = w; w += 4 * na;
-    c.at = w; w += 4 * na;
+    c.af = w; w += 4 * 64;   // one entry per lane (the energy half leaves its forces here)
+    c.at = w; w += 4 * 64;
     c.R = w; w += 16 * nf;
     c.trial = w; w += c.NXp;
     c.gt = w; w += c.Dp;
@@ -517,6 +519,20 @@ __device__ inline float3 atom_position(const LigL &L, const WaveL &S, int a)
                        o.z + r2.x * loc.x + r2.y * loc.y + r2.z * loc.z);
 }
 
+// Entry t (0-15) of the two register-held gather chunks, and entry t (0-7) of one
+// chunk: a pair index with the sign bit 0x8000 (set when the atom is the pair's
+// second atom).
+__device__ __forceinline__ uint32_t chunk_entry(const uint4 &q, int t)
+{
+    const uint32_t wv = t < 2 ? q.x : t < 4 ? q.y : t < 6 ? q.z : q.w;
+    return (t & 1) ? (wv >> 16) : (wv & 0xffffu);
+}
+template <int N>
+__device__ __forceinline__ uint32_t pl_entry(const uint4 (&pl)[N], int t)
+{
+    return chunk_entry(pl[(t >> 3) < N ? (t >> 3) : 0], t & 7);
+}
+
 // Trilinear energy and force of one atom from its eight gathered corners (eq. 2
 // and eq. 4); the map gradient along a clamped axis is dropped, the wall added.
 // Written with explicit fused multiply-adds and no others formed, so that every
@@ -557,12 +573,41 @@ __device__ __forceinline__ void trilinear(const float4 &c000, const float4 &c100
     e_atom = E + w_atom;
 }
 
-// Energy of `pose` (LDS, wave-uniform) and its gradient in
-// the tangent coordinates written to grad[0..D) (LDS).  Coordinates are left in
-// S.xyz.  Every lane returns the same values.
+// Restraint of the adaptive search space on the root position p = pose[0..2]:
+// zero inside a site ball, else wall_slope times the distance to the nearest
+// ball (the lowest index on ties); returns the energy, its gradient in g.
+__device__ inline float site_term(const GridView &G, const float *pose, float wall_slope, float3 &g)
+{
+    const int lane = lane_id();
+    const float px = pose[0], py = pose[1], pz = pose[2];
+    uint64_t key = ~0ull;   // (squared distance bits, site index), minimised
+    for (int i = lane; i < G.n_site; i += 64) {
+        const float4 q = G.site[i];
+        const float dx = px - q.x, dy = py - q.y, dz = pz - q.z;
+        const uint64_t k = ((uint64_t)__float_as_uint(dx * dx + dy * dy + dz * dz) << 32) | (uint32_t)i;
+        key = k < key ? k : key;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint64_t other = __shfl_xor(key, o, 64);
+        key = other < key ? other : key;
+    }
+    const float d = sqrtf(__uint_as_float((uint32_t)(key >> 32)));
+    g = make_float3(0.f, 0.f, 0.f);
+    if (d <= G.site_r) return 0.f;
+    const float4 q = G.site[(int)(key & 0xffffffffu)];
+    const float k = wall_slope / d;
+    g = make_float3(k * (px - q.x), k * (py - q.y), k * (pz - q.z));
+    return wall_slope * (d - G.site_r);
+}
+
+// Energy of `pose` (LDS, wave-uniform); every lane returns the same values.  The
+// gradient is left to eval_gradient (a line-search trial needs only the energy
+// unless it is accepted); what it needs stays in `cy` and the wave's scratch,
+// coordinates in S.xyz.
 template <int PPL, int NBW>
-__device__ Energy eval_pose(const LigL &L, const WaveL &S, const IntraRegs<PPL, NBW> &pr, const GridView &G,
-                            const float *pose, float *grad, float wall_slope)
+__device__ Energy eval_energy(const LigL &L, const WaveL &S, const IntraRegs<PPL, NBW> &pr, const GridView &G,
+                              const float *pose, float wall_slope)
 {
     const int lane = lane_id();
 
@@ -721,87 +766,101 @@ __device__ Energy eval_pose(const LigL &L, const WaveL &S, const IntraRegs<PPL, 
     float e_inter = wave_sum(e_atom);
     float wall = wave_sum(w_atom);
     // adaptive search space: outside every site ball the root position pays
-    // wall_slope per A of its distance to the nearest ball (lowest index on ties)
-    float3 g_site = make_float3(0.f, 0.f, 0.f);
+    // wall_slope per A of its distance to the nearest ball
     if (G.n_site > 0) {
-        const float px = pose[0], py = pose[1], pz = pose[2];
-        uint64_t key = ~0ull;   // (squared distance bits, site index), minimised
-        for (int i = lane; i < G.n_site; i += 64) {
-            const float4 q = G.site[i];
-            const float dx = px - q.x, dy = py - q.y, dz = pz - q.z;
-            const uint64_t k = ((uint64_t)__float_as_uint(dx * dx + dy * dy + dz * dz) << 32) | (uint32_t)i;
-            key = k < key ? k : key;
-        }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            const uint64_t other = __shfl_xor(key, o, 64);
-            key = other < key ? other : key;
-        }
-        const float d = sqrtf(__uint_as_float((uint32_t)(key >> 32)));
-        if (d > G.site_r) {
-            const float4 q = G.site[(int)(key & 0xffffffffu)];
-            const float e = wall_slope * (d - G.site_r), k = wall_slope / d;
-            e_inter += e;
-            wall += e;
-            g_site = make_float3(k * (px - q.x), k * (py - q.y), k * (pz - q.z));
-        }
+        float3 g_site;
+        const float e = site_term(G, pose, wall_slope, g_site);
+        e_inter += e;
+        wall += e;
     }
     wave_sync();
 
-    float e_intra = 0.f;
-    // (6) pair lists: pair forces gathered per atom from its list (8 entries per
-    //     16-byte chunk); atom lists: the lane's own sum.  Two lanes per atom when
-    //     there are at most 32 atoms.  Then the atom's total force
+    // (6e) the intra energy, summed per atom lane in the order of its list (pair
+    //      lists: the pair energies stored with the forces, counted at the
+    //      pair's first atom; atom lists: the lane's own sum)
+    if constexpr (PPL > 0) {
+        constexpr int kRegChunks = PPL == 8 ? 2 : 0;
+        if constexpr (kRegChunks > 0) {
+            float v[16];
+#pragma unroll
+            for (int t = 0; t < 16; t++) v[t] = S.pf[pl_entry(pr.pl, t) & 0x7fffu].w;
+#pragma unroll
+            for (int t = 0; t < 16; t++) {
+                if (t == 8 && L.n_chunks < 2) break;
+                e_lane += (pl_entry(pr.pl, t) & 0x8000u) ? 0.f : v[t];
+            }
+        }
+        for (int c = kRegChunks; c < L.n_chunks; c++) {
+            const uint4 q = L.plist[c * 64 + lane];
+            float v[8];
+#pragma unroll
+            for (int t = 0; t < 8; t++) v[t] = S.pf[chunk_entry(q, t) & 0x7fffu].w;
+#pragma unroll
+            for (int t = 0; t < 8; t++) e_lane += (chunk_entry(q, t) & 0x8000u) ? 0.f : v[t];
+        }
+    }
+    const float e_intra = wave_sum(e_lane);
+    // for the gradient half: every lane's inter-molecular force (zero past the
+    // atoms) and, for atom lists, its share of the intra force
+    S.af[lane] = make_float4(f.x, f.y, f.z, 0.f);
+    if constexpr (PPL == 0) S.at[lane] = make_float4(fnb.x, fnb.y, fnb.z, 0.f);
+    Energy out;
+    out.inter = e_inter;
+    out.intra = e_intra;
+    out.wall = wall;
+    out.total = e_inter + e_intra;
+    return out;
+}
+
+// Gradient in the tangent coordinates, written to grad[0..D) (LDS), of the pose
+// whose energy eval_energy last took on this wave (same `pose`; the wave's
+// scratch still holds that evaluation).
+template <int PPL, int NBW>
+__device__ void eval_gradient(const LigL &L, const WaveL &S, const IntraRegs<PPL, NBW> &pr, const GridView &G,
+                              const float *pose, float wall_slope, float *grad)
+{
+    const int lane = lane_id();
+    const float4 xl = S.xyz[lane < L.na ? lane : 0];
+    const float3 x = lane < L.na ? f3(xl) : make_float3(0.f, 0.f, 0.f);
+    float3 f = f3(S.af[lane]);
+    float3 g_site = make_float3(0.f, 0.f, 0.f);
+    if (G.n_site > 0) site_term(G, pose, wall_slope, g_site);
+    // (6g) pair lists: pair forces gathered per atom from its list (8 entries per
+    //      16-byte chunk), in list order; atom lists: the lane's own sum.  Two
+    //      lanes per atom when there are at most 32 atoms.  Then the atom's total
+    //      force
     {
         float3 fp = make_float3(0.f, 0.f, 0.f);
         if constexpr (PPL > 0) {
             // eight pairs per lane: the first two chunks' lists are in registers
-            // and their sixteen loads are issued together (the entries are
-            // added in list order, as in the loop that takes any further chunks
-            // from LDS)
+            // and their sixteen loads are issued together
             constexpr int kRegChunks = PPL == 8 ? 2 : 0;
             if constexpr (kRegChunks > 0) {
                 float4 v[16];
 #pragma unroll
-                for (int t = 0; t < 16; t++) {
-                    const uint4 q = pr.pl[t >> 3];
-                    const uint32_t wv = (t & 7) < 2 ? q.x : (t & 7) < 4 ? q.y : (t & 7) < 6 ? q.z : q.w;
-                    const uint32_t e = (t & 1) ? (wv >> 16) : (wv & 0xffffu);
-                    v[t] = S.pf[e & 0x7fffu];
-                }
+                for (int t = 0; t < 16; t++) v[t] = S.pf[pl_entry(pr.pl, t) & 0x7fffu];
 #pragma unroll
                 for (int t = 0; t < 16; t++) {
                     if (t == 8 && L.n_chunks < 2) break;
-                    const uint4 q = pr.pl[t >> 3];
-                    const uint32_t wv = (t & 7) < 2 ? q.x : (t & 7) < 4 ? q.y : (t & 7) < 6 ? q.z : q.w;
-                    const uint32_t e = (t & 1) ? (wv >> 16) : (wv & 0xffffu);
-                    const bool second = (e & 0x8000u) != 0;
-                    const float sg = second ? -1.f : 1.f;
+                    // sg * v is exact, so this rounds once, as fp +/- v does
+                    const float sg = (pl_entry(pr.pl, t) & 0x8000u) ? -1.f : 1.f;
                     fp = fp + sg * f3(v[t]);
-                    e_lane += second ? 0.f : v[t].w;
                 }
             }
             for (int c = kRegChunks; c < L.n_chunks; c++) {
                 const uint4 q = L.plist[c * 64 + lane];
-                const uint32_t e[8] = {q.x & 0xffffu, q.x >> 16, q.y & 0xffffu, q.y >> 16,
-                                       q.z & 0xffffu, q.z >> 16, q.w & 0xffffu, q.w >> 16};
                 float4 v[8];
 #pragma unroll
-                for (int t = 0; t < 8; t++) v[t] = S.pf[e[t] & 0x7fffu];
+                for (int t = 0; t < 8; t++) v[t] = S.pf[chunk_entry(q, t) & 0x7fffu];
 #pragma unroll
                 for (int t = 0; t < 8; t++) {
-                    // sg * v is exact, so this rounds once, as fp +/- v does;
-                    // the pair's energy counts at its first (lower-numbered) atom
-                    const bool second = (e[t] & 0x8000u) != 0;
-                    const float sg = second ? -1.f : 1.f;
+                    const float sg = (chunk_entry(q, t) & 0x8000u) ? -1.f : 1.f;
                     fp = fp + sg * f3(v[t]);
-                    e_lane += second ? 0.f : v[t].w;
                 }
             }
         } else {
-            fp = fnb;
+            fp = f3(S.at[lane]);
         }
-        e_intra = wave_sum(e_lane);
         if (L.lanes_per_atom == 2) {
             fp.x += __shfl_xor(fp.x, 32, 64);
             fp.y += __shfl_xor(fp.y, 32, 64);
@@ -862,12 +921,16 @@ __device__ Energy eval_pose(const LigL &L, const WaveL &S, const IntraRegs<PPL, 
         grad[6 + lane - 1] = dot3(u, tk);
     }
     wave_sync();
-    Energy out;
-    out.inter = e_inter;
-    out.intra = e_intra;
-    out.wall = wall;
-    out.total = e_inter + e_intra;
-    return out;
+}
+
+// Energy and gradient of `pose`.
+template <int PPL, int NBW>
+__device__ Energy eval_pose(const LigL &L, const WaveL &S, const IntraRegs<PPL, NBW> &pr, const GridView &G,
+                            const float *pose, float *grad, float wall_slope)
+{
+    const Energy e = eval_energy(L, S, pr, G, pose, wall_slope);
+    eval_gradient(L, S, pr, G, pose, wall_slope, grad);
+    return e;
 }
 
 // trial = x (+) alpha * dir   (p += a dp; q <- normalise(quat(a w) q); theta <- wrap(theta + a dtheta)).
@@ -1042,10 +1105,11 @@ __device__ inline float bfgs_step_any(const ChainL &C, int D, int nq, bool upd, 
 // iteration; the lowest-energy iterate is returned).
 //
 // BFGS with Armijo backtracking on the chain's pose x (LDS, in place), run by all
-// W waves of the workgroup together.  The line search evaluates W consecutive
-// trials at once (alpha_t = shrink^t, one per wave) and accepts the first that
-// passes the Armijo test, which is the trial the one-at-a-time search accepts:
-// the result does not depend on W.  `evals` counts the evaluations the
+// W waves of the workgroup together.  The line search evaluates the energies of
+// W consecutive trials at once (alpha_t = shrink^t, one per wave) and accepts
+// the first that passes the Armijo test, which is the trial the one-at-a-time
+// search accepts: the result does not depend on W.  Only the accepted trial's
+// gradient is computed, by its wave, after the decision.  `evals` counts the evaluations the
 // one-at-a-time search makes (speculative trials past the accepted one are not
 // counted).  Wave 0 owns the direction and the inverse-Hessian update.  The
 // final gradient is left in C.g.
@@ -1088,9 +1152,43 @@ __device__ Energy local_opt_group(const LigL &L, const Layout &lay, float *wave_
         }
         if (active) {
             wave_sync();
-            put_energy(C.et + 4 * w, eval_pose(L, S, pr, G, S.trial, S.gt, P.wall_slope));
+            put_energy(C.et + 4 * w, eval_energy(L, S, pr, G, S.trial, P.wall_slope));
         }
         __syncthreads();
+        // the one evaluation of this round whose gradient is needed: wave 0's for
+        // the start point and a Barzilai-Borwein iterate; in a line search, the
+        // accepted trial's (decided alike in every wave, so the barrier below is
+        // taken by all or none), and none when every trial is rejected
+        int gw = 0, acc_slot = -1;
+        float alpha_acc = 0.f;
+        if (t0 >= 0 && !bb) {
+            float a = alpha0;
+            float4 et4[kMaxWaves];
+#pragma unroll
+            for (int q = 0; q < kMaxWaves; q++) et4[q] = reinterpret_cast<const float4 *>(C.et)[q];
+            int v = 0;
+#pragma unroll
+            for (; v < kMaxWaves; v++) {
+                if (v >= W || t0 + v >= P.ls_trials) break;
+                if (et4[v].x <= Ex.total + P.armijo_c1 * a * gp) {
+                    acc_slot = v;
+                    alpha_acc = a;
+                    break;
+                }
+                a *= P.ls_shrink;
+            }
+            evals += acc_slot >= 0 ? acc_slot + 1 : v;
+            if (acc_slot < 0) {
+                if (t0 + W >= P.ls_trials) break;   // every trial rejected: stop at x
+                alpha0 = a;
+                t0 += W;
+                __syncthreads();   // this round's energies are read before the next round writes
+                continue;
+            }
+            gw = acc_slot;
+        }
+        if (w == gw) eval_gradient(L, S, pr, G, S.trial, P.wall_slope, S.gt);
+        if (gw != 0) __syncthreads();
         if (t0 < 0) {
             Ex = get_energy(C.et);
             evals++;
@@ -1132,42 +1230,7 @@ __device__ Energy local_opt_group(const LigL &L, const Layout &lay, float *wave_
             if (En.total < Eb.total) Eb = En;
             it++;
         } else {
-            int acc_slot = -1;
-            float a = alpha0, alpha_acc = 0.f;
-            float4 et4[kMaxWaves];
-#pragma unroll
-            for (int q = 0; q < kMaxWaves; q++) et4[q] = reinterpret_cast<const float4 *>(C.et)[q];
-            float et[kMaxWaves];
-#pragma unroll
-            for (int q = 0; q < kMaxWaves; q++) et[q] = et4[q].x;
-            int v = 0;
-#pragma unroll
-            for (; v < kMaxWaves; v++) {
-                if (v >= W || t0 + v >= P.ls_trials) break;
-                if (et[v] <= Ex.total + P.armijo_c1 * a * gp) {
-                    acc_slot = v;
-                    alpha_acc = a;
-                    break;
-                }
-                a *= P.ls_shrink;
-            }
-            evals += acc_slot >= 0 ? acc_slot + 1 : v;
-            if (acc_slot < 0) {
-                if (t0 + W >= P.ls_trials) break;   // every trial rejected: stop at x
-                alpha0 = a;
-                t0 += W;
-                __syncthreads();   // this round's energies are read before the next round writes
-                continue;
-            }
-            float4 e_acc = et4[0];
-#pragma unroll
-            for (int q = 1; q < kMaxWaves; q++)
-                if (acc_slot == q) e_acc = et4[q];
-            Energy Et;
-            Et.total = e_acc.x;
-            Et.inter = e_acc.y;
-            Et.intra = e_acc.z;
-            Et.wall = e_acc.w;
+            const Energy Et = get_energy(C.et + 4 * acc_slot);
             if (w == 0) {
                 const WaveL A = make_wave(wave_base + acc_slot * lay.wave_words, lay);
                 s_l = 0.f;
