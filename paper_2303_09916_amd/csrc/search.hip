@@ -219,13 +219,19 @@ __device__ __forceinline__ float2 vina_pair(float d, float wh, float wb)
     // intra-ligand layouts inline this in different surroundings and must round
     // alike.
 #pragma clang fp contract(off)
-    const float g1 = __expf(-4.0f * (d * d));
+    // the two gauss terms |w| exp(-k x^2) as exp2(x^2 (-k log2 e) + log2 |w|), the
+    // weight folded into the exponent; both weights are negative
+    static_assert(kWGauss1 == -0.0356f && kWGauss2 == -0.00516f, "exponent constants below");
+    constexpr float kC1 = -5.77078009f;   // -4 log2(e)
+    constexpr float kL1 = -4.81197882f;   // log2(0.0356)
+    constexpr float kC2 = -0.360673755f;  // -0.25 log2(e)
+    constexpr float kL2 = -7.59841299f;   // log2(0.00516)
+    const float a1 = __builtin_amdgcn_exp2f(fmaf(d * d, kC1, kL1));   // -w1
     const float b = d - 3.0f;
-    const float g2 = __expf(-0.25f * (b * b));
+    const float a2 = __builtin_amdgcn_exp2f(fmaf(b * b, kC2, kL2));   // -w2
     const float dn = fminf(d, 0.0f);
-    const float w1 = kWGauss1 * g1, w2 = kWGauss2 * g2;
-    float e = fmaf(kWRepulsion * dn, dn, fmaf(w2, 1.0f, w1));
-    float de = fmaf(kWRepulsion * 2.0f, dn, fmaf(w2, -0.5f * b, w1 * (-8.0f * d)));
+    float e = fmaf(kWRepulsion * dn, dn, -(a1 + a2));
+    float de = fmaf(kWRepulsion * 2.0f, dn, fmaf(a2, 0.5f * b, a1 * (8.0f * d)));
     e = fmaf(wh, fminf(fmaxf(1.5f - d, 0.0f), 1.0f), fmaf(wb, fminf(fmaxf(-d * (1.0f / 0.7f), 0.0f), 1.0f), e));
     de += ((d > 0.5f && d <= 1.5f) ? -wh : 0.0f) + ((d > -0.7f && d <= 0.0f) ? -wb * (1.0f / 0.7f) : 0.0f);
     return make_float2(e, de);
@@ -1131,9 +1137,10 @@ __device__ Energy local_opt_group(const LigL &L, const Layout &lay, float *wave_
     float *xb = C.H;           // Barzilai-Borwein: lowest-energy iterate (the matrix is unused)
     const int Dp = lay.Dp;
     float s_l = 0.f, y_l = 0.f, g_l = 0.f, ys = 0.f;   // wave 0: this iteration's s, y, new g; s.y
-    // Every evaluation of the local optimisation goes through the one call below
-    // (the start pose by wave 0, then one line-search trial per wave per round),
-    // so the kernel holds a single copy of the evaluation code.
+    // Every evaluation of the local optimisation goes through the one energy call
+    // and the one gradient call below (the start pose by wave 0, then one
+    // line-search trial per wave per round), so the kernel holds a single copy
+    // of the evaluation code.
     for (;;) {
         bool active;
         if (t0 < 0) {
