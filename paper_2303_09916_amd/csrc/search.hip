@@ -1115,10 +1115,11 @@ __device__ inline float bfgs_step_any(const ChainL &C, int D, int nq, bool upd, 
 // W consecutive trials at once (alpha_t = shrink^t, one per wave) and accepts
 // the first that passes the Armijo test, which is the trial the one-at-a-time
 // search accepts: the result does not depend on W.  Only the accepted trial's
-// gradient is computed, by its wave, after the decision.  `evals` counts the evaluations the
-// one-at-a-time search makes (speculative trials past the accepted one are not
-// counted).  Wave 0 owns the direction and the inverse-Hessian update.  The
-// final gradient is left in C.g.
+// gradient is computed, by its wave, after the decision, and that wave also
+// takes the step: s, y, the inverse-Hessian update and the next direction (all
+// kept in LDS; wave 0 does this for the start point).  `evals` counts the
+// evaluations the one-at-a-time search makes (speculative trials past the
+// accepted one are not counted).  The final gradient is left in C.g.
 template <int PPL, int NBW>
 __device__ Energy local_opt_group(const LigL &L, const Layout &lay, float *wave_base, const ChainL &C,
                                   const IntraRegs<PPL, NBW> &pr, const GridView &G, const SearchParams &P, float *x,
@@ -1194,8 +1195,9 @@ __device__ Energy local_opt_group(const LigL &L, const Layout &lay, float *wave_
             }
             gw = acc_slot;
         }
+        // that wave also takes the optimiser's step below, so no other wave waits
+        // for the gradient
         if (w == gw) eval_gradient(L, S, pr, G, S.trial, P.wall_slope, S.gt);
-        if (gw != 0) __syncthreads();
         if (t0 < 0) {
             Ex = get_energy(C.et);
             evals++;
@@ -1238,14 +1240,15 @@ __device__ Energy local_opt_group(const LigL &L, const Layout &lay, float *wave_
             it++;
         } else {
             const Energy Et = get_energy(C.et + 4 * acc_slot);
-            if (w == 0) {
-                const WaveL A = make_wave(wave_base + acc_slot * lay.wave_words, lay);
+            if (w == acc_slot) {
+                // the accepted trial's wave: s = alpha p, y = g_new - g, x <- trial
                 s_l = 0.f;
                 y_l = 0.f;
+                g_l = 0.f;
                 if (lane < D) {
-                    const float gn = A.gt[lane];
+                    const float gn = S.gt[lane];
                     s_l = alpha_acc * C.p[lane];
-                    y_l = gn - g_l;
+                    y_l = gn - C.g[lane];
                     g_l = gn;
                 }
                 if (lane < Dp) {
@@ -1253,7 +1256,7 @@ __device__ Energy local_opt_group(const LigL &L, const Layout &lay, float *wave_
                     C.y[lane] = y_l;
                     C.g[lane] = g_l;
                 }
-                if (lane < L.nx) x[lane] = A.trial[lane];
+                if (lane < L.nx) x[lane] = S.trial[lane];
                 ys = wave_sum(s_l * y_l);
             }
             Ex = Et;
@@ -1262,7 +1265,8 @@ __device__ Energy local_opt_group(const LigL &L, const Layout &lay, float *wave_
         if (it >= iters) break;
         // direction of the next iteration: p = -g (Barzilai-Borwein; after the
         // start evaluation of BFGS, where H = I), else the BFGS update of H with
-        // this iteration's s, y when s.y > 0 and p = -H g (wave 0, which owns g and H)
+        // this iteration's s, y when s.y > 0 and p = -H g (by the accepted trial's
+        // wave, which holds s, y and g)
         if (w == 0 && (bb || t0 < 0)) {
             wave_sync();
             if (bb) {
@@ -1273,7 +1277,7 @@ __device__ Energy local_opt_group(const LigL &L, const Layout &lay, float *wave_
                 const float g_p = wave_sum(pl * g_l);
                 if (lane == 0) C.misc[kMiscGp] = g_p;
             }
-        } else if (w == 0) {
+        } else if (w == gw) {
             const bool upd = ys > 0.f;
             float g_p;
             switch (Dp >> 2) {
