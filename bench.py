@@ -10,8 +10,10 @@ optimisation and a Metropolis test, then ranking to the top 9 poses, returned
 to the host.
 
 Printed JSON line (one):
-  value        pose evaluations per second over the timed steps (every energy +
-               gradient evaluation of the search, line-search trials included);
+  value        pose evaluations per second over the timed steps (every evaluation
+               the search makes: the energy at each line-search trial, with the
+               gradient where the method uses it, at the start point and the
+               accepted trial);
   ligands_per_s docking requests completed per second (plain per-ligand form);
   roofline     the search kernel (dominant): algorithmic FP32 flops per launch /
                its average device time (HIP events on the call's stream), vs the
@@ -52,17 +54,19 @@ FP32_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBPS = 8000.0
 
 
-def flops_per_eval(lig, n_pairs, D, evals_per_iter):
-    """Algorithmic FP32 operations of one pose evaluation (FMA = 2, sqrt/exp/div/sin/cos = 1).
+def flops_model(lig, n_pairs, D):
+    """Algorithmic FP32 operations (FMA = 2, sqrt/exp/div/sin/cos = 1) of the
+    search, as (per evaluation, per gradient, per BFGS iteration).
 
-    per atom 131: placement 18, grid coordinates and weights 28, 4-channel
-      trilinear 64, wall/force 3, torque 12, fragment sums 6;
-    per intra pair 63: distance 10, terms 35 (2 exp), force scalar 1, force to
-      both atoms 17;
-    per fragment 126 + 63 per ancestor: local rotation 22, composition 63 per
-      level, world frame 63, subtree sum 18 per member, axis projection 23;
-    BFGS per iteration 10 D^2 + 60 (direction, curvature update, pose step),
-      shared by that iteration's evaluations.
+    An evaluation (every line-search trial) takes the energy: per atom 65
+    (placement 18, grid coordinates and weights 28, energy channel 16, wall 3);
+    per intra pair 45 (distance 10, terms with 2 exp 35); per fragment 85 + 63
+    per ancestor (local rotation 22, composition 63 per level, world frame 63).
+    A gradient (the start point and each accepted trial) adds per atom 66
+    (three gradient channels 48, torque 12, fragment sums 6), per pair 18 (force
+    scalar 1, force to both atoms 17) and per fragment 23 + 18 per subtree member
+    (axis projection, subtree sums).  BFGS: 10 D^2 + 60 per iteration (direction,
+    curvature update, pose step).
     """
     nf = lig.n_frags
     depth = [0] * nf
@@ -71,8 +75,9 @@ def flops_per_eval(lig, n_pairs, D, evals_per_iter):
         depth[k] = depth[lig.frag_parent[k]] + 1
     for k in range(nf - 1, 0, -1):
         sub[lig.frag_parent[k]] += sub[k]
-    frag = sum(126 + 63 * depth[k] + 18 * sub[k] for k in range(nf))
-    return 131 * lig.n_atoms + 63 * n_pairs + frag + (10 * D * D + 60) / max(evals_per_iter, 1.0)
+    energy = 65 * lig.n_atoms + 45 * n_pairs + sum(85 + 63 * depth[k] for k in range(nf))
+    gradient = 66 * lig.n_atoms + 18 * n_pairs + sum(23 + 18 * sub[k] for k in range(nf))
+    return energy, gradient, 10 * D * D + 60
 
 
 def measured_traffic(mc_steps):
@@ -554,13 +559,16 @@ def main():
     value = evals / elapsed
     evals_per_launch = evals / args.steps
     avg_search_s = float(np.mean(search_ms)) * 1e-3
-    # evaluations per BFGS iteration: each local optimisation makes one start
-    # evaluation plus at most bfgs_iters line searches
-    evals_per_lopt = stats.pose_evals / max(stats.local_opts, 1)
-    evals_per_iter = max(1.0, (evals_per_lopt - 1.0) / 20.0)
+    # algorithmic work per launch: an energy per evaluation; a gradient at each
+    # local optimisation's start and accepted trial (at most 1 + 20 per local
+    # optimisation: a line search that rejects every trial ends it early, so
+    # this slightly overstates the work); a BFGS update per iteration
     n_pairs, _ = D.dsdp_ligand_info(L)
-    fpe = flops_per_eval(lig, n_pairs, 6 + lig.n_torsions, evals_per_iter)
-    achieved = evals_per_launch * fpe / avg_search_s / 1e12
+    fe, fg, fb = flops_model(lig, n_pairs, 6 + lig.n_torsions)
+    lopts = stats.local_opts
+    flops_launch = fe * evals_per_launch + fg * lopts * 21 + fb * lopts * 20
+    fpe = flops_launch / evals_per_launch
+    achieved = flops_launch / avg_search_s / 1e12
     gather_gbps = evals_per_launch * lig.n_atoms * 128 / avg_search_s / 1e9
     traffic = measured_traffic(n_steps)
 
