@@ -47,6 +47,23 @@ def test_geometry_queries():
     with pytest.raises(D.DsdpError) as e:
         D.dsdp_grid_dims({"centre": (0, 0, 0), "size": 10.0, "spacing": -1.0})
     assert e.value.status == D.DSDP_ERR_INVALID_ARG
+    # at most 2048 nodes per axis and fewer than 2^31 per map
+    big = {"centre": (0, 0, 0), "size": 80.0, "spacing": 0.05}   # 1600^3 nodes (float spacing)
+    with pytest.raises(D.DsdpError) as e:
+        D.dsdp_grid_dims(big)
+    assert e.value.status == D.DSDP_ERR_UNSUPPORTED
+    assert D.dsdp_grids_bytes(big, 1) == 0
+    n, _ = D.dsdp_grid_dims({"centre": (0, 0, 0), "size": 60.0, "spacing": 0.05})   # 1200^3 < 2^31
+    assert n == (1200, 1200, 1200)
+
+
+def test_gather_probe_host_checks():
+    assert D.dsdp_gather_probe_workspace_bytes(0) == 0
+    assert D.dsdp_gather_probe_workspace_bytes(4) == 4096
+    assert D.dsdp_gather_probe_workspace_bytes(5) == 5120
+    with pytest.raises(D.DsdpError) as e:
+        D.dsdp_gather_probe(None, 4, 4, FakeDev(4096))
+    assert e.value.status == D.DSDP_ERR_INVALID_ARG
 
 
 class FakeDev:
