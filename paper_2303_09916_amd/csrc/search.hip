@@ -294,6 +294,7 @@ struct LigL {
 struct WaveL {
     float4 *xyz;
     float4 *pf;            // [np + 1] force of each pair on its first atom; slot np stays 0
+    float *pe;             // [np + 1] the same pairs' energies, densely (spread over the LDS banks)
     float4 *af, *at;       // [64]: per lane, the forces the energy half leaves for the gradient
                            // half, then prefix sums over atoms of force and of torque about the
                            // root origin
@@ -320,7 +321,7 @@ constexpr int kOptBB = 1;        // SearchParams::optimizer value of Barzilai-Bo
 __host__ __device__ inline int rup4(int v) { return (v + 3) & ~3; }
 
 struct Layout {
-    int xyz, pf, af, at, R, trial, gt, wave_words;         // per-wave offsets
+    int xyz, pf, pe, af, at, R, trial, gt, wave_words;     // per-wave offsets
     int vec, H, hs, pose, et, misc, chain_words, Dp, NXp;     // per-chain offsets
 };
 __host__ __device__ inline Layout make_layout(int na, int nf, int np, int D, int nx)
@@ -333,6 +334,7 @@ __host__ __device__ inline Layout make_layout(int na, int nf, int np, int D, int
     // np = -1: no pair-force scratch (atom lists); else the pairs, the zero slot
     // np, and entries up to a whole group of two 64-pair slots
     c.pf = w; w += np < 0 ? 0 : 4 * max(np + 1, 128 * ((np + 127) / 128));
+    c.pe = w; w += np < 0 ? 0 : rup4(max(np + 1, 128 * ((np + 127) / 128)));
     c.af = w; w += 4 * 64;   // one entry per lane (the energy half leaves its forces here)
     c.at = w; w += 4 * 64;
     c.R = w; w += 16 * nf;
@@ -355,6 +357,7 @@ __device__ inline WaveL make_wave(float *base, const Layout &c)
     WaveL S;
     S.xyz = reinterpret_cast<float4 *>(base + c.xyz);
     S.pf = reinterpret_cast<float4 *>(base + c.pf);
+    S.pe = base + c.pe;
     S.af = reinterpret_cast<float4 *>(base + c.af);
     S.at = reinterpret_cast<float4 *>(base + c.at);
     S.R = reinterpret_cast<float4 *>(base + c.R);
@@ -721,11 +724,13 @@ __device__ Energy eval_energy(const LigL &L, const WaveL &S, const IntraRegs<PPL
                     if constexpr (PPL == 8) {
                         // a padding lane (both indices 0, so dx = dy = dz = +0)
                         // stores +0 into its own entry, at or past the zero slot np
-                        // (the array is padded to whole groups): no branch, so the
+                        // (the arrays are padded to whole groups): no branch, so the
                         // group's pair terms interleave
                         S.pf[lane + 64 * (g + k)] = v;
+                        S.pe[lane + 64 * (g + k)] = ep;
                     } else if (!none) {
                         S.pf[lane + 64 * (g + k)] = v;   // fewer registers live for the larger lists
+                        S.pe[lane + 64 * (g + k)] = ep;
                     }
                 }
             }
@@ -789,7 +794,7 @@ __device__ Energy eval_energy(const LigL &L, const WaveL &S, const IntraRegs<PPL
         if constexpr (kRegChunks > 0) {
             float v[16];
 #pragma unroll
-            for (int t = 0; t < 16; t++) v[t] = S.pf[pl_entry(pr.pl, t) & 0x7fffu].w;
+            for (int t = 0; t < 16; t++) v[t] = S.pe[pl_entry(pr.pl, t) & 0x7fffu];
 #pragma unroll
             for (int t = 0; t < 16; t++) {
                 if (t == 8 && L.n_chunks < 2) break;
@@ -800,7 +805,7 @@ __device__ Energy eval_energy(const LigL &L, const WaveL &S, const IntraRegs<PPL
             const uint4 q = L.plist[c * 64 + lane];
             float v[8];
 #pragma unroll
-            for (int t = 0; t < 8; t++) v[t] = S.pf[chunk_entry(q, t) & 0x7fffu].w;
+            for (int t = 0; t < 8; t++) v[t] = S.pe[chunk_entry(q, t) & 0x7fffu];
 #pragma unroll
             for (int t = 0; t < 8; t++) e_lane += (chunk_entry(q, t) & 0x8000u) ? 0.f : v[t];
         }
@@ -1324,7 +1329,10 @@ __global__ __launch_bounds__(256) void eval_kernel(const uint32_t *__restrict__ 
     const int idx = blockIdx.x * (blockDim.x >> 6) + wave_id();
     if (idx >= n) return;
     const int lane = lane_id();
-    if (PPL > 0 && lane == 0) S.pf[L.np] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (PPL > 0 && lane == 0) {
+        S.pf[L.np] = make_float4(0.f, 0.f, 0.f, 0.f);
+        S.pe[L.np] = 0.f;
+    }
     if (lane < L.nx) S.trial[lane] = poses[(long)idx * L.nx + lane];
     wave_sync();
     const IntraRegs<PPL, NBW> pr = load_intra<PPL, NBW>(L);
@@ -1360,7 +1368,11 @@ __global__ __launch_bounds__(256) void local_opt_kernel(const uint32_t *blob, in
     const int W = (int)(blockDim.x >> 6);
     const int idx = blockIdx.x;
     const int lane = lane_id(), w = wave_id();
-    if (PPL > 0 && lane == 0) make_wave(wbase + w * lay.wave_words, lay).pf[L.np] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (PPL > 0 && lane == 0) {
+        const WaveL S0 = make_wave(wbase + w * lay.wave_words, lay);
+        S0.pf[L.np] = make_float4(0.f, 0.f, 0.f, 0.f);
+        S0.pe[L.np] = 0.f;
+    }
     if (w == 0 && lane < L.nx) C.cur[lane] = poses_in[(long)idx * L.nx + lane];
     __syncthreads();
     int evals = 0;
@@ -1407,7 +1419,11 @@ __global__ __launch_bounds__(256) void tick_kernel(const uint32_t *arena, const 
     const uint64_t seed = (uint64_t)t.seed_lo | ((uint64_t)t.seed_hi << 32);
     float *st = state + (long)t.slot * kStWords;
     int *sti = reinterpret_cast<int *>(st);
-    if (PPL > 0 && lane == 0) make_wave(wbase + w * lay.wave_words, lay).pf[L.np] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (PPL > 0 && lane == 0) {
+        const WaveL S0 = make_wave(wbase + w * lay.wave_words, lay);
+        S0.pf[L.np] = make_float4(0.f, 0.f, 0.f, 0.f);
+        S0.pe[L.np] = 0.f;
+    }
 
     Energy Ex, Eb;
     int step, evals, accepted, lopts;
