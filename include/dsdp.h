@@ -141,7 +141,8 @@ typedef struct {
 
 /* Work counters of one dock call. */
 typedef struct {
-    int64_t pose_evals;              /* energy+gradient evaluations, every line-search trial counted */
+    int64_t pose_evals;              /* pose evaluations: every line-search trial (its energy; the gradient
+                                        only where the method uses it: start point, accepted trial) */
     int64_t local_opts;              /* local optimisations (= chains x steps) */
     int64_t accepted;                /* Metropolis acceptances */
     int32_t n_nonfinite;             /* chains whose best energy is not finite (excluded from ranking) */
