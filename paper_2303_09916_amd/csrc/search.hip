@@ -276,7 +276,8 @@ struct LigL {
     float rg;
     const float4 *atom;      // local offset, w = map index
     const float4 *fu;        // torsion axis in parent frame, w = (parent + 1) | depth << 16
-    const float4 *foff;      // origin in parent frame, w = subtree mask
+    const float4 *foff;      // origin in parent frame (w: subtree mask bits, not read here: subtrees
+                             // are slot ranges)
     const int *atom_frag;
     const int *atom_ext;         // caller's index of the atom in each slot
     const uint32_t *frag_range;  // first slot | end slot << 8 | subtree end slot << 16
@@ -612,7 +613,7 @@ __device__ inline float site_term(const GridView &G, const float *pose, float wa
 
 // Energy of `pose` (LDS, wave-uniform); every lane returns the same values.  The
 // gradient is left to eval_gradient (a line-search trial needs only the energy
-// unless it is accepted); what it needs stays in `cy` and the wave's scratch,
+// unless it is accepted); what it needs stays in the wave's scratch,
 // coordinates in S.xyz.
 template <int PPL, int NBW>
 __device__ Energy eval_energy(const LigL &L, const WaveL &S, const IntraRegs<PPL, NBW> &pr, const GridView &G,
