@@ -177,6 +177,19 @@ __device__ __forceinline__ float4 quat_mul(float4 a, float4 b)
                        a.x * b.z - a.y * b.w + a.z * b.x + a.w * b.y,
                        a.x * b.w + a.y * b.z - a.z * b.y + a.w * b.x);
 }
+// rotation by th about the unit axis u (xyz) as a quaternion (w, x, y, z in x, y, z, w)
+__device__ __forceinline__ float4 quat_axis(float4 u, float th)
+{
+    const float s = __sinf(0.5f * th), c = __cosf(0.5f * th);
+    return make_float4(c, s * u.x, s * u.y, s * u.z);
+}
+// R(q) v for a unit quaternion q: v + w t + r x t with t = 2 r x v, r the vector part
+__device__ __forceinline__ float3 quat_rotate(float4 q, float3 v)
+{
+    const float3 r = make_float3(q.y, q.z, q.w);
+    const float3 t = 2.f * cross3(r, v);
+    return v + q.x * t + cross3(r, t);
+}
 __device__ __forceinline__ float4 quat_normalize(float4 q)
 {
     const float k = rsqrtf(q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w);
@@ -462,16 +475,20 @@ struct Energy {
 // World frame (rotation rows and origin) of every fragment for `pose`, in S.R:
 // R_k = R_0 Q_a1 .. Q_k and o_k = p + R_0 (off_a1 + Q_a1 (off_a2 + ... off_k)) over
 // k's ancestors a1, a2, .. below the root, with R_0 = R(q) and Q_m the rotation
-// of fragment m about its torsion axis.  Lane k forms its frame alone: the loads
+// of fragment m about its torsion axis (composed as quaternions, see below).
+// Lane k forms its frame alone: the loads
 // for k and its first two ancestors (from anc, a per-lane list) are issued
 // together and every lane computes the rotations it needs; deeper ancestors, if
 // any, follow the parent links.
 __device__ inline void frames(const LigL &L, const WaveL &S, uint32_t anc, const float *pose)
 {
+    // composed as unit quaternions ((w, x, y, z) in the x, y, z, w slots): a
+    // torsion rotation is (cos(theta/2), sin(theta/2) u), products and vector
+    // rotations need fewer operations than 3x3 matrices; one matrix per fragment
+    // is formed at the end
     const int lane = lane_id();
-    const float4 q = quat_normalize(make_float4(pose[3], pose[4], pose[5], pose[6]));
-    const M3 R0 = quat_to_mat(q.x, q.y, q.z, q.w);
-    M3 R = R0;
+    const float4 q0 = quat_normalize(make_float4(pose[3], pose[4], pose[5], pose[6]));
+    float4 qR = q0;
     float3 o = make_float3(pose[0], pose[1], pose[2]);
     if (lane > 0 && lane < L.nf) {
         constexpr int kAhead = 3;   // the fragment and two ancestors
@@ -488,28 +505,29 @@ __device__ inline void frames(const LigL &L, const WaveL &S, uint32_t anc, const
             off[j] = L.foff[m];
             th[j] = pose[6 + m];
         }
-        M3 M = axis_angle(u[0].x, u[0].y, u[0].z, th[0]);
+        float4 qM = quat_axis(u[0], th[0]);
         float3 v = f3(off[0]);
 #pragma unroll
         for (int j = 1; j < kAhead; j++) {
             if (mm[j] > 0) {
-                const M3 Qm = axis_angle(u[j].x, u[j].y, u[j].z, th[j]);
-                v = f3(off[j]) + mv(Qm, v);
-                M = mul(Qm, M);
+                const float4 qm = quat_axis(u[j], th[j]);
+                v = f3(off[j]) + quat_rotate(qm, v);
+                qM = quat_mul(qm, qM);
             }
         }
         int m = mm[kAhead - 1] > 0 ? (int)(__float_as_uint(u[kAhead - 1].w) & 0xffffu) - 1 : 0;
         while (m > 0) {
             const float4 um = L.fu[m];
-            const M3 Qm = axis_angle(um.x, um.y, um.z, pose[6 + m]);
-            v = f3(L.foff[m]) + mv(Qm, v);
-            M = mul(Qm, M);
+            const float4 qm = quat_axis(um, pose[6 + m]);
+            v = f3(L.foff[m]) + quat_rotate(qm, v);
+            qM = quat_mul(qm, qM);
             m = (int)(__float_as_uint(um.w) & 0xffffu) - 1;
         }
-        R = mul(R0, M);
-        o = o + mv(R0, v);
+        qR = quat_normalize(quat_mul(q0, qM));
+        o = o + quat_rotate(q0, v);
     }
     if (lane < L.nf) {
+        const M3 R = quat_to_mat(qR.x, qR.y, qR.z, qR.w);
         S.R[4 * lane + 0] = make_float4(R.a[0], R.a[1], R.a[2], 0.f);
         S.R[4 * lane + 1] = make_float4(R.a[3], R.a[4], R.a[5], 0.f);
         S.R[4 * lane + 2] = make_float4(R.a[6], R.a[7], R.a[8], 0.f);
