@@ -493,7 +493,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the docking chains are independent "
-              f"and a multi-GPU run would replicate maps and split chains, which this build does not launch.",
+              f"so a multi-GPU run would replicate the maps and split the chains across GPUs; that path is not "
+              f"implemented here.",
               file=sys.stderr)
         sys.exit(2)
 

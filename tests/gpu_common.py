@@ -1,7 +1,7 @@
 """GPU-side fixtures: device buffers and library calls for the parity tests.
 
 Every call goes through the C ABI (libdsdp.so) via the package's ctypes binding.
-The library must be built; if it is missing on a GPU machine the tests fail (they do
+The library must be built; if it is missing on a machine with a GPU the tests fail (they do
 not skip).
 """
 import numpy as np
