@@ -758,16 +758,23 @@ __device__ Energy eval_energy(const LigL &L, const WaveL &S, const IntraRegs<PPL
         const int a = L.lanes_per_atom == 2 ? (lane & 31) : lane;
         if (a < L.na) {
             const float4 xa = S.xyz[a];
+            // the next word's partner positions are loaded while this word's four
+            // pairs are evaluated
+            uint32_t word = L.nbr_words > 0 ? L.nbr[lane] : 0xFFFFFFFFu;
+            float4 xj[4];
+#pragma unroll
+            for (int b = 0; b < 4; b++) {
+                const uint32_t e = (word >> (8 * b)) & 255u;
+                xj[b] = S.xyz[e != kNbrNone ? (int)(e & 63u) : a];
+            }
 #pragma unroll 1
             for (int m = 0; m < L.nbr_words; m++) {
-                const uint32_t word = L.nbr[m * 64 + lane];
-                // the word's four partners loaded at once (an empty byte reads the
-                // lane's own atom), then evaluated without branches
-                float4 xj[4];
+                const uint32_t nword = m + 1 < L.nbr_words ? L.nbr[(m + 1) * 64 + lane] : 0xFFFFFFFFu;
+                float4 xn[4];
 #pragma unroll
                 for (int b = 0; b < 4; b++) {
-                    const uint32_t e = (word >> (8 * b)) & 255u;
-                    xj[b] = S.xyz[e != kNbrNone ? (int)(e & 63u) : a];
+                    const uint32_t e = (nword >> (8 * b)) & 255u;
+                    xn[b] = S.xyz[e != kNbrNone ? (int)(e & 63u) : a];
                 }
 #pragma unroll
                 for (int b = 0; b < 4; b++) {
@@ -782,6 +789,9 @@ __device__ Energy eval_energy(const LigL &L, const WaveL &S, const IntraRegs<PPL
                     fnb.y = use ? add_product(fnb.y, es.y, dy) : fnb.y;
                     fnb.z = use ? add_product(fnb.z, es.y, dz) : fnb.z;
                 }
+                word = nword;
+#pragma unroll
+                for (int b = 0; b < 4; b++) xj[b] = xn[b];
             }
         }
     }
