@@ -117,6 +117,10 @@ typedef struct {
     int32_t bb_iters;        /* Barzilai-Borwein iterations; the paper finds 100-150 enough (100) */
     float bb_step0;          /* first step length, and the one used after a step with s.y <= 0 (0.01) */
     float bb_step_max;       /* largest step length (1.0) */
+    float ls_min_decrease;   /* a line-search trial is accepted only if it lowers the energy by at
+                                least this much besides passing the Armijo test (kcal/mol; 1e-4).
+                                Float32 energies of nearby poses differ by rounding noise of about
+                                1e-5 kcal/mol, so smaller decreases are not resolved */
 } dsdp_params;
 
 #define DSDP_OPT_BFGS 0

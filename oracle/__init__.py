@@ -33,7 +33,8 @@ class Params(C.Structure):
     _fields_ = [("temperature", C.c_double), ("wall_slope", C.c_double), ("rmsd_cluster", C.c_double),
                 ("trans_amp", C.c_double), ("bfgs_iters", C.c_int), ("ls_trials", C.c_int),
                 ("ls_shrink", C.c_double), ("armijo_c1", C.c_double), ("optimizer", C.c_int),
-                ("bb_iters", C.c_int), ("bb_step0", C.c_double), ("bb_step_max", C.c_double)]
+                ("bb_iters", C.c_int), ("bb_step0", C.c_double), ("bb_step_max", C.c_double),
+                ("ls_min_decrease", C.c_double)]
 
 
 OPT_BFGS, OPT_BB = 0, 1
@@ -80,7 +81,8 @@ def lib():
         "orc_local_opt": (C.c_long, [vp, vp, C.POINTER(Params), _dp, C.POINTER(C.c_double), vp,
                                      C.POINTER(C.c_double)]),
         "orc_bfgs_plain": (C.c_long, [OBJECTIVE, C.c_int, _dp, C.POINTER(C.c_double), _dp, C.c_int, C.c_int,
-                                      C.c_double, C.c_double]),
+                                      C.c_double, C.c_double, C.c_double]),
+        "orc_bfgs_update": (None, [C.c_int, _dp, _dp, _dp]),
         "orc_bb_plain": (C.c_long, [OBJECTIVE, C.c_int, _dp, C.POINTER(C.c_double), _dp, C.c_int, C.c_double,
                                     C.c_double]),
         "orc_philox": (None, [_up, _up, _up]),
@@ -326,7 +328,7 @@ class LigandModel:
         return bp, be, cnt
 
 
-def bfgs_plain(fun, x0, iters=100, trials=10, shrink=0.1, c1=1e-4):
+def bfgs_plain(fun, x0, iters=100, trials=10, shrink=0.1, c1=1e-4, min_dec=0.0):
     """Oracle BFGS on a plain function fun(x) -> (f, grad) (textbook pins)."""
     D = len(x0)
 
@@ -341,8 +343,22 @@ def bfgs_plain(fun, x0, iters=100, trials=10, shrink=0.1, c1=1e-4):
     x = np.array(x0, dtype=np.float64)
     fx = C.c_double()
     g = np.zeros(D)
-    n = lib().orc_bfgs_plain(cfun, D, x, C.byref(fx), g, iters, trials, shrink, c1)
+    n = lib().orc_bfgs_plain(cfun, D, x, C.byref(fx), g, iters, trials, shrink, c1, min_dec)
     return x, fx.value, g, n
+
+
+MAXD = 40   # row stride of the oracle's inverse-Hessian matrix
+
+
+def bfgs_update(H, s, y):
+    """The oracle's inverse-BFGS update of the symmetric D x D matrix H with step
+    s and gradient change y (y.s > 0); returns the new matrix."""
+    D = len(s)
+    Hp = np.zeros((MAXD, MAXD))
+    Hp[:D, :D] = H
+    lib().orc_bfgs_update(D, Hp.reshape(-1), np.ascontiguousarray(s, dtype=np.float64),
+                          np.ascontiguousarray(y, dtype=np.float64))
+    return Hp[:D, :D].copy()
 
 
 def philox(ctr, key):

@@ -862,6 +862,7 @@ typedef struct {
     int bb_iters;             /* Barzilai-Borwein iterations */
     double bb_step0;          /* first BB step length (and the one used when s.y <= 0) */
     double bb_step_max;       /* largest BB step length */
+    double ls_min_decrease;   /* smallest energy decrease a line-search trial must reach */
 } orc_params;
 
 void orc_params_default(orc_params *p)
@@ -878,6 +879,7 @@ void orc_params_default(orc_params *p)
     p->bb_iters = 100;        /* the paper finds 100-150 BB iterations enough (Section 2, Figure 2) */
     p->bb_step0 = 1e-2;
     p->bb_step_max = 1.0;
+    p->ls_min_decrease = 1e-4;
 }
 
 /* generic objective: returns f(x), writes g = grad f(x) (dimension D) */
@@ -889,21 +891,46 @@ typedef void (*orc_retract)(void *ctx, const double *x, const double *step, doub
 #define ORC_MAXX 48
 
 /*
+ * Inverse-BFGS update of the D x D matrix H (row stride ORC_MAXD) with the step s
+ * and gradient change y, y.s > 0 (Nocedal & Wright, ref. [36]):
+ *   H <- (I - rho s y^T) H (I - rho y s^T) + rho s s^T,  rho = 1 / y.s,
+ * written out for a symmetric H as
+ *   H + rho ((1 + rho y^T H y) s s^T - s (H y)^T - (H y) s^T).
+ * The result satisfies the secant condition H y = s.
+ */
+void orc_bfgs_update(int D, double *H, const double *s, const double *y)
+{
+    double Hy[ORC_MAXD], ys = 0, yHy = 0;
+    for (int r = 0; r < D; r++) ys += y[r] * s[r];
+    const double rho = 1.0 / ys;
+    for (int r = 0; r < D; r++) {
+        double acc = 0;
+        for (int c = 0; c < D; c++) acc += H[r * ORC_MAXD + c] * y[c];
+        Hy[r] = acc;
+        yHy += y[r] * acc;
+    }
+    for (int r = 0; r < D; r++)
+        for (int c = 0; c < D; c++)
+            H[r * ORC_MAXD + c] += rho * ((1.0 + rho * yHy) * s[r] * s[c] - s[r] * Hy[c] - Hy[r] * s[c]);
+}
+
+/*
  * Inverse-BFGS minimisation in tangent coordinates.
  *   H = I; repeat `iters` times:
  *     p = -H g;  line search: alpha = 1, shrink by `shrink` up to `trials` times
- *     until f(x (+) alpha p) <= f(x) + c1 alpha g.p (Armijo); none accepted -> stop;
- *     s = alpha p, y = g_new - g; if y.s > 0:
- *       H <- (I - rho s y^T) H (I - rho y s^T) + rho s s^T,  rho = 1 / y.s.
+ *     until f(x (+) alpha p) - f(x) <= min(c1 alpha g.p, -min_dec) (the Armijo
+ *     test, with a decrease of at least min_dec); none accepted -> stop;
+ *     s = alpha p, y = g_new - g; if y.s > 0: inverse-BFGS update of H.
  * x has dimension nx (the pose, with a 4-component quaternion), the tangent
  * space dimension D.  Returns the number of objective evaluations.  margin
- * (nullable) receives the smallest relative distance of any Armijo or curvature
- * test from its threshold (how close the run came to a different decision).
+ * (nullable) receives the smallest relative distance of any line-search or
+ * curvature test from its threshold (how close the run came to a different
+ * decision).
  */
 long orc_bfgs(void *ctx, orc_objective f, orc_retract retract, int nx, int D, double *x, double *fx, double *g,
-              int iters, int trials, double shrink, double c1, double *margin)
+              int iters, int trials, double shrink, double c1, double min_dec, double *margin)
 {
-    double H[ORC_MAXD][ORC_MAXD], p[ORC_MAXD], gn[ORC_MAXD], s[ORC_MAXD], y[ORC_MAXD], Hy[ORC_MAXD];
+    double H[ORC_MAXD][ORC_MAXD], p[ORC_MAXD], gn[ORC_MAXD], s[ORC_MAXD], y[ORC_MAXD];
     double xn[ORC_MAXX], step[ORC_MAXD];
     long evals = 0;
     double mmin = DBL_MAX;
@@ -925,10 +952,10 @@ long orc_bfgs(void *ctx, orc_objective f, orc_retract retract, int nx, int D, do
             retract(ctx, x, step, xn);
             En = f(ctx, xn, gn);
             evals++;
-            double thr = E + c1 * alpha * gp;
-            double rel = fabs(En - thr) / (fabs(E) + fabs(thr) + 1e-12);
+            double thr = fmin(c1 * alpha * gp, -min_dec);
+            double rel = fabs((En - E) - thr) / (fabs(E) + fabs(E + thr) + 1e-12);
             if (rel < mmin) mmin = rel;
-            if (En <= thr) { ok = 1; break; }
+            if (En - E <= thr) { ok = 1; break; }
             alpha *= shrink;
         }
         if (!ok) break;
@@ -945,19 +972,7 @@ long orc_bfgs(void *ctx, orc_objective f, orc_retract retract, int nx, int D, do
         E = En;
         double crel = fabs(ys) / (sqrt(ss * yy) + 1e-300);
         if (crel < mmin) mmin = crel;
-        if (ys > 0) {
-            double rho = 1.0 / ys, yHy = 0;
-            for (int r = 0; r < D; r++) {
-                double acc = 0;
-                for (int c = 0; c < D; c++) acc += H[r][c] * y[c];
-                Hy[r] = acc;
-                yHy += y[r] * acc;
-            }
-            /* expanded form of the inverse update (H symmetric) */
-            for (int r = 0; r < D; r++)
-                for (int c = 0; c < D; c++)
-                    H[r][c] += rho * ((1.0 + rho * yHy) * s[r] * s[c] - s[r] * Hy[c] - Hy[r] * s[c]);
-        }
+        if (ys > 0) orc_bfgs_update(D, &H[0][0], s, y);
     }
     *fx = E;
     if (margin) *margin = mmin;
@@ -1059,7 +1074,7 @@ long orc_local_opt(const orc_ligand *L, const orc_grid *g, const orc_params *prm
                    prm->bb_step0, prm->bb_step_max, margin);
     } else {
         n = orc_bfgs(&c, pose_objective, pose_retract, 7 + L->n_tors, 6 + L->n_tors, pose, E, gl,
-                     prm->bfgs_iters, prm->ls_trials, prm->ls_shrink, prm->armijo_c1, margin);
+                     prm->bfgs_iters, prm->ls_trials, prm->ls_shrink, prm->armijo_c1, prm->ls_min_decrease, margin);
     }
     if (grad) memcpy(grad, gl, sizeof(double) * (6 + L->n_tors));
     return n;
@@ -1078,10 +1093,10 @@ static void plain_retract(void *vctx, const double *x, const double *step, doubl
     for (int r = 0; r < c->D; r++) xn[r] = x[r] + step[r];
 }
 long orc_bfgs_plain(orc_objective f, int D, double *x, double *fx, double *g, int iters, int trials, double shrink,
-                    double c1)
+                    double c1, double min_dec)
 {
     plain_ctx c = {f, D};
-    return orc_bfgs(&c, plain_objective, plain_retract, D, D, x, fx, g, iters, trials, shrink, c1, NULL);
+    return orc_bfgs(&c, plain_objective, plain_retract, D, D, x, fx, g, iters, trials, shrink, c1, min_dec, NULL);
 }
 
 /* generic Barzilai-Borwein over a ctypes callback, for textbook-function pins */

@@ -56,7 +56,8 @@ class dsdp_params(C.Structure):
                 ("rmsd_cluster", C.c_float), ("trans_amp", C.c_float), ("bfgs_iters", C.c_int32),
                 ("ls_trials", C.c_int32), ("ls_shrink", C.c_float), ("armijo_c1", C.c_float),
                 ("waves_per_chain", C.c_int32), ("intra_form", C.c_int32), ("optimizer", C.c_int32),
-                ("bb_iters", C.c_int32), ("bb_step0", C.c_float), ("bb_step_max", C.c_float)]
+                ("bb_iters", C.c_int32), ("bb_step0", C.c_float), ("bb_step_max", C.c_float),
+                ("ls_min_decrease", C.c_float)]
 
 
 class dsdp_pose(C.Structure):

@@ -438,6 +438,7 @@ SearchParams to_search(const dsdp_params *p)
     s.bb_iters = p->bb_iters;
     s.bb_step0 = p->bb_step0;
     s.bb_step_max = p->bb_step_max;
+    s.ls_min_decrease = p->ls_min_decrease;
     return s;
 }
 
@@ -449,7 +450,7 @@ dsdp_status check_params(const dsdp_params *p)
         p->bfgs_iters < 0 || p->ls_trials < 1 || !(p->ls_shrink > 0 && p->ls_shrink < 1) || !(p->armijo_c1 >= 0) ||
         p->waves_per_chain < 0 || p->waves_per_chain > 4 || p->intra_form < DSDP_INTRA_AUTO ||
         p->intra_form > DSDP_INTRA_ATOMS || (p->optimizer != DSDP_OPT_BFGS && p->optimizer != DSDP_OPT_BB) ||
-        p->bb_iters < 0 || !(p->bb_step0 > 0) || !(p->bb_step_max >= p->bb_step0))
+        p->bb_iters < 0 || !(p->bb_step0 > 0) || !(p->bb_step_max >= p->bb_step0) || !(p->ls_min_decrease >= 0))
         return fail(DSDP_ERR_INVALID_ARG, "search parameter out of range");
     return DSDP_OK;
 }
@@ -681,6 +682,7 @@ void dsdp_params_default(dsdp_params *p)
     p->bb_iters = 100;
     p->bb_step0 = 1e-2f;
     p->bb_step_max = 1.0f;
+    p->ls_min_decrease = 1e-4f;
 }
 
 dsdp_status dsdp_grid_dims(const dsdp_box *box, int32_t *n, float *origin)

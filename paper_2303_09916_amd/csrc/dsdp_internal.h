@@ -157,6 +157,7 @@ struct SearchParams {
     float ls_shrink, armijo_c1;
     int optimizer, bb_iters;     // DSDP_OPT_*; Barzilai-Borwein iterations
     float bb_step0, bb_step_max;
+    float ls_min_decrease;       // smallest energy decrease a line-search trial must reach
 };
 
 // Launchers (defined in the .hip files).

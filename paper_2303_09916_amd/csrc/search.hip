@@ -1208,11 +1208,16 @@ __device__ Energy local_opt_group(const LigL &L, const Layout &lay, float *wave_
             float4 et4[kMaxWaves];
 #pragma unroll
             for (int q = 0; q < kMaxWaves; q++) et4[q] = reinterpret_cast<const float4 *>(C.et)[q];
+            // Armijo test on the energy change, E(trial) - E(x) <= c1 a g.p, which
+            // must also be a decrease of at least ls_min_decrease.  The float
+            // difference of two nearby energies is exact, whereas forming
+            // E(x) + c1 a g.p would round the tiny term away near convergence
+            // and accept trials that do not lower the energy at all.
             int v = 0;
 #pragma unroll
             for (; v < kMaxWaves; v++) {
                 if (v >= W || t0 + v >= P.ls_trials) break;
-                if (et4[v].x <= Ex.total + P.armijo_c1 * a * gp) {
+                if (et4[v].x - Ex.total <= fminf(P.armijo_c1 * a * gp, -P.ls_min_decrease)) {
                     acc_slot = v;
                     alpha_acc = a;
                     break;
@@ -1505,9 +1510,11 @@ __global__ __launch_bounds__(256) void tick_kernel(const uint32_t *arena, const 
                     const float4 q = G.site[0];
                     C.cur[lane] = lane == 0 ? q.x : (lane == 1 ? q.y : q.z);
                 }
-                wave_sync();
-                copy_pose(L, C.cur, C.best);
             }
+            // the chain best starts as the initial pose (what a chain that takes
+            // no step reports)
+            wave_sync();
+            copy_pose(L, C.cur, C.best);
         }
         Ex.total = 0.f; Ex.inter = 0.f; Ex.intra = 0.f; Ex.wall = 0.f;
         Eb.total = __int_as_float(0x7f800000); Eb.inter = Eb.intra = Eb.wall = 0.f;

@@ -62,6 +62,55 @@ def test_bfgs_rosenbrock():
     np.testing.assert_allclose(x, [1.0, 1.0], atol=1e-5)
 
 
+def test_bfgs_update_secant_and_direct_form():
+    """The inverse update satisfies the secant condition H+ y = s, stays symmetric
+    positive definite for y.s > 0, and is the inverse of the direct BFGS update
+    B+ = B - B s s^T B / s^T B s + y y^T / y^T s of B = H^-1 (Nocedal & Wright,
+    ref. [36]): a wrong sign, index or transposed product fails one of these."""
+    rng = np.random.default_rng(3)
+    for D in (1, 2, 7, 13, 37):
+        M = rng.normal(size=(D, D))
+        H = M @ M.T + 0.5 * np.eye(D)
+        s = rng.normal(size=D)
+        y = rng.normal(size=D)
+        if y @ s <= 0:
+            y = -y
+        Hn = O.bfgs_update(H, s, y)
+        np.testing.assert_allclose(Hn @ y, s, rtol=1e-10, atol=1e-10 * np.abs(s).max())
+        np.testing.assert_allclose(Hn, Hn.T, rtol=0, atol=1e-12 * np.abs(Hn).max())
+        assert np.linalg.eigvalsh(Hn).min() > 0
+        B = np.linalg.inv(H)
+        Bs = B @ s
+        Bn = B - np.outer(Bs, Bs) / (s @ Bs) + np.outer(y, y) / (y @ s)
+        np.testing.assert_allclose(Hn, np.linalg.inv(Bn), rtol=1e-8, atol=1e-8 * np.abs(Hn).max())
+    # one dimension, H = 1: the secant step length s / y
+    np.testing.assert_allclose(O.bfgs_update(np.eye(1), [0.3], [1.5]), [[0.2]], rtol=1e-15)
+
+
+def test_bfgs_line_search_decisions():
+    """One iteration on f = x^2 from x = 1 (p = -2, g.p = -4): the full step lands
+    on f = 1 (no decrease, rejected), alpha = 0.1 gives x = 0.8 with a decrease of
+    0.36.  A required decrease above 0.36 rejects every trial: x stays, 1 + 10
+    evaluations.  An energy that is constant while its reported gradient is not
+    zero (what interpolated stored gradients can do near a minimum) never moves,
+    even when alpha c1 g.p is far below the energy's rounding unit."""
+    def quad(x):
+        return float(x[0] ** 2), np.array([2 * x[0]])
+
+    x, fx, g, n = O.bfgs_plain(quad, np.array([1.0]), iters=1)
+    assert x[0] == pytest.approx(0.8, abs=1e-15) and n == 3
+    x, fx, g, n = O.bfgs_plain(quad, np.array([1.0]), iters=1, min_dec=0.3)
+    assert x[0] == pytest.approx(0.8, abs=1e-15) and n == 3
+    x, fx, g, n = O.bfgs_plain(quad, np.array([1.0]), iters=1, min_dec=0.5)
+    assert x[0] == 1.0 and n == 11 and fx == 1.0
+
+    def flat(x):
+        return 1.0e3, np.array([1.0])
+
+    x, fx, g, n = O.bfgs_plain(flat, np.array([0.25]), iters=5, trials=20)
+    assert x[0] == 0.25 and n == 21
+
+
 @pytest.fixture(scope="module")
 def site():
     rec = make_receptor(300, radius=10.0, seed=0)
