@@ -312,6 +312,24 @@ dsdp_status dsdp_dock(dsdp_grids g, const dsdp_ligand *lig, int32_t n_chains, in
                       dsdp_pose *out, float *out_xyz, int32_t *n_out, dsdp_pose *chains_out,
                       dsdp_dock_stats *stats);
 
+/*
+ * dsdp_dock without a workspace argument and without any device allocation, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops and harnesses that forbid hipMalloc).  The workspace is a static
+ * array of DSDP_STATIC_SCRATCH_BYTES in the library, one per device (the current
+ * device at the call), held until the process ends; a dock whose
+ * dsdp_dock_workspace_bytes exceeds it fails with DSDP_ERR_UNSUPPORTED before
+ * any launch (about 1.7 KB per chain: some 4900 chains of a 32-atom ligand).
+ * Arguments, results and synchronisation are those of dsdp_dock, and the
+ * results are bitwise the same.  Every call on a device shares that device's
+ * array: calls that overlap on one device (from several threads or streams)
+ * race and must be serialised by the caller.
+ */
+#define DSDP_STATIC_SCRATCH_BYTES ((size_t)8 << 20)
+dsdp_status dsdp_dock_static(dsdp_grids g, const dsdp_ligand *lig, int32_t n_chains, int32_t n_steps, uint64_t seed,
+                             const dsdp_params *prm, int32_t top_k, void *stream, dsdp_pose *out, float *out_xyz,
+                             int32_t *n_out, dsdp_pose *chains_out, dsdp_dock_stats *stats);
+
 /* Device workspace bytes for dsdp_dock_batch over these ligands (0 on invalid input). */
 size_t dsdp_dock_batch_workspace_bytes(const dsdp_ligand *ligs, int32_t n_ligs, int32_t n_chains);
 

@@ -98,6 +98,10 @@ _SIGS = {
                               C.POINTER(dsdp_params), C.c_int32, _vp, C.c_size_t, _vp, C.POINTER(dsdp_pose),
                               C.POINTER(C.c_float), C.POINTER(C.c_int32), C.POINTER(dsdp_pose),
                               C.POINTER(dsdp_dock_stats)]),
+    "dsdp_dock_static": (C.c_int32, [_vp, C.POINTER(dsdp_ligand), C.c_int32, C.c_int32, C.c_uint64,
+                                     C.POINTER(dsdp_params), C.c_int32, _vp, C.POINTER(dsdp_pose),
+                                     C.POINTER(C.c_float), C.POINTER(C.c_int32), C.POINTER(dsdp_pose),
+                                     C.POINTER(dsdp_dock_stats)]),
     "dsdp_dock_batch_workspace_bytes": (C.c_size_t, [C.POINTER(dsdp_ligand), C.c_int32, C.c_int32]),
     "dsdp_dock_batch": (C.c_int32, [_vp, C.POINTER(dsdp_ligand), C.c_int32, C.c_int32, C.c_int32,
                                     C.POINTER(C.c_uint64), C.POINTER(dsdp_params), C.c_int32, C.c_int32, _vp,
@@ -306,6 +310,26 @@ def dsdp_dock(grids, lig, n_chains, n_steps, seed, top_k, d_ws, params=None, str
                            _stream(stream), out,
                            xyz.ctypes.data_as(C.POINTER(C.c_float)) if want_xyz else None, C.byref(n_out),
                            chains, C.byref(stats)))
+    n = n_out.value
+    return list(out)[:n], (xyz[:n] if want_xyz else None), (list(chains) if want_chains else None), stats
+
+
+DSDP_STATIC_SCRATCH_BYTES = 8 << 20   # the library's per-device static scratch (dsdp_dock_static)
+
+
+def dsdp_dock_static(grids, lig, n_chains, n_steps, seed, top_k, params=None, stream=None, want_xyz=True,
+                     want_chains=False):
+    """dsdp_dock on the library's static scratch (no workspace, no device allocation).
+    Returns what dsdp_dock returns."""
+    out = (dsdp_pose * max(top_k, 1))()
+    xyz = np.zeros((max(top_k, 1), lig.n_atoms, 3), dtype=np.float32) if want_xyz else None
+    n_out = C.c_int32(0)
+    chains = (dsdp_pose * n_chains)() if want_chains else None
+    stats = dsdp_dock_stats()
+    _check(lib().dsdp_dock_static(grids, C.byref(lig.c), int(n_chains), int(n_steps), C.c_uint64(int(seed)),
+                                  C.byref(params) if params is not None else None, int(top_k), _stream(stream), out,
+                                  xyz.ctypes.data_as(C.POINTER(C.c_float)) if want_xyz else None, C.byref(n_out),
+                                  chains, C.byref(stats)))
     n = n_out.value
     return list(out)[:n], (xyz[:n] if want_xyz else None), (list(chains) if want_chains else None), stats
 

@@ -990,10 +990,13 @@ dsdp_status dsdp_local_opt(dsdp_grids g, const dsdp_ligand *lig, const float *d_
     return DSDP_OK;
 }
 
-dsdp_status dsdp_dock(dsdp_grids g, const dsdp_ligand *lig, int32_t n_chains, int32_t n_steps, uint64_t seed,
+namespace {
+// dsdp_dock on a workspace that is either the caller's (d_ws, ws_bytes) or, with
+// d_ws NULL, the library's static scratch of this device.
+dsdp_status dock_impl(dsdp_grids g, const dsdp_ligand *lig, int32_t n_chains, int32_t n_steps, uint64_t seed,
                       const dsdp_params *prm, int32_t top_k, void *d_ws, size_t ws_bytes, void *stream,
                       dsdp_pose *out, float *out_xyz, int32_t *n_out, dsdp_pose *chains_out,
-                      dsdp_dock_stats *stats)
+                      dsdp_dock_stats *stats, bool static_ws)
 {
     if (n_out) *n_out = 0;
     if (!g) return fail(DSDP_ERR_INVALID_ARG, "grids handle is NULL");
@@ -1008,6 +1011,13 @@ dsdp_status dsdp_dock(dsdp_grids g, const dsdp_ligand *lig, int32_t n_chains, in
     st = prepare_ligand(lig, g->map_of_type, pl, intra_ctx(prm, n_chains, false));
     if (st) return st;
     const SearchWs w = search_ws(pl.h, n_chains);
+    if (static_ws) {
+        if (w.total > kStaticScratchBytes)
+            return fail(DSDP_ERR_UNSUPPORTED, "this dock needs %zu bytes of scratch; the static scratch holds %zu",
+                        w.total, kStaticScratchBytes);
+        HIP_TRY(static_scratch(&d_ws), "static scratch address");
+        ws_bytes = kStaticScratchBytes;
+    }
     if (!d_ws || ws_bytes < w.total) return fail(DSDP_ERR_WORKSPACE_TOO_SMALL, "workspace needs %zu bytes", w.total);
     if (!aligned256(d_ws)) return fail(DSDP_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
     const SearchParams sp = to_search(prm);
@@ -1097,6 +1107,24 @@ dsdp_status dsdp_dock(dsdp_grids g, const dsdp_ligand *lig, int32_t n_chains, in
         stats->search_ms = ms_search;
     }
     return DSDP_OK;
+}
+}  // namespace
+
+dsdp_status dsdp_dock(dsdp_grids g, const dsdp_ligand *lig, int32_t n_chains, int32_t n_steps, uint64_t seed,
+                      const dsdp_params *prm, int32_t top_k, void *d_ws, size_t ws_bytes, void *stream,
+                      dsdp_pose *out, float *out_xyz, int32_t *n_out, dsdp_pose *chains_out,
+                      dsdp_dock_stats *stats)
+{
+    return dock_impl(g, lig, n_chains, n_steps, seed, prm, top_k, d_ws, ws_bytes, stream, out, out_xyz, n_out,
+                     chains_out, stats, false);
+}
+
+dsdp_status dsdp_dock_static(dsdp_grids g, const dsdp_ligand *lig, int32_t n_chains, int32_t n_steps, uint64_t seed,
+                             const dsdp_params *prm, int32_t top_k, void *stream, dsdp_pose *out, float *out_xyz,
+                             int32_t *n_out, dsdp_pose *chains_out, dsdp_dock_stats *stats)
+{
+    return dock_impl(g, lig, n_chains, n_steps, seed, prm, top_k, nullptr, 0, stream, out, out_xyz, n_out,
+                     chains_out, stats, true);
 }
 
 size_t dsdp_dock_batch_workspace_bytes(const dsdp_ligand *ligs, int32_t n_ligs, int32_t n_chains)

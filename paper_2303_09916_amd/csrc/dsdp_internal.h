@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include "dsdp.h"
 #include <stdint.h>
 
 namespace dsdp {
@@ -186,6 +187,10 @@ hipError_t launch_rank(const float *records, const float4 *best_xyz, const RankS
 // slots per lane; 3 atom lists.
 constexpr int kNumClasses = 4;
 int search_class(const LigHeader &h);
+// Size of the per-device static scratch array behind dsdp_dock_static, and its
+// device address on the current device (looked up on first use per device).
+constexpr size_t kStaticScratchBytes = DSDP_STATIC_SCRATCH_BYTES;
+hipError_t static_scratch(void **ptr);
 // Top-k voxels of a score volume (dims x, y, z) and their single-linkage labels
 // (squared integer voxel offset <= lim links two voxels); k <= kMaxSitePoints.
 hipError_t launch_site_extract(const float *scores, const int *dims, int k, int lim, int *out_index, int *out_label,

@@ -15,6 +15,8 @@
 // depend on which wave, workgroup or launch runs it.
 #include "dsdp_internal.h"
 
+#include <mutex>
+
 namespace dsdp {
 namespace {
 
@@ -1764,4 +1766,36 @@ hipError_t launch_rank(const float *records, const float4 *best_xyz, const RankS
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- static scratch
+// Workspace of dsdp_dock_static, for callers that cannot allocate device memory.
+// One copy per device, held until the process ends; its host-side name is not a
+// device address, so host code uses only the address looked up below.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];   // device address of `scratch` per device, looked up once
+}  // namespace
+
+hipError_t static_scratch(void **ptr)
+{
+    *ptr = nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p || ((uintptr_t)p & 255u)) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
 }  // namespace dsdp
+
