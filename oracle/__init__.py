@@ -92,6 +92,7 @@ def lib():
         "orc_mutate": (C.c_int, [vp, C.POINTER(Params), C.c_uint64, C.c_uint32, C.c_uint32, _dp]),
         "orc_metropolis": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_double]),
         "orc_metropolis_uniform": (C.c_double, [C.c_uint64, C.c_uint32, C.c_uint32]),
+        "orc_metropolis_uniform": (C.c_double, [C.c_uint64, C.c_uint32, C.c_uint32]),
         "orc_chain": (None, [vp, vp, C.POINTER(Params), C.c_uint64, C.c_uint32, C.c_int, _dp, _dp, _lp]),
         "orc_dock": (None, [vp, vp, C.POINTER(Params), C.c_int, C.c_int, C.c_uint64, _dp, _dp, _lp, C.c_int]),
         "orc_max_threads": (C.c_int, []),
@@ -381,6 +382,11 @@ def shoemake(u1, u2, u3):
 
 def metropolis(e_new, e_old, T, u):
     return bool(lib().orc_metropolis(e_new, e_old, T, u))
+
+
+def metropolis_uniform(seed, chain, step):
+    """The uniform draw of a chain's Metropolis test at a step."""
+    return lib().orc_metropolis_uniform(int(seed), int(chain), int(step))
 
 
 def rmsd(a, b):

@@ -247,10 +247,11 @@ def test_local_opt_endpoint_spread_default(cfg1):
     Ee, _, _ = gc.gpu_eval(g, lig, Pg)
     assert np.all(Eg[:, 0] <= E0[:, 0] + 1e-6 * np.abs(E0[:, 0]))
     np.testing.assert_allclose(Ee[:, 0], Eg[:, 0], rtol=1e-6, atol=1e-6)
-    d_go, d_oo, e_g, e_o = [], [], [], []
+    d_go, d_oo, e_g, e_o, n_o = [], [], [], [], []
     for k in range(len(P)):
         p0 = P[k].astype(np.float64)
-        xo, Eo, _, _, _ = L.local_opt(ref, p0)
+        xo, Eo, _, no, _ = L.local_opt(ref, p0)
+        n_o.append(no)
         xp, Ep, _, _, _ = L.local_opt(ref, p0 * (1 + 1e-7 * rng.normal(size=p0.shape)))
         d_go.append(rmsd(L.fk(Pg[k].astype(np.float64)), L.fk(xo)))
         d_oo.append(rmsd(L.fk(xp), L.fk(xo)))
@@ -262,9 +263,12 @@ def test_local_opt_endpoint_spread_default(cfg1):
     ks_e = st.ks_2samp(e_g, e_o).pvalue
     log(f"[local opt K=20] gpu-vs-oracle RMSD median {np.median(d_go):.3g} p90 {np.quantile(d_go, .9):.3g}; "
         f"oracle-vs-perturbed median {np.median(d_oo):.3g} p90 {np.quantile(d_oo, .9):.3g}; KS p {ks_d:.3f}; "
-        f"endpoint energy KS p {ks_e:.3f}")
+        f"endpoint energy KS p {ks_e:.3f}; evaluations per start gpu {np.mean(Ng):.2f} oracle {np.mean(n_o):.2f}")
     assert np.median(d_go) <= 3 * np.median(d_oo) + 1e-3
     assert ks_e > 0.01
+    # the same work: the mean number of evaluations per local optimisation (every
+    # line-search trial counted) within 5 % of the oracle's over the same starts
+    assert abs(np.mean(Ng) / np.mean(n_o) - 1) <= 0.05
 
 
 @pytest.mark.parametrize("form", [1, 2])
