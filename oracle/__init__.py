@@ -48,9 +48,12 @@ def lib():
     global _LIB
     if _LIB is not None:
         return _LIB
-    path = os.path.join(_HERE, "liboracle.so")
-    if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(os.path.join(_HERE, "dsdp_oracle.c")):
-        _build.build()
+    # DSDP_ORACLE_LIB selects another build of the oracle (the host-sanitizer build)
+    path = os.environ.get("DSDP_ORACLE_LIB")
+    if not path:
+        path = os.path.join(_HERE, "liboracle.so")
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(os.path.join(_HERE, "dsdp_oracle.c")):
+            _build.build()
     L = C.CDLL(path)
     vp = C.c_void_p
     sig = {

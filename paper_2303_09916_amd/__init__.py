@@ -14,7 +14,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libdsdp.so")
+# DSDP_LIB selects another build of the library (the host-sanitizer build)
+LIB_PATH = os.environ.get("DSDP_LIB") or os.path.join(_HERE, "libdsdp.so")
 _LIB = None
 
 DSDP_OK = 0
