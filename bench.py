@@ -15,20 +15,33 @@ Printed JSON line (one):
                gradient where the method uses it, at the start point and the
                accepted trial);
   ligands_per_s docking requests completed per second (plain per-ligand form);
-  roofline     the search kernel (dominant): algorithmic FP32 flops per launch /
-               its average device time (HIP events on the call's stream), vs the
-               MI355X FP32 vector peak; also its gather bytes per second;
+  mc_chain_steps_per_s  Monte Carlo steps (mutation, local optimisation,
+               Metropolis) completed per second over all chains;
+  roofline     the search kernel (dominant), bound by its map gathers: the
+               algorithmic gather bytes per launch (evaluations x atoms x 128 B:
+               eight float4 corners per atom) / its average device time (HIP
+               events on the call's stream), against the gather roofline measured
+               on the same maps (dsdp_gather_probe with the device full of waves),
+               with the HBM peak beside it; also its VALU FP32 rate against the
+               non-packed vector peak (78.6 TFLOP/s) and the measured VALU busy
+               fraction from the committed counter profile;
+  grid_build   the grid-build stress workload (12000-atom receptor, 40 A box,
+               107^3 nodes x 9 maps): device time, receptor pair terms per second,
+               VALU rate, and the oracle's cell-list and brute-force builds;
   cpu_baseline the FP64 oracle on a bounded sample of the same workload, timed
-               on this host's cores (OpenMP over chains);
+               on this host's cores (OpenMP over chains), and single-threaded;
   batched      the batched workload (one receptor, uneven ligands of 10-60 atoms
                and 0-15 rotatable bonds, 128 chains x 1000 steps each): ligands/s
                of one dsdp_dock_batch call over all of them against ligands/s of
                plain per-ligand dsdp_dock calls on a sample of the same ligands;
   served       the served workload (16 receptors, Poisson arrivals, one ligand
                per request, 128 chains x 1000 steps): the serving scheduler fed
-               at the workload's 200 requests/s (saturation throughput, whether
-               the queue was stable) and at a rate below saturation; p50/p99
-               latency from scheduled arrival to result;
+               first at the workload's 200 requests/s, which overloads it (its
+               steady throughput is the capacity; the queue grows, so latency
+               there depends on the run length), then, as the headline, at 0.85 x
+               that capacity, where the queue is stable: p50/p99 latency from
+               scheduled arrival to result and ligands/s, on a stated sample of
+               the workload's 20000 requests;
   optimizers   the DSDP-shaped request docked with the paper's Barzilai-Borwein
                local optimiser and with BFGS: evaluations per step, throughput,
                best energies;
@@ -50,8 +63,10 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 METRIC = "pose evals/s + ligands docked/s on 1 GPU vs plain; p50/p99 dock latency"
-FP32_PEAK_TFLOPS = 157.3
+FP32_VALU_PEAK_TFLOPS = 78.6   # 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz (no packed FP32)
 HBM_PEAK_GBPS = 8000.0
+DEVICE_SIMDS = 1024
+CLOCK_GHZ = 2.4
 
 
 def flops_model(lig, n_pairs, D):
@@ -80,20 +95,22 @@ def flops_model(lig, n_pairs, D):
     return energy, gradient, 10 * D * D + 60
 
 
-def measured_traffic(mc_steps):
-    """HBM bytes per search launch from the committed counter summary, when it
-    was taken on this kernel source and this launch shape; else None."""
+def profile_value(name, key, source, mc_steps=None):
+    """A figure from a committed counter summary under profiles/, when it was
+    taken on this kernel source (and this launch shape); else None."""
     import hashlib
     try:
         kv = {}
-        for line in open(os.path.join(ROOT, "profiles", "tick_kernel_dsdp_shaped_traffic.md")):
+        for line in open(os.path.join(ROOT, "profiles", name)):
             if ":" in line and not line.startswith(("|", "#", " ")):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
-        src = open(os.path.join(ROOT, "paper_2303_09916_amd", "csrc", "search.hip"), "rb").read()
-        if kv.get("kernel_source_sha256") != hashlib.sha256(src).hexdigest() or mc_steps != 2000:
+        src = open(os.path.join(ROOT, "paper_2303_09916_amd", "csrc", source), "rb").read()
+        if kv.get("kernel_source_sha256") != hashlib.sha256(src).hexdigest():
             return None
-        return float(kv["traffic_bytes_per_launch"])
+        if mc_steps is not None and kv.get("mc_steps") not in (None, str(mc_steps)):
+            return None
+        return float(kv[key])
     except (OSError, KeyError, ValueError):
         return None
 
@@ -108,10 +125,11 @@ def cpu_model():
     return "unknown"
 
 
-def cpu_baseline(cfg, cpu_steps):
+def cpu_baseline(cfg, cpu_steps, single_chains=48, single_steps=50):
     """The FP64 oracle (as it stands) on a bounded sample of the same workload:
     every chain of the request, the first `cpu_steps` MC steps, OpenMP over
-    chains on this host's cores."""
+    chains on this host's cores; then single-threaded on the first
+    `single_chains` chains x `single_steps` steps."""
     import oracle as O
     rec, box, lig = cfg["receptor"], cfg["box"], cfg["ligands"][0]
     b32 = {"centre": np.asarray(box["centre"], np.float32).astype(np.float64),
@@ -125,10 +143,19 @@ def cpu_baseline(cfg, cpu_steps):
     _, _, cnt = Lo.dock(grid, cfg["n_chains"], cpu_steps, cfg["seed"])
     dt = time.perf_counter() - t0
     ev = int(cnt[:, 0].sum())
+    t0 = time.perf_counter()
+    _, _, cnt1 = Lo.dock(grid, single_chains, single_steps, cfg["seed"], n_threads=1)
+    dt1 = time.perf_counter() - t0
+    ev1 = int(cnt1[:, 0].sum())
     return {"value": ev / dt, "unit": "pose evals/s", "cores": O.max_threads(), "kind": "oracle",
             "sample": (f"{cfg['n_chains']} chains x first {cpu_steps} of {cfg['n_steps']} MC steps of the same "
                        f"request (FP64 C, -O2, OpenMP over chains): {ev} evaluations in {dt:.2f} s; its grid "
                        f"build took {t_grid:.2f} s"),
+            "mc_chain_steps_per_s": cfg["n_chains"] * cpu_steps / dt,
+            "single_thread": {"value": ev1 / dt1, "unit": "pose evals/s", "cores": 1,
+                              "mc_chain_steps_per_s": single_chains * single_steps / dt1,
+                              "sample": (f"the first {single_chains} chains x {single_steps} MC steps, one thread: "
+                                         f"{ev1} evaluations in {dt1:.2f} s")},
             "cpu_model": cpu_model(), "nproc": os.cpu_count()}
 
 
@@ -140,6 +167,8 @@ def make_inputs(args):
     from synth import make_config, request_ligand_job
     t0 = time.time()
     inp = {"cfg2": make_config(2)}
+    if args.grid_leg:
+        inp["cfg3"] = make_config(3)
     n_req = args.serve_requests + args.serve_requests_below if args.serve_requests > 0 else 0
     # a fork pool only when there is work for it, and never under a profiler,
     # which may have initialised the GPU in this process before main() runs
@@ -447,6 +476,104 @@ def serve_leg(D, torch, cfg, first, count, rate, slots, spt, label):
     return out
 
 
+def grid_flops_per_pair(T):
+    """Algorithmic FP32 operations of the grid build per node-atom pair within the
+    cutoff (FMA = 2, sqrt/exp/rcp = 1): the distance 10 (3 differences, squared
+    norm 5, sqrt, reciprocal), then per map type 40 (surface distance 1, the two
+    gauss terms with 2 exp 12, repulsion 4, hydrophobic and h-bond terms 8,
+    their derivative 8, force scale 1, energy and three gradient sums 7)."""
+    return 10 + 40 * T
+
+
+def grid_leg(D, torch, cfg, stream, reps=5, oracle=True):
+    """Grid-build stress: dsdp_build_grids on the 12000-atom receptor and 40 A box
+    (107^3 nodes x 9 XS maps).  Device time from HIP events on the call's stream
+    (the ~0.2 MB atom upload and the build kernel; the host's binning of the
+    atoms is timed in build_wall_ms with the rest of the call); algorithmic work = the
+    node-atom pairs within the 8 A cutoff (counted on the host with a k-d tree)
+    x map types.  The oracle builds the same maps with cell lists (all host
+    cores) and, on a two-plane slab of the box, by brute force over every atom
+    (per-node cost extrapolated to the box)."""
+    from scipy.spatial import cKDTree
+    rec, box, types = cfg["receptor"], cfg["box"], cfg["map_types"]
+    T = len(types)
+    n, origin = D.dsdp_grid_dims(box)
+    b32 = {"centre": np.asarray(box["centre"], np.float32).astype(np.float64),
+           "size": np.broadcast_to(np.float32(box["size"]), (3,)).astype(np.float64),
+           "spacing": float(np.float32(box["spacing"]))}
+    maps = torch.empty(D.dsdp_grids_bytes(box, T), dtype=torch.uint8, device="cuda")
+    gws = torch.empty(D.dsdp_build_grids_workspace_bytes(rec.n, box), dtype=torch.uint8, device="cuda")
+    g = D.dsdp_build_grids(rec.xyz, rec.types, box, types, maps, gws, stream)
+    D.dsdp_grids_release(g)
+    torch.cuda.synchronize()
+    dev, wall = [], []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = D.dsdp_build_grids(rec.xyz, rec.types, box, types, maps, gws, stream)
+        torch.cuda.synchronize()
+        wall.append((time.perf_counter() - t0) * 1e3)
+        D.dsdp_grids_release(g)
+        # device time: a spin kernel keeps the stream busy while the host bins the
+        # receptor, so the events bracket the atom upload and the build kernel only
+        torch.cuda._sleep(40_000_000)
+        e0.record(stream)
+        g = D.dsdp_build_grids(rec.xyz, rec.types, box, types, maps, gws, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        dev.append(e0.elapsed_time(e1))
+        D.dsdp_grids_release(g)
+    del maps, gws
+    h = float(np.float32(box["spacing"]))
+    axes = [origin[a] + h * np.arange(n[a]) for a in range(3)]
+    nodes = np.stack(np.meshgrid(*axes, indexing="ij"), -1).reshape(-1, 3)
+    pairs = int(cKDTree(nodes).count_neighbors(cKDTree(rec.xyz.astype(np.float64)), 8.0))
+    del nodes
+    ms = float(np.median(dev))
+    flops = pairs * grid_flops_per_pair(T)
+    out = {
+        "workload": (f"{rec.n}-atom synthetic receptor, {float(np.max(box['size'])):.0f} A box at "
+                     f"{box['spacing']} A ({n[0]}x{n[1]}x{n[2]} nodes x {T} XS maps, FP32), 8 A cutoff, cell lists; "
+                     f"no search"),
+        "nodes": int(np.prod(n)), "map_types": T, "receptor_atoms": int(rec.n),
+        "node_atom_pairs": pairs, "pair_terms": pairs * T,
+        "build_ms": ms, "build_wall_ms": float(np.median(wall)),
+        "pair_terms_per_s": pairs * T / (ms * 1e-3),
+        "maps_bytes": int(np.prod(n)) * T * 16,
+        "valu": {"flops_per_pair": grid_flops_per_pair(T), "achieved_TFLOPs": flops / (ms * 1e-3) / 1e12,
+                 "peak_TFLOPs": FP32_VALU_PEAK_TFLOPS,
+                 "frac": flops / (ms * 1e-3) / 1e12 / FP32_VALU_PEAK_TFLOPS,
+                 "valu_busy_frac": profile_value("grid_build_kernel_grid_stress.md", "valu_busy_frac",
+                                                 "grid_build.hip")},
+    }
+    print(f"[bench] grid build: {n[0]}^3 x {T} maps from {rec.n} atoms in {ms:.2f} ms (device), "
+          f"{pairs * T / (ms * 1e-3) / 1e9:.1f} G pair terms/s", file=sys.stderr, flush=True)
+    if oracle:
+        import oracle as O
+        t0 = time.perf_counter()
+        O.Grid(rec.xyz, rec.types, b32, types, with_mass=False)
+        t_cell = time.perf_counter() - t0
+        slab = dict(b32)
+        slab["size"] = np.array([b32["size"][0], b32["size"][1], b32["spacing"]])
+        ns, _ = O.grid_geometry(slab)
+        t0 = time.perf_counter()
+        O.Grid(rec.xyz, rec.types, slab, types, use_cells=False, with_mass=False)
+        t_slab = time.perf_counter() - t0
+        per_node = t_slab / float(np.prod(ns))
+        out["oracle"] = {
+            "cores": O.max_threads(),
+            "cell_list_s": t_cell,
+            "cell_list_pair_terms_per_s": pairs * T / t_cell,
+            "brute_force_s_extrapolated": per_node * float(np.prod(n)),
+            "brute_force_sample": (f"a {ns[0]}x{ns[1]}x{ns[2]}-node slab of the box, every receptor atom per node, "
+                                   f"{t_slab:.2f} s, scaled by node count"),
+        }
+        print(f"[bench] grid build oracle: cell lists {t_cell:.2f} s, brute force ~{per_node * np.prod(n):.0f} s "
+              f"({O.max_threads()} threads)", file=sys.stderr, flush=True)
+    return out
+
+
 def gather_probe(D, torch, rec, box, types, maps, gws, stream, n_chains):
     """Attainable rate of the search's map gathers (the eight corners of a cell
     per atom, around a ligand-sized cloud per wave) on the workload's maps: with
@@ -479,15 +606,18 @@ def main():
     ap.add_argument("--plain-sample", type=int, default=24, help="of these, docked one at a time for comparison")
     ap.add_argument("--serve-requests", type=int, default=480,
                     help="requests fed at the served workload's 200/s (0: skip the served legs)")
-    ap.add_argument("--serve-requests-below", type=int, default=240,
-                    help="requests fed at --serve-below x the measured saturation throughput")
-    ap.add_argument("--serve-below", type=float, default=0.7)
+    ap.add_argument("--serve-requests-below", type=int, default=1200,
+                    help="requests fed at --serve-below x the measured saturation throughput (the headline; "
+                         "20000 = the whole workload, about 8 minutes)")
+    ap.add_argument("--serve-below", type=float, default=0.85)
     ap.add_argument("--serve-slots", type=int, default=16384, help="scheduler chain slots")
     ap.add_argument("--serve-steps-per-tick", type=int, default=100)
     ap.add_argument("--table1-ligands", type=int, default=4,
                     help="systems per shape of the paper-shaped re-docking table (0: skip)")
     ap.add_argument("--no-optimizer-leg", action="store_true",
                     help="skip the Barzilai-Borwein vs BFGS and search-space comparisons")
+    ap.add_argument("--no-grid-leg", dest="grid_leg", action="store_false",
+                    help="skip the grid-build stress workload (12000 atoms, 107^3 x 9 maps)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one plain device copy of this size (for counter calibration)")
     args = ap.parse_args()
@@ -569,9 +699,10 @@ def main():
     lopts = stats.local_opts
     flops_launch = fe * evals_per_launch + fg * lopts * 21 + fb * lopts * 20
     fpe = flops_launch / evals_per_launch
-    achieved = flops_launch / avg_search_s / 1e12
+    valu_tflops = flops_launch / avg_search_s / 1e12
     gather_gbps = evals_per_launch * lig.n_atoms * 128 / avg_search_s / 1e9
-    traffic = measured_traffic(n_steps)
+    traffic = profile_value("tick_kernel_dsdp_shaped_traffic.md", "traffic_bytes_per_launch", "search.hip", n_steps)
+    valu_busy = profile_value("tick_kernel_dsdp_shaped_instruction_mix.md", "valu_busy_frac", "search.hip")
 
     out = {
         "metric": METRIC,
@@ -596,22 +727,26 @@ def main():
         "ligands_per_s": args.steps / elapsed,
         "dock_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "evals_per_step": evals_per_launch,
+        "evals_per_local_opt": evals_per_launch / stats.local_opts,
+        "mc_chain_steps_per_s": n_chains * n_steps * args.steps / elapsed,
         "best_e_total": best,
         "roofline": {
             "kernel": "tick_kernel",
-            "bound": "alu",
-            "achieved": achieved,
-            "peak": FP32_PEAK_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved / FP32_PEAK_TFLOPS,
+            "bound": "gather",
+            "achieved": gather_gbps,
+            "peak": probe["full_GBps"],
+            "unit": "GB/s",
+            "frac": gather_gbps / probe["full_GBps"],
             "traffic": traffic,
             "traffic_GBps": traffic / avg_search_s / 1e9 if traffic else None,
             "avg_launch_ms": avg_search_s * 1e3,
-            "flops_per_eval": fpe,
-            "gather_GBps": gather_gbps,
-            "gather_frac_of_hbm": gather_gbps / HBM_PEAK_GBPS,
+            "bytes_per_eval": lig.n_atoms * 128,
+            "evals_per_launch": evals_per_launch,
+            "hbm_peak_GBps": HBM_PEAK_GBPS,
+            "frac_of_hbm_peak": gather_gbps / HBM_PEAK_GBPS,
             "gather_probe": probe,
-            "gather_frac_of_probe": gather_gbps / probe["full_GBps"],
+            "valu": {"flops_per_eval": fpe, "achieved_TFLOPs": valu_tflops, "peak_TFLOPs": FP32_VALU_PEAK_TFLOPS,
+                     "frac": valu_tflops / FP32_VALU_PEAK_TFLOPS, "valu_busy_frac": valu_busy},
         },
         "cpu_baseline": None,
         "batched": None,
@@ -619,6 +754,8 @@ def main():
         "optimizers": None,
     }
 
+    if "cfg3" in inp:
+        out["grid_build"] = grid_leg(D, torch, inp["cfg3"], stream, oracle=not args.no_cpu_baseline)
     if not args.no_optimizer_leg:
         out["optimizers"] = optimizer_leg(D, torch, cfg, n_steps)
     if not args.no_optimizer_leg:
@@ -639,15 +776,19 @@ def main():
                                f"top {c5['top_k']}")}
         if args.serve_requests > 0:
             sat = serve_leg(D, torch, c5, 0, args.serve_requests, 200.0, args.serve_slots,
-                            args.serve_steps_per_tick, "200 req/s")
-            served["at_200_per_s"] = sat
-            served["saturation_ligands_per_s"] = sat["steady_ligands_per_s"] or sat["ligands_per_s"]
+                            args.serve_steps_per_tick, "200 req/s, overload")
+            served["overload_at_200_per_s"] = sat
+            served["capacity_ligands_per_s"] = sat["steady_ligands_per_s"] or sat["ligands_per_s"]
             if args.serve_requests_below > 0:
-                rate = args.serve_below * served["saturation_ligands_per_s"]
+                rate = args.serve_below * served["capacity_ligands_per_s"]
                 below = serve_leg(D, torch, c5, args.serve_requests, args.serve_requests_below, rate,
                                   args.serve_slots, args.serve_steps_per_tick,
-                                  f"{args.serve_below:.0%} of saturation")
-                served["below_saturation"] = below
+                                  f"{args.serve_below:.0%} of capacity")
+                served["stable"] = below
+                served["stable"]["fraction_of_capacity"] = args.serve_below
+                served["sample"] = (f"{args.serve_requests} + {args.serve_requests_below} of the workload's 20000 "
+                                    f"requests (the whole stream at a stable rate takes about "
+                                    f"{20000 / rate / 60:.0f} minutes; the default run stays within a few)")
         out["served"] = served
 
     if not args.no_cpu_baseline:

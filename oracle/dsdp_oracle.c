@@ -1293,11 +1293,11 @@ void orc_dock(const orc_ligand *L, const orc_grid *g, const orc_params *prm, int
 {
     const int nx = 7 + L->n_tors;
 #ifdef _OPENMP
-    if (n_threads > 0) omp_set_num_threads(n_threads);
+    const int nt = n_threads > 0 ? n_threads : omp_get_max_threads();
 #else
     (void)n_threads;
 #endif
-#pragma omp parallel for schedule(dynamic, 1)
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
     for (int c = 0; c < n_chains; c++)
         orc_chain(L, g, prm, seed, (uint32_t)c, n_steps, best_pose + (long)c * nx, best_e + 4L * c, counters + 3L * c);
 }
