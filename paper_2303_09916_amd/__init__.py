@@ -58,7 +58,13 @@ class dsdp_params(C.Structure):
                 ("ls_trials", C.c_int32), ("ls_shrink", C.c_float), ("armijo_c1", C.c_float),
                 ("waves_per_chain", C.c_int32), ("intra_form", C.c_int32), ("optimizer", C.c_int32),
                 ("bb_iters", C.c_int32), ("bb_step0", C.c_float), ("bb_step_max", C.c_float),
-                ("ls_min_decrease", C.c_float)]
+                ("ls_min_decrease", C.c_float), ("tune", C.c_int32)]
+
+
+class dsdp_tune_entry(C.Structure):
+    _fields_ = [("device", C.c_int32), ("chains", C.c_int32), ("shapes", C.c_int32), ("plan", C.c_int32),
+                ("intra_form_small", C.c_int32), ("intra_form_large", C.c_int32), ("waves_per_chain", C.c_int32),
+                ("trial_steps", C.c_int32), ("trial_ms", C.c_float * 6)]
 
 
 class dsdp_pose(C.Structure):
@@ -103,6 +109,8 @@ _SIGS = {
                                      C.POINTER(dsdp_params), C.c_int32, _vp, C.POINTER(dsdp_pose),
                                      C.POINTER(C.c_float), C.POINTER(C.c_int32), C.POINTER(dsdp_pose),
                                      C.POINTER(dsdp_dock_stats)]),
+    "dsdp_tune_entries": (C.c_int32, [C.POINTER(dsdp_tune_entry), C.c_int32]),
+    "dsdp_tune_reset": (None, []),
     "dsdp_dock_batch_workspace_bytes": (C.c_size_t, [C.POINTER(dsdp_ligand), C.c_int32, C.c_int32]),
     "dsdp_dock_batch": (C.c_int32, [_vp, C.POINTER(dsdp_ligand), C.c_int32, C.c_int32, C.c_int32,
                                     C.POINTER(C.c_uint64), C.POINTER(dsdp_params), C.c_int32, C.c_int32, _vp,
@@ -364,6 +372,23 @@ def dsdp_dock_batch(grids, ligs, n_chains, n_steps, seeds, top_k, d_ws, params=N
                                  _ptr(d_ws), _nbytes(d_ws), _stream(stream), out, n_out, C.byref(stats)))
     res = [[out[l * top_k + q] for q in range(n_out[l])] for l in range(n)]
     return res, stats
+
+
+def dsdp_tune_entries():
+    """The batched search's tuner cache on the current device, as dicts."""
+    n = lib().dsdp_tune_entries(None, 0)
+    arr = (dsdp_tune_entry * max(n, 1))()
+    n = min(n, lib().dsdp_tune_entries(arr, n))
+    out = []
+    for i in range(n):
+        e = {f: getattr(arr[i], f) for f, _ in dsdp_tune_entry._fields_}
+        e["trial_ms"] = list(e["trial_ms"])
+        out.append(e)
+    return out
+
+
+def dsdp_tune_reset():
+    lib().dsdp_tune_reset()
 
 
 def dsdp_grids_set_site(grids, points, radius=7.0):

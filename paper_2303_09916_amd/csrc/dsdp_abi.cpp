@@ -8,6 +8,7 @@
 #include "../../include/dsdp.h"
 #include "dsdp_internal.h"
 #include "dsdp_host.h"
+#include "tuner.h"
 
 #include <hip/hip_runtime.h>
 
@@ -450,7 +451,8 @@ dsdp_status check_params(const dsdp_params *p)
         p->bfgs_iters < 0 || p->ls_trials < 1 || !(p->ls_shrink > 0 && p->ls_shrink < 1) || !(p->armijo_c1 >= 0) ||
         p->waves_per_chain < 0 || p->waves_per_chain > 4 || p->intra_form < DSDP_INTRA_AUTO ||
         p->intra_form > DSDP_INTRA_ATOMS || (p->optimizer != DSDP_OPT_BFGS && p->optimizer != DSDP_OPT_BB) ||
-        p->bb_iters < 0 || !(p->bb_step0 > 0) || !(p->bb_step_max >= p->bb_step0) || !(p->ls_min_decrease >= 0))
+        p->bb_iters < 0 || !(p->bb_step0 > 0) || !(p->bb_step_max >= p->bb_step0) || !(p->ls_min_decrease >= 0) ||
+        (p->tune != 0 && p->tune != 1))
         return fail(DSDP_ERR_INVALID_ARG, "search parameter out of range");
     return DSDP_OK;
 }
@@ -683,6 +685,7 @@ void dsdp_params_default(dsdp_params *p)
     p->bb_step0 = 1e-2f;
     p->bb_step_max = 1.0f;
     p->ls_min_decrease = 1e-4f;
+    p->tune = 1;
 }
 
 dsdp_status dsdp_grid_dims(const dsdp_box *box, int32_t *n, float *origin)
@@ -990,6 +993,8 @@ dsdp_status dsdp_local_opt(dsdp_grids g, const dsdp_ligand *lig, const float *d_
     return DSDP_OK;
 }
 
+}  // extern "C"
+
 namespace {
 // dsdp_dock on a workspace that is either the caller's (d_ws, ws_bytes) or, with
 // d_ws NULL, the library's static scratch of this device.
@@ -1110,6 +1115,8 @@ dsdp_status dock_impl(dsdp_grids g, const dsdp_ligand *lig, int32_t n_chains, in
 }
 }  // namespace
 
+extern "C" {
+
 dsdp_status dsdp_dock(dsdp_grids g, const dsdp_ligand *lig, int32_t n_chains, int32_t n_steps, uint64_t seed,
                       const dsdp_params *prm, int32_t top_k, void *d_ws, size_t ws_bytes, void *stream,
                       dsdp_pose *out, float *out_xyz, int32_t *n_out, dsdp_pose *chains_out,
@@ -1127,6 +1134,192 @@ dsdp_status dsdp_dock_static(dsdp_grids g, const dsdp_ligand *lig, int32_t n_cha
                      chains_out, stats, true);
 }
 
+}  // extern "C"
+
+namespace {
+
+Tuner &tuner()
+{
+    static Tuner t;
+    return t;
+}
+
+constexpr int kTrialSteps = 3;   // MC steps of a tuner trial (every chain of the batch)
+
+// One launch of a batch plan: a kernel variant and wave count, the LDS its
+// largest member needs, its chains (contiguous in the task table).
+struct BatchGroup {
+    int cls = 0, waves = 1;
+    size_t lds = 0;
+    long first = 0, count = 0;
+};
+struct BatchPlan {
+    std::vector<BatchGroup> groups;
+    std::vector<int> order;                // ligands in task-table order
+    std::vector<const Prepared *> blob;    // each ligand's blob in the plan's layout
+};
+
+// The plan of candidate `c`: each ligand's layout from its pair class, one
+// launch per (kernel variant, waves); waves lowered for a launch whose largest
+// member does not fit the LDS.  Returns false when a ligand cannot run.
+bool tuned_plan(int c, const std::vector<Prepared> &pp, const std::vector<Prepared> &pa, int n_chains, BatchPlan &out)
+{
+    const Plan pl = plan(c);
+    out = BatchPlan();
+    const int n = (int)pp.size();
+    out.blob.resize((size_t)n);
+    std::map<std::pair<int, int>, std::vector<int>> groups;
+    for (int l = 0; l < n; l++) {
+        const Prepared &pr = plan_form(pl, pp[(size_t)l].h.n_pairs) == DSDP_INTRA_PAIRS ? pp[(size_t)l] : pa[(size_t)l];
+        out.blob[(size_t)l] = &pr;
+        groups[{search_class(pr.h), pl.waves}].push_back(l);
+    }
+    for (auto &kv : groups) {
+        BatchGroup b;
+        b.cls = kv.first.first;
+        b.waves = kv.first.second;
+        for (;;) {
+            b.lds = 0;
+            for (int l : kv.second) b.lds = std::max(b.lds, search_lds_bytes(out.blob[(size_t)l]->h, b.waves));
+            if (b.lds <= device_max_lds() || b.waves == 1) break;
+            b.waves--;
+        }
+        if (b.lds > device_max_lds()) return false;
+        // the largest ligands' chains first, so that the launch ends on short work
+        std::vector<int> mem = kv.second;
+        std::stable_sort(mem.begin(), mem.end(), [&](int a, int c) {
+            const LigHeader &ha = out.blob[(size_t)a]->h, &hc = out.blob[(size_t)c]->h;
+            return ha.n_atoms + ha.n_pairs > hc.n_atoms + hc.n_pairs;
+        });
+        b.first = (long)out.order.size() * n_chains;
+        b.count = (long)mem.size() * n_chains;
+        for (int l : mem) out.order.push_back(l);
+        out.groups.push_back(b);
+    }
+    return true;
+}
+
+// Upload a plan's host-written sections: blobs, tasks in the plan's order, the
+// grid view, ranking segments.
+dsdp_status upload_plan(const BatchPlan &bp, const dsdp_grids_s *g, const uint64_t *seeds, int n_chains, int n_steps,
+                        int top_k, const SearchWs &w, char *ws, hipStream_t s)
+{
+    const int n_ligs = (int)bp.blob.size();
+    HostImage img(w.host_end);
+    std::vector<uint32_t> blob_off((size_t)n_ligs);
+    size_t o = 0;
+    for (int l = 0; l < n_ligs; l++) {
+        blob_off[(size_t)l] = (uint32_t)o;
+        std::memcpy(img.at<uint32_t>(w.arena) + o, bp.blob[(size_t)l]->blob.data(), bp.blob[(size_t)l]->blob.size() * 4);
+        o += bp.blob[(size_t)l]->blob.size();
+    }
+    ChainTask *tasks = img.at<ChainTask>(w.tasks);
+    long ti = 0;
+    for (int l : bp.order)
+        for (int c = 0; c < n_chains; c++, ti++) {
+            ChainTask &t = tasks[ti];
+            t.blob_off = blob_off[(size_t)l];
+            t.blob_words = (uint32_t)bp.blob[(size_t)l]->h.total_words;
+            t.chain = (uint32_t)c;
+            t.n_steps = n_steps;
+            t.seed_lo = (uint32_t)seeds[l];
+            t.seed_hi = (uint32_t)(seeds[l] >> 32);
+            t.grid = 0;
+            t.slot = (int)((long)l * n_chains + c);
+            t.fresh = 0;
+        }
+    GridView view;
+    dsdp_status st = device_view(g, ws, w, img.bytes.data(), s, view);
+    if (st) return st;
+    *img.at<GridView>(w.grids) = view;
+    RankSeg *segs = img.at<RankSeg>(w.segs);
+    for (int l = 0; l < n_ligs; l++) {
+        segs[l].slot0 = l * n_chains;
+        segs[l].n_chains = n_chains;
+        segs[l].n_atoms = bp.blob[(size_t)l]->h.n_atoms;
+        segs[l].top_k = top_k;
+        segs[l].sel_off = l * (n_chains + 1);
+    }
+    HIP_TRY(hipMemcpyAsync(ws, img.bytes.data(), img.bytes.size(), hipMemcpyHostToDevice, s), "task upload");
+    HIP_TRY(hipStreamSynchronize(s), "task upload");
+    return DSDP_OK;
+}
+
+// Streams and events of a plan's branches (one stream per launch group), released
+// on every return path.
+struct Branches {
+    std::vector<hipStream_t> s;
+    std::vector<hipEvent_t> e;   // one per group, then the fork event
+    ~Branches()
+    {
+        for (auto x : s)
+            if (x) (void)hipStreamDestroy(x);
+        for (auto x : e)
+            if (x) (void)hipEventDestroy(x);
+    }
+    hipError_t make(int n)
+    {
+        s.assign((size_t)n, nullptr);
+        e.assign((size_t)n + 1, nullptr);
+        for (auto &x : s)
+            if (hipError_t r = hipStreamCreateWithFlags(&x, hipStreamNonBlocking)) return r;
+        for (auto &x : e)
+            if (hipError_t r = hipEventCreateWithFlags(&x, hipEventDisableTiming)) return r;
+        return hipSuccess;
+    }
+};
+
+// Ticks of a plan from stream `cs`: each group's ticks on its own branch (the
+// groups are independent, so one group's tail overlaps the others' work), joined
+// back on `cs`.  Used for trials and inside the batch's graph capture.
+hipError_t launch_plan(const BatchPlan &bp, Branches &br, const SearchWs &w, char *ws, const SearchParams &sp,
+                       int spt, int n_ticks, hipStream_t cs)
+{
+    const int nb = (int)bp.groups.size();
+    hipError_t le = hipEventRecord(br.e[(size_t)nb], cs);
+    for (int i = 0; i < nb && le == hipSuccess; i++) {
+        const BatchGroup &b = bp.groups[(size_t)i];
+        le = hipStreamWaitEvent(br.s[(size_t)i], br.e[(size_t)nb], 0);
+        for (int k = 0; k < n_ticks && le == hipSuccess; k++)
+            le = launch_tick(b.cls, b.waves, b.lds, (const uint32_t *)(ws + w.arena),
+                             (const ChainTask *)(ws + w.tasks) + b.first, (int)b.count,
+                             (const GridView *)(ws + w.grids), sp, spt, k == 0 ? 1 : 0, (float *)(ws + w.state),
+                             (float *)(ws + w.records), (float4 *)(ws + w.xyz), br.s[(size_t)i]);
+        if (le == hipSuccess) le = hipEventRecord(br.e[(size_t)i], br.s[(size_t)i]);
+        if (le == hipSuccess) le = hipStreamWaitEvent(cs, br.e[(size_t)i], 0);
+    }
+    return le;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t dsdp_tune_entries(dsdp_tune_entry *out, int32_t cap)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    const std::vector<TuneEntry> v = tuner().entries(dev);
+    for (int i = 0; out && i < cap && i < (int)v.size(); i++) {
+        dsdp_tune_entry &o = out[i];
+        const TuneEntry &e = v[(size_t)i];
+        std::memset(&o, 0, sizeof o);
+        o.device = e.key.device;
+        o.chains = e.key.chains;
+        o.shapes = (int32_t)e.key.shapes.size();
+        o.plan = e.pick;
+        const Plan p = plan(e.pick);
+        o.intra_form_small = p.form_small;
+        o.intra_form_large = p.form_large;
+        o.waves_per_chain = p.waves;
+        o.trial_steps = e.trial_steps;
+        for (int c = 0; c < DSDP_TUNE_PLANS && c < (int)e.trial_ms.size(); c++) o.trial_ms[c] = e.trial_ms[(size_t)c];
+    }
+    return (int32_t)v.size();
+}
+
+void dsdp_tune_reset(void) { tuner().clear(); }
+
 size_t dsdp_dock_batch_workspace_bytes(const dsdp_ligand *ligs, int32_t n_ligs, int32_t n_chains)
 {
     if (!ligs || n_ligs < 1 || n_chains < 1) return 0;
@@ -1136,6 +1329,7 @@ size_t dsdp_dock_batch_workspace_bytes(const dsdp_ligand *ligs, int32_t n_ligs, 
         if (lw == 0) return 0;
         words += lw;
     }
+    // blobs sized for either layout, so the tuner's plan does not change the size
     return search_ws(words, (long)n_ligs * n_chains, 1, n_ligs).total;
 }
 
@@ -1153,16 +1347,27 @@ dsdp_status dsdp_dock_batch(dsdp_grids g, const dsdp_ligand *ligs, int32_t n_lig
     if (top_k > 0 && (!out || !n_out)) return fail(DSDP_ERR_INVALID_ARG, "out/n_out is NULL");
     dsdp_status st = check_params(prm);
     if (st) return st;
-    std::vector<Prepared> pls((size_t)n_ligs);
+    dsdp_params def;
+    dsdp_params_default(&def);
+    const dsdp_params &pp = prm ? *prm : def;
+    const bool tune = pp.tune == 1 && pp.optimizer == DSDP_OPT_BFGS && pp.waves_per_chain == 0 &&
+                      pp.intra_form == DSDP_INTRA_AUTO && n_steps > 0;
+    // every ligand prepared in the fixed rule's layout (atom lists for a mixed
+    // launch, unless the caller fixed one) and, when tuning, in the other one
+    std::vector<Prepared> pls((size_t)n_ligs), alt(tune ? (size_t)n_ligs : 0);
     size_t words = 0;
     for (int l = 0; l < n_ligs; l++) {
-        st = prepare_ligand(&ligs[l], g->map_of_type, pls[l], intra_ctx(prm, (long)n_ligs * n_chains, true));
+        st = prepare_ligand(&ligs[l], g->map_of_type, pls[(size_t)l], intra_ctx(prm, (long)n_ligs * n_chains, true));
+        if (!st && tune) {
+            const int other = pls[(size_t)l].h.intra_form == kFormPairs ? DSDP_INTRA_ATOMS : DSDP_INTRA_PAIRS;
+            st = prepare_ligand(&ligs[l], g->map_of_type, alt[(size_t)l], IntraCtx{other});
+        }
         if (st) {
             char msg[600];
             snprintf(msg, sizeof msg, "ligand %d: %s", l, g_error.c_str());
             return fail(st, "%s", msg);
         }
-        words += (size_t)pls[l].h.total_words;
+        words += max_blob_words(&ligs[l]);
     }
     const long n_slots = (long)n_ligs * n_chains;
     const SearchWs w = search_ws(words, n_slots, 1, n_ligs);
@@ -1171,100 +1376,84 @@ dsdp_status dsdp_dock_batch(dsdp_grids g, const dsdp_ligand *ligs, int32_t n_lig
     const SearchParams sp = to_search(prm);
     hipStream_t s = (hipStream_t)stream;
     char *ws = (char *)d_ws;
-
-    // launch groups (kernel variant and LDS need); each group's chains are
-    // contiguous in the task table
-    struct Bucket {
-        int cls = 0, waves = 1;
-        size_t lds = 0;
-        long first = 0, count = 0;
-    };
-    std::vector<Bucket> buckets;
-    std::vector<int> order;
-    {
-        std::vector<const LigHeader *> hdr((size_t)n_ligs);
-        std::vector<long> ch((size_t)n_ligs, n_chains);
-        for (int l = 0; l < n_ligs; l++) hdr[l] = &pls[l].h;
-        std::vector<LaunchGroup> groups;
-        st = plan_groups(prm, hdr, ch, groups);
-        if (st) return st;
-        for (const LaunchGroup &g : groups) {
-            Bucket b;
-            b.cls = g.cls;
-            b.waves = g.waves;
-            b.lds = g.lds;
-            b.first = (long)order.size() * n_chains;
-            b.count = g.chains;
-            for (int l : g.members) order.push_back(l);
-            buckets.push_back(b);
-        }
-    }
-
-    HostImage img(w.host_end);
-    std::vector<uint32_t> blob_off((size_t)n_ligs);
-    {
-        size_t o = 0;
-        for (int l = 0; l < n_ligs; l++) {
-            blob_off[l] = (uint32_t)o;
-            std::memcpy(img.at<uint32_t>(w.arena) + o, pls[l].blob.data(), pls[l].blob.size() * 4);
-            o += pls[l].blob.size();
-        }
-    }
-    ChainTask *tasks = img.at<ChainTask>(w.tasks);
-    long ti = 0;
-    for (int l : order)
-        for (int c = 0; c < n_chains; c++, ti++) {
-            ChainTask &t = tasks[ti];
-            t.blob_off = blob_off[l];
-            t.blob_words = (uint32_t)pls[l].h.total_words;
-            t.chain = (uint32_t)c;
-            t.n_steps = n_steps;
-            t.seed_lo = (uint32_t)seeds[l];
-            t.seed_hi = (uint32_t)(seeds[l] >> 32);
-            t.grid = 0;
-            t.slot = (int)((long)l * n_chains + c);
-            t.fresh = 0;
-        }
-    {
-        GridView view;
-        st = device_view(g, ws, w, img.bytes.data(), s, view);
-        if (st) return st;
-        *img.at<GridView>(w.grids) = view;
-    }
-    RankSeg *segs = img.at<RankSeg>(w.segs);
-    for (int l = 0; l < n_ligs; l++) {
-        segs[l].slot0 = l * n_chains;
-        segs[l].n_chains = n_chains;
-        segs[l].n_atoms = pls[l].h.n_atoms;
-        segs[l].top_k = top_k;
-        segs[l].sel_off = l * (n_chains + 1);
-    }
-    HIP_TRY(hipMemcpyAsync(ws, img.bytes.data(), img.bytes.size(), hipMemcpyHostToDevice, s), "task upload");
-    HIP_TRY(hipStreamSynchronize(s), "task upload");
-
-    // ticks of steps_per_tick MC steps (0: about eight ticks), captured once as a
-    // graph: for each tick one launch per bucket, then the ranking
-    const int spt = steps_per_tick > 0 ? steps_per_tick : std::max(1, (n_steps + 7) / 8);
-    const int n_ticks = n_steps > 0 ? (n_steps + spt - 1) / spt : 1;
-    float *rec = (float *)(ws + w.records);
-    float4 *bxyz = (float4 *)(ws + w.xyz);
-    int *sel = (int *)(ws + w.sel);
     hipStream_t cs = nullptr;
     HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "stream");
     struct StreamGuard {
         hipStream_t s;
         ~StreamGuard() { (void)hipStreamDestroy(s); }
     } guard{cs};
+
+    BatchPlan bp;
+    if (tune) {
+        // the fixed rule's layout is in pls, the other in alt
+        const bool pls_atoms = pls[0].h.intra_form == kFormAtoms;
+        const std::vector<Prepared> &pp_pairs = pls_atoms ? alt : pls, &pp_atoms = pls_atoms ? pls : alt;
+        int dev = 0;
+        HIP_TRY(hipGetDevice(&dev), "device");
+        std::vector<ShapeBucket> shapes((size_t)n_ligs);
+        for (int l = 0; l < n_ligs; l++)
+            shapes[(size_t)l] = shape_bucket(pls[(size_t)l].h.n_atoms, pls[(size_t)l].h.n_pairs, 6 + pls[(size_t)l].h.n_tors);
+        const TuneKey key = tune_key(dev, n_chains, shapes);
+        dsdp_status mst = DSDP_OK;
+        // a trial: the candidate's plan over every chain of the batch for a few
+        // steps from fresh starts (the search afterwards starts afresh too)
+        auto measure = [&](int c) -> float {
+            BatchPlan tp;
+            if (mst || !tuned_plan(c, pp_pairs, pp_atoms, n_chains, tp)) return -1.f;
+            if ((mst = upload_plan(tp, g, seeds, n_chains, n_steps, top_k, w, ws, cs))) return -1.f;
+            Branches br;
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            float ms = -1.f;
+            bool ok = br.make((int)tp.groups.size()) == hipSuccess && hipEventCreate(&e0) == hipSuccess &&
+                      hipEventCreate(&e1) == hipSuccess && hipEventRecord(e0, cs) == hipSuccess &&
+                      launch_plan(tp, br, w, ws, sp, kTrialSteps, 1, cs) == hipSuccess &&
+                      hipEventRecord(e1, cs) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+                      hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+            if (!ok) mst = fail(DSDP_ERR_DEVICE, "tuner trial: %s", hipGetErrorString(hipGetLastError()));
+            return ok ? ms : -1.f;
+        };
+        int pick = 0;
+        const bool found = tuner().pick(key, measure, pick, n_slots, kTrialSteps);
+        if (mst) return mst;
+        if (!found || !tuned_plan(pick, pp_pairs, pp_atoms, n_chains, bp))
+            return fail(DSDP_ERR_UNSUPPORTED, "no launch plan fits the batch");
+    } else {
+        std::vector<const LigHeader *> hdr((size_t)n_ligs);
+        std::vector<long> ch((size_t)n_ligs, n_chains);
+        for (int l = 0; l < n_ligs; l++) hdr[(size_t)l] = &pls[(size_t)l].h;
+        std::vector<LaunchGroup> groups;
+        st = plan_groups(prm, hdr, ch, groups);
+        if (st) return st;
+        bp.blob.resize((size_t)n_ligs);
+        for (int l = 0; l < n_ligs; l++) bp.blob[(size_t)l] = &pls[(size_t)l];
+        for (const LaunchGroup &lg : groups) {
+            BatchGroup b;
+            b.cls = lg.cls;
+            b.waves = lg.waves;
+            b.lds = lg.lds;
+            b.first = (long)bp.order.size() * n_chains;
+            b.count = lg.chains;
+            for (int l : lg.members) bp.order.push_back(l);
+            bp.groups.push_back(b);
+        }
+    }
+    st = upload_plan(bp, g, seeds, n_chains, n_steps, top_k, w, ws, s);
+    if (st) return st;
+
+    // ticks of steps_per_tick MC steps (0: about eight ticks), captured once as a
+    // graph: each group's ticks on its own branch, then the ranking
+    const int spt = steps_per_tick > 0 ? steps_per_tick : std::max(1, (n_steps + 7) / 8);
+    const int n_ticks = n_steps > 0 ? (n_steps + spt - 1) / spt : 1;
+    float *rec = (float *)(ws + w.records);
+    float4 *bxyz = (float4 *)(ws + w.xyz);
+    int *sel = (int *)(ws + w.sel);
+    Branches br;
+    HIP_TRY(br.make((int)bp.groups.size()), "stream");
     hipGraph_t graph = nullptr;
     HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed), "graph capture");
-    hipError_t le = hipSuccess;
-    for (int k = 0; k < n_ticks && le == hipSuccess; k++)
-        for (const Bucket &b : buckets) {
-            le = launch_tick(b.cls, b.waves, b.lds, (const uint32_t *)(ws + w.arena),
-                             (const ChainTask *)(ws + w.tasks) + b.first, (int)b.count, (const GridView *)(ws + w.grids),
-                             sp, spt, k == 0 ? 1 : 0, (float *)(ws + w.state), rec, bxyz, cs);
-            if (le != hipSuccess) break;
-        }
+    hipError_t le = launch_plan(bp, br, w, ws, sp, spt, n_ticks, cs);
     if (le == hipSuccess) le = launch_rank(rec, bxyz, (const RankSeg *)(ws + w.segs), n_ligs, n_chains, sp.rmsd_cluster, sel, cs);
     hipError_t ce = hipStreamEndCapture(cs, &graph);
     if (le != hipSuccess) {
@@ -1300,7 +1489,8 @@ dsdp_status dsdp_dock_batch(dsdp_grids g, const dsdp_ligand *ligs, int32_t n_lig
         const int cnt = top_k > 0 ? sl[0] : 0;
         for (int q = 0; q < cnt; q++) {
             const int c = sl[1 + q];
-            fill_pose(&h_rec[((size_t)l * n_chains + c) * kRecWords], pls[l].h.n_tors, c, out[(size_t)l * top_k + q]);
+            fill_pose(&h_rec[((size_t)l * n_chains + c) * kRecWords], pls[(size_t)l].h.n_tors, c,
+                      out[(size_t)l * top_k + q]);
         }
         if (n_out) n_out[l] = cnt;
     }

@@ -64,3 +64,33 @@ def test_batch_mixed_wave_counts(site):
     b, _ = D.dsdp_dock_batch(g.handle, Ls, 16, 6, [5, 6, 7, 8], 4, ws, D.dsdp_params_default(waves_per_chain=3), 0)
     for x, y in zip(a, b):
         assert poses_bytes(x) == poses_bytes(y)
+
+
+def test_batch_tuner_picks_cached_and_results_unchanged(site):
+    """The tuner times its candidate launch plans once per batch make-up and
+    device, caches the fastest, and its pick changes nothing: tuned, fixed-rule
+    and alone give the same bits."""
+    import gpu_common as gc
+    import paper_2303_09916_amd as D
+    g = site
+    ligs = ligands()
+    Ls = [D.Ligand.from_synth(l) for l in ligs]
+    seeds = [2000 + k for k in range(len(ligs))]
+    ws = gc.dev_bytes(g.torch, D.dsdp_dock_batch_workspace_bytes(Ls, 16))
+    D.dsdp_tune_reset()
+    assert D.dsdp_tune_entries() == []
+    a, _ = D.dsdp_dock_batch(g.handle, Ls, 16, 6, seeds, 4, ws)
+    picks = D.dsdp_tune_entries()
+    print(f"[tuner] {picks}", flush=True)
+    assert len(picks) == 1
+    e = picks[0]
+    assert e["chains"] == 16 and e["shapes"] >= 3 and 0 <= e["plan"] < 6
+    assert e["trial_ms"][e["plan"]] == min(t for t in e["trial_ms"] if t >= 0) and e["trial_steps"] > 0
+    assert e["intra_form_small"] in (1, 2) and e["intra_form_large"] in (1, 2) and e["waves_per_chain"] in (1, 2)
+    b, _ = D.dsdp_dock_batch(g.handle, Ls, 16, 6, seeds, 4, ws)
+    assert D.dsdp_tune_entries() == picks          # cached: nothing measured again
+    c, _ = D.dsdp_dock_batch(g.handle, Ls, 16, 6, seeds, 4, ws, D.dsdp_params_default(tune=0))
+    for k in range(len(ligs)):
+        assert poses_bytes(a[k]) == poses_bytes(b[k]) == poses_bytes(c[k])
+        alone, _, _, _ = gc.gpu_dock(g, ligs[k], 16, 6, seeds[k], 4)
+        assert poses_bytes(a[k]) == poses_bytes(alone)
