@@ -442,7 +442,12 @@ def serve_leg(D, torch, cfg, first, count, rate, slots, spt, label):
         max_queued = 0
         queued_at_last_arrival = None
         t0 = time.perf_counter()
+        t_report = t0
         while done < count:
+            if time.perf_counter() - t_report > 30.0:
+                t_report = time.perf_counter()
+                print(f"[bench] served ({label}): {done} of {count} requests done after {t_report - t0:.0f}s",
+                      file=sys.stderr, flush=True)
             now = time.perf_counter() - t0
             while nxt < count and arr[nxt] <= now:
                 t = D.dsdp_sched_submit(h, rids[target[nxt]], Ls[nxt], n_chains, n_steps, 1 + first + nxt, top_k)

@@ -287,7 +287,10 @@ dsdp_status dsdp_eval_poses(dsdp_grids g, const dsdp_ligand *lig, const float *d
 
 /*
  * One BFGS local optimisation per given pose (the search kernel's local
- * optimiser; Armijo backtracking, inverse-BFGS update when y.s > 0).
+ * optimiser, Section 2 "Binding pose search", second modification, which names
+ * Vina's BFGS, ref. [36]; Armijo backtracking on the energy change with a
+ * minimum decrease, inverse-BFGS update when y.s > 0; or the paper's
+ * Barzilai-Borwein method when prm->optimizer says so).
  *   d_poses_in / d_poses_out  [n_poses][7 + Nt] device (may alias);
  *   d_energy                  [n_poses][4] device out (as dsdp_eval_poses);
  *   d_evals                   nullable [n_poses] int32 device out: evaluations used.
@@ -298,7 +301,10 @@ dsdp_status dsdp_local_opt(dsdp_grids g, const dsdp_ligand *lig, const float *d_
                            void *d_ws, size_t ws_bytes, void *stream);
 
 /*
- * Dock one ligand: n_chains independent Monte Carlo chains of n_steps steps
+ * Dock one ligand (Section 2: the search runs many short Monte Carlo copies in
+ * parallel, parallelisation paragraph, with the grid maps and local optimiser of
+ * "Binding pose search"; ranked poses as in Figure 4): n_chains independent
+ * Monte Carlo chains of n_steps steps
  * (mutate, BFGS local optimisation, Metropolis), each chain's random numbers
  * drawn from Philox4x32-10 keyed by `seed` with counters (chain, step, stream,
  * block), then ranking by e_total and greedy heavy-atom RMSD clustering
