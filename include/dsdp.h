@@ -104,9 +104,11 @@ typedef struct {
     int32_t ls_trials;       /* Armijo trials per iteration (10) */
     float ls_shrink;         /* step shrink factor per failed trial (0.1) */
     float armijo_c1;         /* sufficient-decrease constant (1e-4) */
-    int32_t waves_per_chain; /* wavefronts per chain, 1..4: that many line-search trials are
-                                evaluated at once; results do not depend on it.  0 = chosen
-                                by the library from the chain count and the device (0) */
+    int32_t waves_per_chain; /* wavefronts per chain, 1..4: with BFGS that many line-search
+                                trials are evaluated at once; with Barzilai-Borwein and pair
+                                lists each evaluation's pairs are spread over them (atom lists:
+                                one wave works).  Results do not depend on it.  0 = chosen by
+                                the library from the chain count and the device (0) */
     int32_t intra_form;      /* layout of the intra-ligand term on the device: DSDP_INTRA_AUTO
                                 (chosen by the library for the launch), DSDP_INTRA_PAIRS or
                                 DSDP_INTRA_ATOMS.  Results do not depend on it (0) */

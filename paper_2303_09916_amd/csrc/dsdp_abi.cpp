@@ -558,8 +558,10 @@ size_t device_max_lds()
 dsdp_status pick_waves(const dsdp_params *prm, const LigHeader &h, int n_chains, int &waves)
 {
     int w = (prm && prm->waves_per_chain > 0) ? prm->waves_per_chain : 0;
-    // Barzilai-Borwein evaluates one point per iteration: more waves would idle
-    if (w == 0 && prm && prm->optimizer == DSDP_OPT_BB) w = 1;
+    // Barzilai-Borwein evaluates one point per iteration: with atom lists one
+    // wave does all of it (more would idle); pair lists spread its pairs over
+    // the waves
+    if (w == 0 && prm && prm->optimizer == DSDP_OPT_BB && h.intra_form != kFormPairs) w = 1;
     if (w == 0) {
         const long slots = 8L * device_cus();
         w = (int)std::max(1L, std::min(4L, slots / std::max(1, n_chains)));

@@ -77,6 +77,14 @@ __device__ __forceinline__ float wave_scan(float v)
     return v;
 }
 
+// The value of lane l ^ 32 for lanes 0-31 (lanes 32-63 get lane l - 32's): one
+// v_permlane32_swap, no LDS.
+__device__ __forceinline__ float other_half(float v)
+{
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(lane_id() < 32 ? r[1] : r[0]);
+}
+
 // ---------------------------------------------------------------- Philox4x32-10
 // Salmon et al., SC'11: ten rounds of two 32x32->64 multiplies, Weyl key bumps.
 __device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1)
@@ -309,8 +317,8 @@ struct LigL {
 // Scratch of one pose evaluation (one per wave).
 struct WaveL {
     float4 *xyz;
-    float4 *pf;            // [np + 1] force of each pair on its first atom; slot np stays 0
-    float *pe;             // [np + 1] the same pairs' energies, densely (spread over the LDS banks)
+    float4 *pf;            // [np + 1] force of each pair on its first atom (xyz) and its energy
+                           // (w); slot np stays 0
     float4 *af, *at;       // [64]: per lane, the forces the energy half leaves for the gradient
                            // half, then prefix sums over atoms of force and of torque about the
                            // root origin
@@ -332,12 +340,13 @@ struct ChainL {
 
 constexpr int kMaxWaves = 4;     // waves per chain (concurrent line-search trials)
 constexpr int kMiscGp = 40;      // slot of g.p in misc
+constexpr int kMiscBBa = 41;     // slot of the Barzilai-Borwein step length in misc
 constexpr int kOptBB = 1;        // SearchParams::optimizer value of Barzilai-Borwein
 
 __host__ __device__ inline int rup4(int v) { return (v + 3) & ~3; }
 
 struct Layout {
-    int xyz, pf, pe, af, at, R, trial, gt, wave_words;     // per-wave offsets
+    int xyz, pf, af, at, R, trial, gt, wave_words;     // per-wave offsets
     int vec, H, hs, pose, et, misc, chain_words, Dp, NXp;     // per-chain offsets
 };
 __host__ __device__ inline Layout make_layout(int na, int nf, int np, int D, int nx)
@@ -350,8 +359,7 @@ __host__ __device__ inline Layout make_layout(int na, int nf, int np, int D, int
     // np = -1: no pair-force scratch (atom lists); else the pairs, the zero slot
     // np, and entries up to a whole group of two 64-pair slots
     c.pf = w; w += np < 0 ? 0 : 4 * max(np + 1, 128 * ((np + 127) / 128));
-    c.pe = w; w += np < 0 ? 0 : rup4(max(np + 1, 128 * ((np + 127) / 128)));
-    c.af = w; w += 4 * 64;   // one entry per lane (the energy half leaves its forces here)
+    c.af = w; w += 4 * 64;   // one entry per lane (the energy half leaves its total forces here)
     c.at = w; w += 4 * 64;
     c.R = w; w += 16 * nf;
     c.trial = w; w += c.NXp;
@@ -373,7 +381,6 @@ __device__ inline WaveL make_wave(float *base, const Layout &c)
     WaveL S;
     S.xyz = reinterpret_cast<float4 *>(base + c.xyz);
     S.pf = reinterpret_cast<float4 *>(base + c.pf);
-    S.pe = base + c.pe;
     S.af = reinterpret_cast<float4 *>(base + c.af);
     S.at = reinterpret_cast<float4 *>(base + c.at);
     S.R = reinterpret_cast<float4 *>(base + c.R);
@@ -635,9 +642,18 @@ __device__ inline float site_term(const GridView &G, const float *pose, float wa
 // gradient is left to eval_gradient (a line-search trial needs only the energy
 // unless it is accepted); what it needs stays in the wave's scratch,
 // coordinates in S.xyz.
+//
+// With parts > 1 (pair lists only), `parts` waves of the workgroup evaluate one
+// pose together: every wave forms the frames and coordinates, wave `part`
+// evaluates the groups of pair slots numbered part, part + parts, ... and stores
+// their terms into pf_shared (wave 0's pair array), and after a workgroup
+// barrier wave 0 alone gathers them and finishes; the other waves return zeros.
+// Every pair term and every sum is the one a single wave forms, so the result
+// does not depend on `parts`.  All `parts` waves must make the call.
 template <int PPL, int NBW>
 __device__ Energy eval_energy(const LigL &L, const WaveL &S, const IntraRegs<PPL, NBW> &pr, const GridView &G,
-                              const float *pose, float wall_slope)
+                              const float *pose, float wall_slope, int part = 0, int parts = 1,
+                              float4 *pf_shared = nullptr)
 {
     const int lane = lane_id();
 
@@ -661,7 +677,9 @@ __device__ Energy eval_energy(const LigL &L, const WaveL &S, const IntraRegs<PPL
                         o.y + r1.x * loc.x + r1.y * loc.y + r1.z * loc.z,
                         o.z + r2.x * loc.x + r2.y * loc.y + r2.z * loc.z);
         S.xyz[lane] = make_float4(x.x, x.y, x.z, PPL == 0 ? L.arad[lane] : 0.f);
-
+    }
+    if (lane < L.na && part == 0) {
+        const float4 loc = pr.loc;
         // wall and clamping: a coordinate outside the box is clamped onto the face;
         // the atom pays wall_slope per Angstrom outside and the map gradient along
         // a clamped axis is dropped (selected per axis, no branches)
@@ -722,9 +740,10 @@ __device__ Energy eval_energy(const LigL &L, const WaveL &S, const IntraRegs<PPL
         // without branches (out-of-cutoff and padding pairs select 0)
         const int slots = (L.np + 63) >> 6;
         constexpr int kGroup = 2;
+        float4 *const pf = parts > 1 ? pf_shared : S.pf;
 #pragma unroll
         for (int g = 0; g < PPL; g += kGroup) {
-            if (g < slots) {
+            if (g < slots && (g / kGroup) % parts == part) {
                 float4 xi[kGroup], xj[kGroup];
 #pragma unroll
                 for (int k = 0; k < kGroup; k++) {
@@ -745,13 +764,11 @@ __device__ Energy eval_energy(const LigL &L, const WaveL &S, const IntraRegs<PPL
                     if constexpr (PPL == 8) {
                         // a padding lane (both indices 0, so dx = dy = dz = +0)
                         // stores +0 into its own entry, at or past the zero slot np
-                        // (the arrays are padded to whole groups): no branch, so the
+                        // (the array is padded to whole groups): no branch, so the
                         // group's pair terms interleave
-                        S.pf[lane + 64 * (g + k)] = v;
-                        S.pe[lane + 64 * (g + k)] = ep;
+                        pf[lane + 64 * (g + k)] = v;
                     } else if (!none) {
-                        S.pf[lane + 64 * (g + k)] = v;   // fewer registers live for the larger lists
-                        S.pe[lane + 64 * (g + k)] = ep;
+                        pf[lane + 64 * (g + k)] = v;   // fewer registers live for the larger lists
                     }
                 }
             }
@@ -801,7 +818,7 @@ __device__ Energy eval_energy(const LigL &L, const WaveL &S, const IntraRegs<PPL
     // (5) inter-molecular energy and force from the gathered corners: eq. 2 for
     //     the energy and eq. 4 (the same weights on the stored gradients)
     if constexpr (PPL > 0) {
-        if (lane < L.na)
+        if (lane < L.na && part == 0)
             trilinear(c000, c100, c010, c110, c001, c101, c011, c111, px, py, pz, clx, cly, clz, wg, w_atom, e_atom,
                       f);
     }
@@ -815,37 +832,63 @@ __device__ Energy eval_energy(const LigL &L, const WaveL &S, const IntraRegs<PPL
         e_inter += e;
         wall += e;
     }
+    if (parts > 1) {
+        __syncthreads();   // every part's pair terms are stored
+        if (part != 0) return Energy{0.f, 0.f, 0.f, 0.f};
+    }
     wave_sync();
 
-    // (6e) the intra energy, summed per atom lane in the order of its list (pair
-    //      lists: the pair energies stored with the forces, counted at the
-    //      pair's first atom; atom lists: the lane's own sum)
+    // (6) per atom lane, in the order of its list, the intra energies (at the
+    //     pair's first atom) and forces of its pairs: pair lists gather the
+    //     stored entries (force xyz and energy w, eight entries per 16-byte list
+    //     chunk), atom lists have both sums in registers.  Two lanes per atom
+    //     when there are at most 32 atoms; the atom's total force (inter-
+    //     molecular plus intra) is left in the wave's scratch for the gradient
+    //     half, so a trial's gradient starts from it if the trial is accepted.
+    float3 fp = make_float3(0.f, 0.f, 0.f);
     if constexpr (PPL > 0) {
         constexpr int kRegChunks = PPL == 8 ? 2 : 0;
         if constexpr (kRegChunks > 0) {
-            float v[16];
+            // eight pairs per lane: the first two chunks' lists are in registers
+            // and their sixteen loads are issued together
+            float4 v[16];
 #pragma unroll
-            for (int t = 0; t < 16; t++) v[t] = S.pe[pl_entry(pr.pl, t) & 0x7fffu];
+            for (int t = 0; t < 16; t++) v[t] = S.pf[pl_entry(pr.pl, t) & 0x7fffu];
 #pragma unroll
             for (int t = 0; t < 16; t++) {
                 if (t == 8 && L.n_chunks < 2) break;
-                e_lane += (pl_entry(pr.pl, t) & 0x8000u) ? 0.f : v[t];
+                // sg * v is exact, so this rounds once, as fp +/- v does
+                const bool second = (pl_entry(pr.pl, t) & 0x8000u) != 0;
+                const float sg = second ? -1.f : 1.f;
+                fp = fp + sg * f3(v[t]);
+                e_lane += second ? 0.f : v[t].w;
             }
         }
         for (int c = kRegChunks; c < L.n_chunks; c++) {
             const uint4 q = L.plist[c * 64 + lane];
-            float v[8];
+            float4 v[8];
 #pragma unroll
-            for (int t = 0; t < 8; t++) v[t] = S.pe[chunk_entry(q, t) & 0x7fffu];
+            for (int t = 0; t < 8; t++) v[t] = S.pf[chunk_entry(q, t) & 0x7fffu];
 #pragma unroll
-            for (int t = 0; t < 8; t++) e_lane += (chunk_entry(q, t) & 0x8000u) ? 0.f : v[t];
+            for (int t = 0; t < 8; t++) {
+                const bool second = (chunk_entry(q, t) & 0x8000u) != 0;
+                const float sg = second ? -1.f : 1.f;
+                fp = fp + sg * f3(v[t]);
+                e_lane += second ? 0.f : v[t].w;
+            }
         }
+    } else {
+        fp = fnb;
     }
+    if (L.lanes_per_atom == 2) {
+        // lane l < 32 adds lane l + 32's share (one cross-half swap per component)
+        fp.x += other_half(fp.x);
+        fp.y += other_half(fp.y);
+        fp.z += other_half(fp.z);
+    }
+    if (lane < L.na) f = f + fp;
     const float e_intra = wave_sum(e_lane);
-    // for the gradient half: every lane's inter-molecular force (zero past the
-    // atoms) and, for atom lists, its share of the intra force
     S.af[lane] = make_float4(f.x, f.y, f.z, 0.f);
-    if constexpr (PPL == 0) S.at[lane] = make_float4(fnb.x, fnb.y, fnb.z, 0.f);
     Energy out;
     out.inter = e_inter;
     out.intra = e_intra;
@@ -864,52 +907,9 @@ __device__ void eval_gradient(const LigL &L, const WaveL &S, const IntraRegs<PPL
     const int lane = lane_id();
     const float4 xl = S.xyz[lane < L.na ? lane : 0];
     const float3 x = lane < L.na ? f3(xl) : make_float3(0.f, 0.f, 0.f);
-    float3 f = f3(S.af[lane]);
+    const float3 f = f3(S.af[lane]);   // the atom's total force from the energy half
     float3 g_site = make_float3(0.f, 0.f, 0.f);
     if (G.n_site > 0) site_term(G, pose, wall_slope, g_site);
-    // (6g) pair lists: pair forces gathered per atom from its list (8 entries per
-    //      16-byte chunk), in list order; atom lists: the lane's own sum.  Two
-    //      lanes per atom when there are at most 32 atoms.  Then the atom's total
-    //      force
-    {
-        float3 fp = make_float3(0.f, 0.f, 0.f);
-        if constexpr (PPL > 0) {
-            // eight pairs per lane: the first two chunks' lists are in registers
-            // and their sixteen loads are issued together
-            constexpr int kRegChunks = PPL == 8 ? 2 : 0;
-            if constexpr (kRegChunks > 0) {
-                float4 v[16];
-#pragma unroll
-                for (int t = 0; t < 16; t++) v[t] = S.pf[pl_entry(pr.pl, t) & 0x7fffu];
-#pragma unroll
-                for (int t = 0; t < 16; t++) {
-                    if (t == 8 && L.n_chunks < 2) break;
-                    // sg * v is exact, so this rounds once, as fp +/- v does
-                    const float sg = (pl_entry(pr.pl, t) & 0x8000u) ? -1.f : 1.f;
-                    fp = fp + sg * f3(v[t]);
-                }
-            }
-            for (int c = kRegChunks; c < L.n_chunks; c++) {
-                const uint4 q = L.plist[c * 64 + lane];
-                float4 v[8];
-#pragma unroll
-                for (int t = 0; t < 8; t++) v[t] = S.pf[chunk_entry(q, t) & 0x7fffu];
-#pragma unroll
-                for (int t = 0; t < 8; t++) {
-                    const float sg = (chunk_entry(q, t) & 0x8000u) ? -1.f : 1.f;
-                    fp = fp + sg * f3(v[t]);
-                }
-            }
-        } else {
-            fp = f3(S.at[lane]);
-        }
-        if (L.lanes_per_atom == 2) {
-            fp.x += __shfl_xor(fp.x, 32, 64);
-            fp.y += __shfl_xor(fp.y, 32, 64);
-            fp.z += __shfl_xor(fp.z, 32, 64);
-        }
-        if (lane < L.na) f = f + fp;
-    }
 
     // (7) gradient in the tangent coordinates.  With the root origin p, atom
     //     forces f_a and t_a = (x_a - p) x f_a, summed as lane prefix sums in
@@ -1143,8 +1143,11 @@ __device__ inline float bfgs_step_any(const ChainL &C, int D, int nq, bool upd, 
 
 // Local optimisation of the chain's pose x (LDS, in place), run by all W waves of
 // the workgroup together: BFGS with Armijo backtracking, or the Barzilai-Borwein
-// gradient method (no line search: wave 0 alone evaluates one point per
-// iteration; the lowest-energy iterate is returned).
+// gradient method (no line search: one point per iteration, the lowest-energy
+// iterate is returned).  Barzilai-Borwein with pair lists spreads each
+// evaluation's intra-ligand pairs over the W waves (eval_energy with parts = W;
+// wave 0 takes the gradient and the step); with atom lists wave 0 works alone,
+// since splitting an atom's list would change the order of its sums.
 //
 // BFGS with Armijo backtracking on the chain's pose x (LDS, in place), run by all
 // W waves of the workgroup together.  The line search evaluates the energies of
@@ -1164,6 +1167,8 @@ __device__ Energy local_opt_group(const LigL &L, const Layout &lay, float *wave_
     const int lane = lane_id(), w = wave_id(), D = L.D;
     const WaveL S = make_wave(wave_base + w * lay.wave_words, lay);
     const bool bb = P.optimizer == kOptBB;
+    const bool split = bb && PPL > 0 && W > 1;   // every wave takes part in each evaluation
+    float4 *const pf0 = make_wave(wave_base, lay).pf;
     const int iters = bb ? P.bb_iters : P.bfgs_iters;
     Energy Ex, Eb;
     float gp = 0.f;
@@ -1181,10 +1186,10 @@ __device__ Energy local_opt_group(const LigL &L, const Layout &lay, float *wave_
     for (;;) {
         bool active;
         if (t0 < 0) {
-            active = (w == 0);
+            active = split || w == 0;
             if (active && lane < L.nx) S.trial[lane] = x[lane];
         } else if (bb) {
-            active = (w == 0);
+            active = split || w == 0;
             if (active) pose_step(L, x, bb_a, C.p, S.trial);
         } else {
             active = t0 + w < P.ls_trials;
@@ -1196,7 +1201,8 @@ __device__ Energy local_opt_group(const LigL &L, const Layout &lay, float *wave_
         }
         if (active) {
             wave_sync();
-            put_energy(C.et + 4 * w, eval_energy(L, S, pr, G, S.trial, P.wall_slope));
+            const Energy e = eval_energy(L, S, pr, G, S.trial, P.wall_slope, split ? w : 0, split ? W : 1, pf0);
+            if (!split || w == 0) put_energy(C.et + 4 * w, e);
         }
         __syncthreads();
         // the one evaluation of this round whose gradient is needed: wave 0's for
@@ -1272,6 +1278,7 @@ __device__ Energy local_opt_group(const LigL &L, const Layout &lay, float *wave_
                 }
                 const float sy = wave_sum(sl * yl), ss = wave_sum(sl * sl);
                 bb_a = sy > 0.f ? fminf(ss / sy, P.bb_step_max) : P.bb_step0;
+                if (split && lane == 0) C.misc[kMiscBBa] = bb_a;
                 if (lane < L.nx) {
                     x[lane] = S.trial[lane];
                     if (En.total < Eb.total) xb[lane] = S.trial[lane];
@@ -1331,6 +1338,7 @@ __device__ Energy local_opt_group(const LigL &L, const Layout &lay, float *wave_
         }
         __syncthreads();
         gp = C.misc[kMiscGp];
+        if (split && t0 >= 0) bb_a = C.misc[kMiscBBa];
         t0 = 0;
         alpha0 = 1.f;
     }
@@ -1367,7 +1375,6 @@ __global__ __launch_bounds__(256) void eval_kernel(const uint32_t *__restrict__ 
     const int lane = lane_id();
     if (PPL > 0 && lane == 0) {
         S.pf[L.np] = make_float4(0.f, 0.f, 0.f, 0.f);
-        S.pe[L.np] = 0.f;
     }
     if (lane < L.nx) S.trial[lane] = poses[(long)idx * L.nx + lane];
     wave_sync();
@@ -1407,7 +1414,6 @@ __global__ __launch_bounds__(256) void local_opt_kernel(const uint32_t *blob, in
     if (PPL > 0 && lane == 0) {
         const WaveL S0 = make_wave(wbase + w * lay.wave_words, lay);
         S0.pf[L.np] = make_float4(0.f, 0.f, 0.f, 0.f);
-        S0.pe[L.np] = 0.f;
     }
     if (w == 0 && lane < L.nx) C.cur[lane] = poses_in[(long)idx * L.nx + lane];
     __syncthreads();
@@ -1458,7 +1464,6 @@ __global__ __launch_bounds__(256) void tick_kernel(const uint32_t *arena, const 
     if (PPL > 0 && lane == 0) {
         const WaveL S0 = make_wave(wbase + w * lay.wave_words, lay);
         S0.pf[L.np] = make_float4(0.f, 0.f, 0.f, 0.f);
-        S0.pe[L.np] = 0.f;
     }
 
     Energy Ex, Eb;

@@ -7,8 +7,9 @@ FP64 oracle, through the C ABI, plus its invariances inside the search.
   * at the default 100 iterations (where float rounding steers the iteration,
     as it does the oracle's own under 1e-7 input noise) the endpoint energies
     have the oracle's distribution;
-  * searches are bitwise independent of the waves per chain and of the
-    intra-ligand layout, and count (iters + 1) evaluations per step;
+  * searches are bitwise independent of the waves per chain (with pair lists
+    each evaluation is spread over them) and of the intra-ligand layout, and
+    count (iters + 1) evaluations per step;
   * full searches match the oracle's chain-best distribution.
 """
 import time
@@ -113,10 +114,33 @@ def test_bb_dock_invariances(cfg1):
     base = dict(optimizer=D.DSDP_OPT_BB, bb_iters=15)
     a = gc.gpu_dock(g, lig, 32, 10, 3, 5, D.dsdp_params_default(**base))
     assert a[3].pose_evals == 32 * 10 * 16 and a[3].local_opts == 32 * 10
-    for extra in (dict(waves_per_chain=2), dict(waves_per_chain=4), dict(intra_form=1), dict(intra_form=2)):
+    # pair lists spread each evaluation over the chain's waves, atom lists use one
+    for extra in (dict(waves_per_chain=2), dict(waves_per_chain=4), dict(intra_form=1), dict(intra_form=2),
+                  dict(intra_form=1, waves_per_chain=1), dict(intra_form=1, waves_per_chain=3),
+                  dict(intra_form=1, waves_per_chain=4), dict(intra_form=2, waves_per_chain=2)):
         b = gc.gpu_dock(g, lig, 32, 10, 3, 5, D.dsdp_params_default(**base, **extra))
         assert [bytes(p) for p in a[2]] == [bytes(p) for p in b[2]], extra
         assert [bytes(p) for p in a[0]] == [bytes(p) for p in b[0]], extra
+
+
+def test_bb_local_opt_split_bitwise(cfg1):
+    # one evaluation spread over 1-4 waves (pair lists) gives the bits of one wave
+    cfg, ref, g = cfg1
+    gc = _gc()
+    import paper_2303_09916_amd as D
+    lig = cfg["ligands"][0]
+    L = O.LigandModel(lig)
+    rng = np.random.default_rng(13)
+    lo, hi = ref.origin, ref.origin + (ref.n - 1) * ref.h
+    P = random_poses(L.n_tors, 64, lo, hi, rng)
+    out = []
+    for form, waves in ((1, 1), (1, 2), (1, 3), (1, 4), (2, 1), (2, 4)):
+        prm = D.dsdp_params_default(optimizer=D.DSDP_OPT_BB, bb_iters=40, intra_form=form, waves_per_chain=waves)
+        Pg, Eg, Ng = gc.gpu_local_opt(g, lig, P, prm)
+        assert np.all(Ng == 41)
+        out.append((form, waves, Pg.tobytes(), Eg.tobytes()))
+    for form, waves, p, e in out[1:]:
+        assert p == out[0][2] and e == out[0][3], (form, waves)
 
 
 def test_bb_dock_distribution_matches_oracle(cfg1):
