@@ -624,6 +624,33 @@ def gather_probe(D, torch, rec, box, types, maps, gws, stream, n_chains):
             "search_waves": waves, "bytes_per_gather": 128}
 
 
+def occupancy_leg(D, torch, cfg, L, maps, gws, stream, peak_GBps, chain_counts=(1024, 4096, 8192), n_steps=100):
+    """The same search kernel, request and maps with more chains than the
+    workload's: the gather rate it reaches once enough chains run at once to
+    hide each chain's dependent round trips (the workload's 384 chains fill
+    about a third of the device's SIMDs)."""
+    rec, box, lig, types = cfg["receptor"], cfg["box"], cfg["ligands"][0], cfg["map_types"]
+    g = D.dsdp_build_grids(rec.xyz, rec.types, box, types, maps, gws, stream)
+    out = []
+    for n in chain_counts:
+        ws = torch.empty(D.dsdp_dock_workspace_bytes(L, n), dtype=torch.uint8, device="cuda")
+        D.dsdp_dock(g, L, n, 3, cfg["seed"], cfg["top_k"], ws, stream=stream)
+        best = None
+        for _ in range(2):
+            _, _, _, st = D.dsdp_dock(g, L, n, n_steps, cfg["seed"], cfg["top_k"], ws, stream=stream)
+            if best is None or st.search_ms < best.search_ms:
+                best = st
+        del ws
+        gbps = best.pose_evals * lig.n_atoms * 128 / (best.search_ms * 1e-3) / 1e9
+        out.append({"chains": n, "mc_steps": n_steps, "search_ms": best.search_ms,
+                    "evals_per_s": best.pose_evals / (best.search_ms * 1e-3), "achieved_GBps": gbps,
+                    "frac": gbps / peak_GBps})
+        print(f"[bench] occupancy: {n} chains x {n_steps} steps: {best.search_ms:.2f} ms, {gbps:.0f} GB/s of "
+              f"gathers, {gbps / peak_GBps:.2f} of the probe", file=sys.stderr, flush=True)
+    D.dsdp_grids_release(g)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -648,6 +675,8 @@ def main():
                     help="skip the Barzilai-Borwein vs BFGS and search-space comparisons")
     ap.add_argument("--no-grid-leg", dest="grid_leg", action="store_false",
                     help="skip the grid-build stress workload (12000 atoms, 107^3 x 9 maps)")
+    ap.add_argument("--no-occupancy-leg", dest="occupancy_leg", action="store_false",
+                    help="skip the search kernel at 1024-8192 chains (the gather rate with the device full)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one plain device copy of this size (for counter calibration)")
     args = ap.parse_args()
@@ -715,7 +744,9 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     probe = gather_probe(D, torch, rec, box, types, maps, gws, stream, n_chains)
-    del maps, gws, dws
+    del dws
+    occupancy = occupancy_leg(D, torch, cfg, L, maps, gws, stream, probe["full_GBps"]) if args.occupancy_leg else None
+    del maps, gws
 
     value = evals / elapsed
     evals_per_launch = evals / args.steps
@@ -775,6 +806,7 @@ def main():
             "hbm_peak_GBps": HBM_PEAK_GBPS,
             "frac_of_hbm_peak": gather_gbps / HBM_PEAK_GBPS,
             "gather_probe": probe,
+            "occupancy": occupancy,
             "valu": {"flops_per_eval": fpe, "achieved_TFLOPs": valu_tflops, "peak_TFLOPs": FP32_VALU_PEAK_TFLOPS,
                      "frac": valu_tflops / FP32_VALU_PEAK_TFLOPS, "valu_busy_frac": valu_busy},
         },

@@ -1397,8 +1397,10 @@ dsdp_status dsdp_dock_batch(dsdp_grids g, const dsdp_ligand *ligs, int32_t n_lig
             shapes[(size_t)l] = shape_bucket(pls[(size_t)l].h.n_atoms, pls[(size_t)l].h.n_pairs, 6 + pls[(size_t)l].h.n_tors);
         const TuneKey key = tune_key(dev, n_chains, shapes);
         dsdp_status mst = DSDP_OK;
-        // a trial: the candidate's plan over every chain of the batch for a few
-        // steps from fresh starts (the search afterwards starts afresh too)
+        // a trial: the candidate's plan over every chain of the batch, one
+        // untimed step from fresh starts (so that no candidate pays a kernel's
+        // first-launch costs in its time) and then kTrialSteps timed steps (the
+        // search afterwards starts afresh)
         auto measure = [&](int c) -> float {
             BatchPlan tp;
             if (mst || !tuned_plan(c, pp_pairs, pp_atoms, n_chains, tp)) return -1.f;
@@ -1407,7 +1409,8 @@ dsdp_status dsdp_dock_batch(dsdp_grids g, const dsdp_ligand *ligs, int32_t n_lig
             hipEvent_t e0 = nullptr, e1 = nullptr;
             float ms = -1.f;
             bool ok = br.make((int)tp.groups.size()) == hipSuccess && hipEventCreate(&e0) == hipSuccess &&
-                      hipEventCreate(&e1) == hipSuccess && hipEventRecord(e0, cs) == hipSuccess &&
+                      hipEventCreate(&e1) == hipSuccess && launch_plan(tp, br, w, ws, sp, 1, 1, cs) == hipSuccess &&
+                      hipEventRecord(e0, cs) == hipSuccess &&
                       launch_plan(tp, br, w, ws, sp, kTrialSteps, 1, cs) == hipSuccess &&
                       hipEventRecord(e1, cs) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
                       hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
