@@ -123,11 +123,12 @@ typedef struct {
                                 least this much besides passing the Armijo test (kcal/mol; 1e-4).
                                 Float32 energies of nearby poses differ by rounding noise of about
                                 1e-5 kcal/mol, so smaller decreases are not resolved */
-    int32_t tune;            /* launch plan of dsdp_dock_batch with BFGS, when waves_per_chain and
-                                intra_form are 0: 1 = the candidate plan that ran fastest on a
-                                short trial of the batch, measured once per batch make-up and
-                                device and cached (see dsdp_tune_entries); 0 = a fixed rule.
-                                Results do not depend on it (1) */
+    int32_t tune;            /* launch plan of dsdp_dock_batch (BFGS) and layout and waves of
+                                dsdp_dock, when waves_per_chain and intra_form are 0: 1 = the
+                                candidate that ran fastest on a short trial of the request,
+                                measured once per request make-up and device and cached (see
+                                dsdp_tune_entries; dsdp_dock_static only reads the cache);
+                                0 = a fixed rule.  Results do not depend on it (1) */
 } dsdp_params;
 
 #define DSDP_OPT_BFGS 0
@@ -344,30 +345,37 @@ dsdp_status dsdp_dock_static(dsdp_grids g, const dsdp_ligand *lig, int32_t n_cha
                              int32_t *n_out, dsdp_pose *chains_out, dsdp_dock_stats *stats);
 
 /*
- * The batched search's tuner cache (the autotuner of the batching pattern; the
- * paper runs one ligand at a time).  For each batch make-up (ligand shapes, chains
- * per ligand) the library timed its candidate launch plans on a short trial of
- * the batch and keeps the fastest.  A plan gives the intra-ligand layout of
- * ligands with at most 512 pairs and of larger ones, and the waves per chain;
- * ligands that share a kernel variant and a wave count share a launch.
+ * The search's tuner cache (the autotuner of the batching pattern, also used by
+ * dsdp_dock; the paper runs one ligand at a time).  For each request make-up
+ * (kind, ligand shapes, chains per ligand) the library timed its candidates on a
+ * short trial of the request itself and keeps the fastest.  A batch plan (6
+ * candidates) gives the intra-ligand layout of ligands with at most 512 pairs
+ * and of larger ones, and the waves per chain; ligands that share a kernel
+ * variant and a wave count share a launch.  A dock candidate (8) gives the
+ * ligand's layout (pair lists, then atom lists) and the waves (4, 3, 2, 1).
  */
-#define DSDP_TUNE_PLANS 6
+#define DSDP_TUNE_CANDIDATES 8
+#define DSDP_TUNE_BATCH 0       /* dsdp_dock_batch with BFGS */
+#define DSDP_TUNE_DOCK_BFGS 1   /* dsdp_dock with BFGS */
+#define DSDP_TUNE_DOCK_BB 2     /* dsdp_dock with Barzilai-Borwein */
 typedef struct {
     int32_t device;            /* HIP device ordinal the entry was measured on */
+    int32_t kind;              /* DSDP_TUNE_* */
     int32_t chains;            /* chains per ligand */
     int32_t shapes;            /* distinct ligand shapes (atoms in steps of 8, pair class, > 10 torsions) */
-    int32_t plan;              /* pick: index of the candidate plan */
-    int32_t intra_form_small;  /* pick: DSDP_INTRA_PAIRS or DSDP_INTRA_ATOMS for <= 512 pairs */
-    int32_t intra_form_large;  /* pick: the same for more pairs */
+    int32_t plan;              /* pick: index of the candidate */
+    int32_t intra_form_small;  /* pick: DSDP_INTRA_PAIRS or DSDP_INTRA_ATOMS for <= 512 pairs (docks: the layout) */
+    int32_t intra_form_large;  /* pick: the same for more pairs (docks: the layout) */
     int32_t waves_per_chain;   /* pick */
-    int32_t trial_steps;       /* MC steps of each trial (every chain of the batch) */
-    float trial_ms[DSDP_TUNE_PLANS];   /* each candidate's trial time (< 0: could not run) */
+    int32_t trial_steps;       /* timed MC steps of each trial (every chain of the request) */
+    float trial_ms[DSDP_TUNE_CANDIDATES];   /* each candidate's trial time (< 0: could not run;
+                                               0 past the kind's candidates) */
 } dsdp_tune_entry;
 
 /* Copies up to cap entries of the current device's cache into out (nullable);
  * returns the number of entries the cache holds for the device. */
 int32_t dsdp_tune_entries(dsdp_tune_entry *out, int32_t cap);
-/* Empties the cache (every device); the next batches measure again. */
+/* Empties the cache (every device); the next requests measure again. */
 void dsdp_tune_reset(void);
 
 /* Device workspace bytes for dsdp_dock_batch over these ligands (0 on invalid input). */

@@ -61,10 +61,15 @@ class dsdp_params(C.Structure):
                 ("ls_min_decrease", C.c_float), ("tune", C.c_int32)]
 
 
+DSDP_TUNE_CANDIDATES = 8
+DSDP_TUNE_BATCH, DSDP_TUNE_DOCK_BFGS, DSDP_TUNE_DOCK_BB = 0, 1, 2
+
+
 class dsdp_tune_entry(C.Structure):
-    _fields_ = [("device", C.c_int32), ("chains", C.c_int32), ("shapes", C.c_int32), ("plan", C.c_int32),
-                ("intra_form_small", C.c_int32), ("intra_form_large", C.c_int32), ("waves_per_chain", C.c_int32),
-                ("trial_steps", C.c_int32), ("trial_ms", C.c_float * 6)]
+    _fields_ = [("device", C.c_int32), ("kind", C.c_int32), ("chains", C.c_int32), ("shapes", C.c_int32),
+                ("plan", C.c_int32), ("intra_form_small", C.c_int32), ("intra_form_large", C.c_int32),
+                ("waves_per_chain", C.c_int32), ("trial_steps", C.c_int32),
+                ("trial_ms", C.c_float * DSDP_TUNE_CANDIDATES)]
 
 
 class dsdp_pose(C.Structure):
@@ -374,16 +379,18 @@ def dsdp_dock_batch(grids, ligs, n_chains, n_steps, seeds, top_k, d_ws, params=N
     return res, stats
 
 
-def dsdp_tune_entries():
-    """The batched search's tuner cache on the current device, as dicts."""
+def dsdp_tune_entries(kind=None):
+    """The search's tuner cache on the current device, as dicts (only entries of
+    `kind` when given); trial_ms lists the kind's candidates only."""
     n = lib().dsdp_tune_entries(None, 0)
     arr = (dsdp_tune_entry * max(n, 1))()
     n = min(n, lib().dsdp_tune_entries(arr, n))
     out = []
     for i in range(n):
         e = {f: getattr(arr[i], f) for f, _ in dsdp_tune_entry._fields_}
-        e["trial_ms"] = list(e["trial_ms"])
-        out.append(e)
+        e["trial_ms"] = list(e["trial_ms"])[: 6 if e["kind"] == DSDP_TUNE_BATCH else DSDP_TUNE_CANDIDATES]
+        if kind is None or e["kind"] == kind:
+            out.append(e)
     return out
 
 

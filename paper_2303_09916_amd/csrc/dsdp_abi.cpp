@@ -248,12 +248,9 @@ dsdp_status prepare_ligand(const dsdp_ligand *lig, const int *map_of_type, Prepa
         return (a.second - a.first) < (b.second - b.first);
     });
     std::vector<uint32_t> pairs;
-    std::vector<float> rsum;
     for (const auto &ij : plist) {
         const int i = ij.first, j = ij.second;
-        const int ti = xs[i], tj = xs[j];
-        pairs.push_back((uint32_t)i | ((uint32_t)j << 8) | (pair_flags(ti, tj) << 16));
-        rsum.push_back(xs_radius(ti) + xs_radius(tj));
+        pairs.push_back((uint32_t)i | ((uint32_t)j << 8) | (pair_flags(xs[i], xs[j]) << 16));
     }
     const int np = (int)pairs.size();
     // depth and subtree masks
@@ -325,15 +322,14 @@ dsdp_status prepare_ligand(const dsdp_ligand *lig, const int *map_of_type, Prepa
             maxlen = std::max(maxlen, lane_list[l].size());
         }
     }
+    h.off_atom_rad = take(na, 1);
     if (h.intra_form == kFormPairs) {
         h.off_pair = take(np, 1);
-        h.off_pair_rsum = take(np, 1);
         h.n_chunks = (int)((maxlen + 7) / 8);
         h.off_plist = take(h.n_chunks * 64 * 4, 4);
     } else {
         h.nbr_words = (int)((maxlen + 3) / 4);
         h.off_nbr = take(h.nbr_words * 64, 1);
-        h.off_atom_rad = take(na, 1);
     }
     h.total_words = (w + 3) / 4 * 4;
 
@@ -384,10 +380,7 @@ dsdp_status prepare_ligand(const dsdp_ligand *lig, const int *map_of_type, Prepa
         blob[(size_t)h.off_frag_anc + k] = anc;
     }
     if (h.intra_form == kFormPairs) {
-        for (int p = 0; p < np; p++) {
-            blob[(size_t)h.off_pair + p] = pairs[p];
-            fput(h.off_pair_rsum + p, rsum[p]);
-        }
+        for (int p = 0; p < np; p++) blob[(size_t)h.off_pair + p] = pairs[p];
         for (int c = 0; c < h.n_chunks; c++)
             for (int l = 0; l < 64; l++)
                 for (int q = 0; q < 8; q++) {
@@ -407,8 +400,8 @@ dsdp_status prepare_ligand(const dsdp_ligand *lig, const int *map_of_type, Prepa
                 }
                 blob[(size_t)h.off_nbr + (size_t)m * 64 + l] = word;
             }
-        for (int i = 0; i < na; i++) fput(h.off_atom_rad + i, xs_radius(xs[i]));
     }
+    for (int i = 0; i < na; i++) fput(h.off_atom_rad + i, xs_radius(xs[i]));
     out.h = h;
     out.blob.swap(blob);
     return DSDP_OK;
@@ -998,6 +991,115 @@ dsdp_status dsdp_local_opt(dsdp_grids g, const dsdp_ligand *lig, const float *d_
 }  // extern "C"
 
 namespace {
+
+Tuner &tuner()
+{
+    static Tuner t;
+    return t;
+}
+
+constexpr int kTrialSteps = 4;   // timed MC steps of a tuner trial (every chain of the request)
+
+// The workspace's host-written part for one dock (blob, chain tasks from fresh
+// starts, grid view, ranking segment), uploaded on s.
+dsdp_status upload_dock(const dsdp_grids_s *g, const Prepared &pl, const SearchWs &w, int n_chains, int n_steps,
+                        uint64_t seed, int top_k, char *ws, hipStream_t s)
+{
+    HostImage img(w.host_end);
+    std::memcpy(img.at<uint32_t>(w.arena), pl.blob.data(), pl.blob.size() * 4);
+    ChainTask *tasks = img.at<ChainTask>(w.tasks);
+    for (int c = 0; c < n_chains; c++) {
+        ChainTask &t = tasks[c];
+        t.blob_off = 0;
+        t.blob_words = (uint32_t)pl.h.total_words;
+        t.chain = (uint32_t)c;
+        t.n_steps = n_steps;
+        t.seed_lo = (uint32_t)seed;
+        t.seed_hi = (uint32_t)(seed >> 32);
+        t.grid = 0;
+        t.slot = c;
+        t.fresh = 1;
+    }
+    GridView view;
+    dsdp_status st = device_view(g, ws, w, img.bytes.data(), s, view);
+    if (st) return st;
+    *img.at<GridView>(w.grids) = view;
+    RankSeg *seg = img.at<RankSeg>(w.segs);
+    seg->slot0 = 0;
+    seg->n_chains = n_chains;
+    seg->n_atoms = pl.h.n_atoms;
+    seg->top_k = top_k;
+    seg->sel_off = 0;
+    HIP_TRY(hipMemcpyAsync(ws, img.bytes.data(), img.bytes.size(), hipMemcpyHostToDevice, s), "task upload");
+    HIP_TRY(hipStreamSynchronize(s), "task upload");
+    return DSDP_OK;
+}
+
+// The tuned layout and waves of a dock: the cached pick for the request's
+// make-up (optimiser, ligand shape, chains), else each candidate timed on a
+// trial of the request itself (every chain, one untimed step from fresh starts
+// and then the next kTrialSteps steps timed, on the caller's workspace) and the
+// fastest cached.  With lookup_only nothing is measured (waves stays 0 without a
+// cached pick).  `use` is pl or alt (the other layout, prepared here).
+dsdp_status tune_dock(const dsdp_grids_s *g, const dsdp_ligand *lig, const dsdp_params *prm, const Prepared &pl,
+                      Prepared &alt, int n_chains, uint64_t seed, const SearchParams &sp, char *ws, size_t ws_bytes,
+                      hipStream_t s, bool lookup_only, const Prepared *&use, int &waves)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "device");
+    const int kind = prm->optimizer == DSDP_OPT_BB ? kTuneDockBb : kTuneDockBfgs;
+    const TuneKey key = tune_key(dev, n_chains, {shape_bucket(pl.h.n_atoms, pl.h.n_pairs, 6 + pl.h.n_tors)}, kind);
+    const int pl_form = pl.h.intra_form == kFormPairs ? DSDP_INTRA_PAIRS : DSDP_INTRA_ATOMS;
+    bool have_alt = false;
+    dsdp_status mst = DSDP_OK;
+    auto layout = [&](int form) -> const Prepared * {
+        if (form == pl_form) return &pl;
+        if (!have_alt) {
+            if ((mst = prepare_ligand(lig, g->map_of_type, alt, IntraCtx{form}))) return nullptr;
+            have_alt = true;
+        }
+        return &alt;
+    };
+    int pick = -1;
+    if (lookup_only) {
+        if (!tuner().find(key, pick)) return DSDP_OK;
+    } else {
+        auto measure = [&](int c) -> float {
+            const DockCandidate dc = dock_candidate(c);
+            const Prepared *P = mst ? nullptr : layout(dc.form);
+            if (!P) return -1.f;
+            const size_t lds = search_lds_bytes(P->h, dc.waves);
+            const SearchWs w = search_ws(P->h, n_chains);
+            if (lds > device_max_lds() || w.total > ws_bytes) return -1.f;
+            // trial chains run 1 + kTrialSteps steps whatever the request's length,
+            // so that requests of any length share the cached pick
+            if ((mst = upload_dock(g, *P, w, n_chains, 1 + kTrialSteps, seed, 0, ws, s))) return -1.f;
+            Events ev;
+            float ms = -1.f;
+            auto tick = [&](int steps, int init) {
+                return launch_tick(search_class(P->h), dc.waves, lds, (const uint32_t *)(ws + w.arena),
+                                   (const ChainTask *)(ws + w.tasks), n_chains, (const GridView *)(ws + w.grids), sp,
+                                   steps, init, (float *)(ws + w.state), (float *)(ws + w.records),
+                                   (float4 *)(ws + w.xyz), s);
+            };
+            const bool ok = ev.create() == hipSuccess && tick(1, 1) == hipSuccess &&
+                            hipEventRecord(ev.e[0], s) == hipSuccess && tick(kTrialSteps, 0) == hipSuccess &&
+                            hipEventRecord(ev.e[1], s) == hipSuccess && hipEventSynchronize(ev.e[1]) == hipSuccess &&
+                            hipEventElapsedTime(&ms, ev.e[0], ev.e[1]) == hipSuccess;
+            if (!ok) mst = fail(DSDP_ERR_DEVICE, "dock tuner trial: %s", hipGetErrorString(hipGetLastError()));
+            return ok ? ms : -1.f;
+        };
+        const bool found = tuner().pick(key, measure, pick, n_chains, kTrialSteps);
+        if (mst) return mst;
+        if (!found) return DSDP_OK;   // no candidate fits: the fixed rule decides
+    }
+    const DockCandidate dc = dock_candidate(pick);
+    use = layout(dc.form);
+    if (mst) return mst;
+    waves = dc.waves;
+    return DSDP_OK;
+}
+
 // dsdp_dock on a workspace that is either the caller's (d_ws, ws_bytes) or, with
 // d_ws NULL, the library's static scratch of this device.
 dsdp_status dock_impl(dsdp_grids g, const dsdp_ligand *lig, int32_t n_chains, int32_t n_steps, uint64_t seed,
@@ -1014,55 +1116,44 @@ dsdp_status dock_impl(dsdp_grids g, const dsdp_ligand *lig, int32_t n_chains, in
     if (top_k > 0 && (!out || !n_out)) return fail(DSDP_ERR_INVALID_ARG, "out/n_out is NULL");
     dsdp_status st = check_params(prm);
     if (st) return st;
-    Prepared pl;
-    st = prepare_ligand(lig, g->map_of_type, pl, intra_ctx(prm, n_chains, false));
+    Prepared pl0, alt;
+    st = prepare_ligand(lig, g->map_of_type, pl0, intra_ctx(prm, n_chains, false));
     if (st) return st;
+    const SearchParams sp = to_search(prm);
+    hipStream_t s = (hipStream_t)stream;
+    if (static_ws) HIP_TRY(static_scratch(&d_ws), "static scratch address");
+    // layout and waves: the tuner's (the static entry point only reads its
+    // cache: it measures nothing), else the fixed rule
+    const Prepared *use = &pl0;
+    int waves = 0;
+    dsdp_params dp;
+    if (!prm) {
+        dsdp_params_default(&dp);
+        prm = &dp;
+    }
+    if (prm->tune == 1 && prm->waves_per_chain == 0 && prm->intra_form == DSDP_INTRA_AUTO && n_steps > 0 && d_ws &&
+        aligned256(d_ws)) {
+        st = tune_dock(g, lig, prm, pl0, alt, n_chains, seed, sp, (char *)d_ws,
+                       static_ws ? kStaticScratchBytes : ws_bytes, s, static_ws, use, waves);
+        if (st) return st;
+    }
+    const Prepared &pl = *use;
+    if (waves == 0) {
+        st = pick_waves(prm, pl.h, n_chains, waves);
+        if (st) return st;
+    }
     const SearchWs w = search_ws(pl.h, n_chains);
     if (static_ws) {
         if (w.total > kStaticScratchBytes)
             return fail(DSDP_ERR_UNSUPPORTED, "this dock needs %zu bytes of scratch; the static scratch holds %zu",
                         w.total, kStaticScratchBytes);
-        HIP_TRY(static_scratch(&d_ws), "static scratch address");
         ws_bytes = kStaticScratchBytes;
     }
     if (!d_ws || ws_bytes < w.total) return fail(DSDP_ERR_WORKSPACE_TOO_SMALL, "workspace needs %zu bytes", w.total);
     if (!aligned256(d_ws)) return fail(DSDP_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
-    const SearchParams sp = to_search(prm);
-    int waves = 1;
-    st = pick_waves(prm, pl.h, n_chains, waves);
-    if (st) return st;
-    hipStream_t s = (hipStream_t)stream;
     char *ws = (char *)d_ws;
-
-    HostImage img(w.host_end);
-    std::memcpy(img.at<uint32_t>(w.arena), pl.blob.data(), pl.blob.size() * 4);
-    ChainTask *tasks = img.at<ChainTask>(w.tasks);
-    for (int c = 0; c < n_chains; c++) {
-        ChainTask &t = tasks[c];
-        t.blob_off = 0;
-        t.blob_words = (uint32_t)pl.h.total_words;
-        t.chain = (uint32_t)c;
-        t.n_steps = n_steps;
-        t.seed_lo = (uint32_t)seed;
-        t.seed_hi = (uint32_t)(seed >> 32);
-        t.grid = 0;
-        t.slot = c;
-        t.fresh = 1;
-    }
-    {
-        GridView view;
-        st = device_view(g, ws, w, img.bytes.data(), s, view);
-        if (st) return st;
-        *img.at<GridView>(w.grids) = view;
-    }
-    RankSeg *seg = img.at<RankSeg>(w.segs);
-    seg->slot0 = 0;
-    seg->n_chains = n_chains;
-    seg->n_atoms = pl.h.n_atoms;
-    seg->top_k = top_k;
-    seg->sel_off = 0;
-    HIP_TRY(hipMemcpyAsync(ws, img.bytes.data(), img.bytes.size(), hipMemcpyHostToDevice, s), "task upload");
-    HIP_TRY(hipStreamSynchronize(s), "task upload");
+    st = upload_dock(g, pl, w, n_chains, n_steps, seed, top_k, ws, s);
+    if (st) return st;
 
     Events ev;
     if (stats) {
@@ -1139,14 +1230,6 @@ dsdp_status dsdp_dock_static(dsdp_grids g, const dsdp_ligand *lig, int32_t n_cha
 }  // extern "C"
 
 namespace {
-
-Tuner &tuner()
-{
-    static Tuner t;
-    return t;
-}
-
-constexpr int kTrialSteps = 3;   // MC steps of a tuner trial (every chain of the batch)
 
 // One launch of a batch plan: a kernel variant and wave count, the LDS its
 // largest member needs, its chains (contiguous in the task table).
@@ -1275,7 +1358,7 @@ struct Branches {
 // groups are independent, so one group's tail overlaps the others' work), joined
 // back on `cs`.  Used for trials and inside the batch's graph capture.
 hipError_t launch_plan(const BatchPlan &bp, Branches &br, const SearchWs &w, char *ws, const SearchParams &sp,
-                       int spt, int n_ticks, hipStream_t cs)
+                       int spt, int n_ticks, hipStream_t cs, bool fresh = true)
 {
     const int nb = (int)bp.groups.size();
     hipError_t le = hipEventRecord(br.e[(size_t)nb], cs);
@@ -1285,7 +1368,7 @@ hipError_t launch_plan(const BatchPlan &bp, Branches &br, const SearchWs &w, cha
         for (int k = 0; k < n_ticks && le == hipSuccess; k++)
             le = launch_tick(b.cls, b.waves, b.lds, (const uint32_t *)(ws + w.arena),
                              (const ChainTask *)(ws + w.tasks) + b.first, (int)b.count,
-                             (const GridView *)(ws + w.grids), sp, spt, k == 0 ? 1 : 0, (float *)(ws + w.state),
+                             (const GridView *)(ws + w.grids), sp, spt, (k == 0 && fresh) ? 1 : 0, (float *)(ws + w.state),
                              (float *)(ws + w.records), (float4 *)(ws + w.xyz), br.s[(size_t)i]);
         if (le == hipSuccess) le = hipEventRecord(br.e[(size_t)i], br.s[(size_t)i]);
         if (le == hipSuccess) le = hipStreamWaitEvent(cs, br.e[(size_t)i], 0);
@@ -1307,15 +1390,23 @@ int32_t dsdp_tune_entries(dsdp_tune_entry *out, int32_t cap)
         const TuneEntry &e = v[(size_t)i];
         std::memset(&o, 0, sizeof o);
         o.device = e.key.device;
+        o.kind = e.key.kind;
         o.chains = e.key.chains;
         o.shapes = (int32_t)e.key.shapes.size();
         o.plan = e.pick;
-        const Plan p = plan(e.pick);
-        o.intra_form_small = p.form_small;
-        o.intra_form_large = p.form_large;
-        o.waves_per_chain = p.waves;
+        if (e.key.kind == kTuneBatch) {
+            const Plan p = plan(e.pick);
+            o.intra_form_small = p.form_small;
+            o.intra_form_large = p.form_large;
+            o.waves_per_chain = p.waves;
+        } else {
+            const DockCandidate d = dock_candidate(e.pick);
+            o.intra_form_small = o.intra_form_large = d.form;
+            o.waves_per_chain = d.waves;
+        }
         o.trial_steps = e.trial_steps;
-        for (int c = 0; c < DSDP_TUNE_PLANS && c < (int)e.trial_ms.size(); c++) o.trial_ms[c] = e.trial_ms[(size_t)c];
+        for (int c = 0; c < DSDP_TUNE_CANDIDATES && c < (int)e.trial_ms.size(); c++)
+            o.trial_ms[c] = e.trial_ms[(size_t)c];
     }
     return (int32_t)v.size();
 }
@@ -1399,19 +1490,22 @@ dsdp_status dsdp_dock_batch(dsdp_grids g, const dsdp_ligand *ligs, int32_t n_lig
         dsdp_status mst = DSDP_OK;
         // a trial: the candidate's plan over every chain of the batch, one
         // untimed step from fresh starts (so that no candidate pays a kernel's
-        // first-launch costs in its time) and then kTrialSteps timed steps (the
-        // search afterwards starts afresh)
+        // first-launch costs in its time, nor times the chains' first steps)
+        // and then the next kTrialSteps steps timed (the search afterwards
+        // starts afresh)
         auto measure = [&](int c) -> float {
             BatchPlan tp;
             if (mst || !tuned_plan(c, pp_pairs, pp_atoms, n_chains, tp)) return -1.f;
-            if ((mst = upload_plan(tp, g, seeds, n_chains, n_steps, top_k, w, ws, cs))) return -1.f;
+            // 1 + kTrialSteps steps whatever the batch's length, so that batches of
+            // any length share the cached pick
+            if ((mst = upload_plan(tp, g, seeds, n_chains, 1 + kTrialSteps, top_k, w, ws, cs))) return -1.f;
             Branches br;
             hipEvent_t e0 = nullptr, e1 = nullptr;
             float ms = -1.f;
             bool ok = br.make((int)tp.groups.size()) == hipSuccess && hipEventCreate(&e0) == hipSuccess &&
                       hipEventCreate(&e1) == hipSuccess && launch_plan(tp, br, w, ws, sp, 1, 1, cs) == hipSuccess &&
                       hipEventRecord(e0, cs) == hipSuccess &&
-                      launch_plan(tp, br, w, ws, sp, kTrialSteps, 1, cs) == hipSuccess &&
+                      launch_plan(tp, br, w, ws, sp, kTrialSteps, 1, cs, false) == hipSuccess &&
                       hipEventRecord(e1, cs) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
                       hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
             if (e0) (void)hipEventDestroy(e0);

@@ -85,14 +85,13 @@ struct LigHeader {
     int32_t off_frag_anc;    // uint32[n_frags]: up to four ancestors below the root, nearest first, one
                              // byte each, 0 after the last
     int32_t off_pair;        // uint32[n_pairs]: i | j << 8 | flags << 16
-    int32_t off_pair_rsum;   // float[n_pairs]: R_i + R_j
     int32_t off_plist;       // uint4[n_chunks][64]: per gather lane, 8 u16 entries (pair | sign << 15) per chunk
     int32_t n_chunks;        // chunks of 8 entries per gather lane
     int32_t lanes_per_atom;  // 2 when n_atoms <= 32 (lanes a and a + 32 split atom a's list), else 1
     int32_t intra_form;      // kFormPairs or kFormAtoms (how the intra-ligand term is laid out)
     int32_t nbr_words;       // atom lists: words of packed partner bytes per lane
     int32_t off_nbr;         // atom lists: uint32[nbr_words][64], byte = partner | hydrophobic << 6 | hbond << 7
-    int32_t off_atom_rad;    // atom lists: float[n_atoms] XS radius
+    int32_t off_atom_rad;    // float[n_atoms] XS radius (both layouts)
     int32_t total_words;     // multiple of 4
 };
 

@@ -306,11 +306,10 @@ struct LigL {
     const uint32_t *frag_range;  // first slot | end slot << 8 | subtree end slot << 16
     const uint32_t *frag_anc;    // up to four ancestors below the root, nearest first, a byte each
     const uint32_t *pair;
-    const float *rsum;
     const uint4 *plist;      // [n_chunks][64] gather lists (pair lists)
     int n_chunks, lanes_per_atom;
     const uint32_t *nbr;     // [nbr_words][64] packed partner bytes (atom lists)
-    const float *arad;       // [na] XS radius (atom lists)
+    const float *arad;       // [na] XS radius
     int nbr_words;
 };
 
@@ -422,7 +421,6 @@ __device__ inline LigL make_lig(const uint32_t *blob, const uint32_t *hdr)
     L.frag_range = blob + h->off_frag_range;
     L.frag_anc = blob + h->off_frag_anc;
     L.pair = blob + h->off_pair;
-    L.rsum = reinterpret_cast<const float *>(blob + h->off_pair_rsum);
     L.plist = reinterpret_cast<const uint4 *>(blob + h->off_plist);
     L.n_chunks = h->n_chunks;
     L.lanes_per_atom = h->lanes_per_atom;
@@ -433,16 +431,22 @@ __device__ inline LigL make_lig(const uint32_t *blob, const uint32_t *hdr)
 }
 
 // A lane's share of the intra-ligand term held in registers for the whole
-// chain.  Pair lists (PPL > 0): pairs lane + 64 k, unused slots carry kPairNone.
-// Atom lists (PPL == 0) keep nothing in registers: the partner words are read
-// from LDS as they are consumed, which bounds the registers the loop needs.
+// chain.  Pair lists of up to 1024 pairs (PPL 8 and 16): the pair words of
+// pairs lane + 64 k, unused slots carrying kPairNone, and (PPL == 8) the lane's
+// first two gather chunks.  The largest pair lists (PPL == 32) and atom lists
+// (PPL == 0) keep nothing in registers: pair words, partner words and gather
+// chunks are read from LDS as they are consumed, which bounds the registers
+// their loops need.  A pair's radius sum R_i + R_j is formed from the atom
+// radii kept with the coordinates.
 constexpr uint32_t kPairNone = 0x80000000u;
+template <int PPL>
+constexpr bool reg_pairs() { return PPL == 8 || PPL == 16; }
 template <int PPL, int NBW>
 struct IntraRegs {
-    uint32_t w[PPL > 0 ? PPL : 1];
-    float rs[PPL > 0 ? PPL : 1];
-    uint4 pl[PPL == 8 ? 2 : 1];   // eight pairs per lane: the lane's first two gather chunks
+    uint32_t w[reg_pairs<PPL>() ? PPL : 1];
+    uint4 pl[PPL == 8 ? 2 : 1];   // the lane's first two gather chunks
     float4 loc;       // the lane's atom: local offset, w = map index bits
+    float rad;        // the lane's atom: XS radius
     int frag;         // the lane's atom: fragment
     uint32_t anc;     // the lane's fragment: ancestors below the root (LigL::frag_anc)
 };
@@ -451,26 +455,27 @@ __device__ inline IntraRegs<PPL, NBW> load_intra(const LigL &L)
 {
     IntraRegs<PPL, NBW> pr;
     const int lane = lane_id();
-    if constexpr (PPL > 0) {
+    if constexpr (reg_pairs<PPL>()) {
 #pragma unroll
         for (int k = 0; k < PPL; k++) {
             const int p = lane + 64 * k;
             pr.w[k] = p < L.np ? L.pair[p] : kPairNone;
-            pr.rs[k] = p < L.np ? L.rsum[p] : 0.f;
         }
-        if constexpr (PPL == 8) {
+    }
+    if constexpr (PPL == 8) {
 #pragma unroll
-            for (int c = 0; c < 2; c++) {
-                const uint32_t pad = (uint32_t)L.np | ((uint32_t)L.np << 16);
-                pr.pl[c] = c < L.n_chunks ? L.plist[c * 64 + lane] : make_uint4(pad, pad, pad, pad);
-            }
+        for (int c = 0; c < 2; c++) {
+            const uint32_t pad = (uint32_t)L.np | ((uint32_t)L.np << 16);
+            pr.pl[c] = c < L.n_chunks ? L.plist[c * 64 + lane] : make_uint4(pad, pad, pad, pad);
         }
     }
     pr.loc = make_float4(0.f, 0.f, 0.f, 0.f);
+    pr.rad = 0.f;
     pr.frag = 0;
     pr.anc = lane < L.nf ? L.frag_anc[lane] : 0u;
     if (lane < L.na) {
         pr.loc = L.atom[lane];
+        pr.rad = L.arad[lane];
         pr.frag = L.atom_frag[lane];
     }
     return pr;
@@ -676,7 +681,7 @@ __device__ Energy eval_energy(const LigL &L, const WaveL &S, const IntraRegs<PPL
         x = make_float3(o.x + r0.x * loc.x + r0.y * loc.y + r0.z * loc.z,
                         o.y + r1.x * loc.x + r1.y * loc.y + r1.z * loc.z,
                         o.z + r2.x * loc.x + r2.y * loc.y + r2.z * loc.z);
-        S.xyz[lane] = make_float4(x.x, x.y, x.z, PPL == 0 ? L.arad[lane] : 0.f);
+        S.xyz[lane] = make_float4(x.x, x.y, x.z, pr.rad);
     }
     if (lane < L.na && part == 0) {
         const float4 loc = pr.loc;
@@ -736,41 +741,57 @@ __device__ Energy eval_energy(const LigL &L, const WaveL &S, const IntraRegs<PPL
     float e_lane = 0.f;   // atom lists: this lane's share of the intra energy
     float3 fnb = make_float3(0.f, 0.f, 0.f);
     if constexpr (PPL > 0) {
-        // groups of slots: the position loads first, then the pair terms
+        // groups of two slots: the position loads first, then the pair terms
         // without branches (out-of-cutoff and padding pairs select 0)
         const int slots = (L.np + 63) >> 6;
         constexpr int kGroup = 2;
         float4 *const pf = parts > 1 ? pf_shared : S.pf;
+        auto group = [&](int g, const uint32_t (&pw)[kGroup]) {
+            float4 xi[kGroup], xj[kGroup];
 #pragma unroll
-        for (int g = 0; g < PPL; g += kGroup) {
-            if (g < slots && (g / kGroup) % parts == part) {
-                float4 xi[kGroup], xj[kGroup];
+            for (int k = 0; k < kGroup; k++) {
+                xi[k] = S.xyz[pw[k] & 255u];
+                xj[k] = S.xyz[(pw[k] >> 8) & 255u];
+            }
+#pragma unroll
+            for (int k = 0; k < kGroup; k++) {
+                const float dx = xi[k].x - xj[k].x, dy = xi[k].y - xj[k].y, dz = xi[k].z - xj[k].z;
+                const float r2 = pair_r2(dx, dy, dz);
+                const float2 es = pair_term(r2, xi[k].w + xj[k].w, pw[k] >> 16);
+                const bool none = (pw[k] & kPairNone) != 0;
+                const bool in = !none && r2 < kCutoff2;
+                const float ep = in ? es.x : 0.f, sp = in ? es.y : 0.f;
+                const float4 v = make_float4(mul_rounded(sp, dx), mul_rounded(sp, dy), mul_rounded(sp, dz), ep);
+                if constexpr (PPL == 8) {
+                    // a padding lane (both indices 0, so dx = dy = dz = +0)
+                    // stores +0 into its own entry, at or past the zero slot np
+                    // (the array is padded to whole groups): no branch, so the
+                    // group's pair terms interleave
+                    pf[lane + 64 * (g + k)] = v;
+                } else if (!none) {
+                    pf[lane + 64 * (g + k)] = v;
+                }
+            }
+        };
+        if constexpr (reg_pairs<PPL>()) {
+            // pair words in registers, the groups unrolled
+#pragma unroll
+            for (int g = 0; g < PPL; g += kGroup) {
+                if (g < slots && (g / kGroup) % parts == part) {
+                    const uint32_t pw[kGroup] = {pr.w[g], pr.w[g + 1]};
+                    group(g, pw);
+                }
+            }
+        } else {
+            // pair words read from LDS group by group
+            for (int g = kGroup * part; g < slots; g += kGroup * parts) {
+                uint32_t pw[kGroup];
 #pragma unroll
                 for (int k = 0; k < kGroup; k++) {
-                    const uint32_t pw = pr.w[g + k];
-                    xi[k] = S.xyz[pw & 255u];
-                    xj[k] = S.xyz[(pw >> 8) & 255u];
+                    const int p = lane + 64 * (g + k);
+                    pw[k] = p < L.np ? L.pair[p] : kPairNone;
                 }
-#pragma unroll
-                for (int k = 0; k < kGroup; k++) {
-                    const uint32_t pw = pr.w[g + k];
-                    const float dx = xi[k].x - xj[k].x, dy = xi[k].y - xj[k].y, dz = xi[k].z - xj[k].z;
-                    const float r2 = pair_r2(dx, dy, dz);
-                    const float2 es = pair_term(r2, pr.rs[g + k], pw >> 16);
-                    const bool none = (pw & kPairNone) != 0;
-                    const bool in = !none && r2 < kCutoff2;
-                    const float ep = in ? es.x : 0.f, sp = in ? es.y : 0.f;
-                    const float4 v = make_float4(mul_rounded(sp, dx), mul_rounded(sp, dy), mul_rounded(sp, dz), ep);
-                    if constexpr (PPL == 8) {
-                        // a padding lane (both indices 0, so dx = dy = dz = +0)
-                        // stores +0 into its own entry, at or past the zero slot np
-                        // (the array is padded to whole groups): no branch, so the
-                        // group's pair terms interleave
-                        pf[lane + 64 * (g + k)] = v;
-                    } else if (!none) {
-                        pf[lane + 64 * (g + k)] = v;   // fewer registers live for the larger lists
-                    }
-                }
+                group(g, pw);
             }
         }
     } else {

@@ -1,17 +1,18 @@
-// Launch-plan tuner of the batched search: plain C++, no device code, so its
-// selection and cache logic can be unit-tested on the host.  Private to the
-// library.
+// Launch-plan tuner of the search: plain C++, no device code, so its selection
+// and cache logic can be unit-tested on the host.  Private to the library.
 //
 // A batch's launch plan says, for every ligand, which layout of the
 // intra-ligand term its blob uses and how many waves each of its chains gets;
-// ligands with the same kernel variant and wave count share a launch.  The
-// candidate plans (kPlans) are fixed; for a batch composition not yet in the
-// cache of the current device, the caller's `measure` callback times every
-// candidate on a short trial of that batch (all of its chains, a few steps)
-// and the fastest is cached by the composition: the histogram of ligand shapes
-// (heavy atoms, intra-ligand pairs, tangent dimension) and the chain count.
-// Candidates the callback reports as impossible (negative time) are skipped.
-// Search results do not depend on the plan, so the tuner only moves speed.
+// ligands with the same kernel variant and wave count share a launch.  A single
+// ligand's dock has the same two choices, layout and waves.  The candidates
+// (kPlans for batches, kDockCandidates for docks) are fixed; for a request not
+// yet in the cache of the current device, the caller's `measure` callback
+// times every candidate on a short trial of that request (all of its chains, a
+// few steps) and the fastest is cached by the request's make-up: the kind of
+// request, the histogram of ligand shapes (heavy atoms, intra-ligand pairs,
+// tangent dimension) and the chain count.  Candidates the callback reports as
+// impossible (negative time) are skipped.  Search results do not depend on the
+// choice, so the tuner only moves speed.
 #pragma once
 
 #include <algorithm>
@@ -51,16 +52,21 @@ inline int round_up_pow2(long v)
     return p;
 }
 
-// The cache key of a batch: device, ligand-shape histogram (each bucket's count
-// rounded up to a power of two, so that batches of about the same make-up share
-// an entry), chains per ligand.
+// Kinds of tuned request (their candidates differ).
+enum TuneKind { kTuneBatch = 0, kTuneDockBfgs = 1, kTuneDockBb = 2 };
+
+// The cache key of a request: device, kind, ligand-shape histogram (each
+// bucket's count rounded up to a power of two, so that batches of about the
+// same make-up share an entry), chains per ligand.
 struct TuneKey {
     int device = 0;
+    int kind = kTuneBatch;
     int chains = 0;
     std::vector<std::pair<ShapeBucket, int>> shapes;   // sorted by bucket
     bool operator<(const TuneKey &o) const
     {
         if (device != o.device) return device < o.device;
+        if (kind != o.kind) return kind < o.kind;
         if (chains != o.chains) return chains < o.chains;
         if (shapes.size() != o.shapes.size()) return shapes.size() < o.shapes.size();
         for (size_t i = 0; i < shapes.size(); i++) {
@@ -73,12 +79,13 @@ struct TuneKey {
     bool operator==(const TuneKey &o) const { return !(*this < o) && !(o < *this); }
 };
 
-inline TuneKey tune_key(int device, int chains, const std::vector<ShapeBucket> &ligands)
+inline TuneKey tune_key(int device, int chains, const std::vector<ShapeBucket> &ligands, int kind = kTuneBatch)
 {
     std::map<ShapeBucket, int> h;
     for (const ShapeBucket &b : ligands) h[b]++;
     TuneKey k;
     k.device = device;
+    k.kind = kind;
     k.chains = chains;
     for (const auto &kv : h) k.shapes.push_back({kv.first, round_up_pow2(kv.second)});
     return k;
@@ -107,9 +114,23 @@ inline Plan plan(int i)
 }
 inline int plan_form(const Plan &p, int n_pairs) { return n_pairs <= 512 ? p.form_small : p.form_large; }
 
+// The candidates of a single ligand's dock: both layouts (1 pair lists, 2 atom
+// lists) at 4, 3, 2 and 1 waves per chain.
+struct DockCandidate {
+    int form;
+    int waves;
+};
+constexpr int kDockCandidates = 8;
+inline DockCandidate dock_candidate(int i)
+{
+    const int c = (i >= 0 && i < kDockCandidates) ? i : 0;
+    return {c < 4 ? 1 : 2, 4 - (c & 3)};
+}
+inline int candidates_of(int kind) { return kind == kTuneBatch ? kPlans : kDockCandidates; }
+
 struct TuneEntry {
     TuneKey key;
-    int pick = 0;                 // index into the candidate plans
+    int pick = 0;                 // index into the kind's candidates
     std::vector<float> trial_ms;  // per candidate (< 0: could not run)
     int trial_steps = 0;
     long trial_chains = 0;
@@ -120,25 +141,19 @@ public:
     // measure(plan index) -> trial milliseconds, or < 0 when the plan cannot run.
     using Measure = std::function<float(int)>;
 
-    // The cached plan of `key`, else the fastest candidate by `measure` (ties to
-    // the lower index), cached.  Returns false when no candidate can run.
+    // The cached pick of `key`, else the fastest of its kind's candidates by
+    // `measure` (ties to the lower index), cached.  Returns false when no
+    // candidate can run.
     bool pick(const TuneKey &key, const Measure &measure, int &out, long trial_chains = 0, int trial_steps = 0)
     {
-        {
-            std::lock_guard<std::mutex> lock(mu_);
-            auto it = cache_.find(key);
-            if (it != cache_.end()) {
-                out = it->second.pick;
-                hits_++;
-                return true;
-            }
-        }
+        if (find(key, out)) return true;
         TuneEntry e;
         e.key = key;
         e.trial_chains = trial_chains;
         e.trial_steps = trial_steps;
         float best = -1.f;
-        for (int c = 0; c < kPlans; c++) {
+        const int n = candidates_of(key.kind);
+        for (int c = 0; c < n; c++) {
             const float t = measure(c);
             e.trial_ms.push_back(t >= 0.f ? t : -1.f);
             if (!(t >= 0.f)) continue;
@@ -152,6 +167,17 @@ public:
         auto it = cache_.find(key);   // another thread may have tuned it meanwhile: keep the first
         if (it == cache_.end()) it = cache_.emplace(key, e).first;
         out = it->second.pick;
+        return true;
+    }
+
+    // The cached pick of `key`, if any (counted as a hit); measures nothing.
+    bool find(const TuneKey &key, int &out)
+    {
+        std::lock_guard<std::mutex> lock(mu_);
+        auto it = cache_.find(key);
+        if (it == cache_.end()) return false;
+        out = it->second.pick;
+        hits_++;
         return true;
     }
 

@@ -80,7 +80,8 @@ def test_batch_tuner_picks_cached_and_results_unchanged(site):
     D.dsdp_tune_reset()
     assert D.dsdp_tune_entries() == []
     a, _ = D.dsdp_dock_batch(g.handle, Ls, 16, 6, seeds, 4, ws)
-    picks = D.dsdp_tune_entries()
+    picks = D.dsdp_tune_entries(D.DSDP_TUNE_BATCH)
+    assert picks == D.dsdp_tune_entries()
     print(f"[tuner] {picks}", flush=True)
     assert len(picks) == 1
     e = picks[0]
@@ -88,7 +89,7 @@ def test_batch_tuner_picks_cached_and_results_unchanged(site):
     assert e["trial_ms"][e["plan"]] == min(t for t in e["trial_ms"] if t >= 0) and e["trial_steps"] > 0
     assert e["intra_form_small"] in (1, 2) and e["intra_form_large"] in (1, 2) and e["waves_per_chain"] in (1, 2)
     b, _ = D.dsdp_dock_batch(g.handle, Ls, 16, 6, seeds, 4, ws)
-    assert D.dsdp_tune_entries() == picks          # cached: nothing measured again
+    assert D.dsdp_tune_entries(D.DSDP_TUNE_BATCH) == picks          # cached: nothing measured again
     c, _ = D.dsdp_dock_batch(g.handle, Ls, 16, 6, seeds, 4, ws, D.dsdp_params_default(tune=0))
     for k in range(len(ligs)):
         assert poses_bytes(a[k]) == poses_bytes(b[k]) == poses_bytes(c[k])

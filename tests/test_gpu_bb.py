@@ -18,7 +18,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from synth import make_config
+from synth import make_config, make_ligand, PALETTE_T9
 from helpers import box32, random_poses, rmsd
 
 pytestmark = pytest.mark.gpu
@@ -141,6 +141,37 @@ def test_bb_local_opt_split_bitwise(cfg1):
         out.append((form, waves, Pg.tobytes(), Eg.tobytes()))
     for form, waves, p, e in out[1:]:
         assert p == out[0][2] and e == out[0][3], (form, waves)
+
+
+@pytest.mark.parametrize("shape", [(20, 4), (45, 10), (64, 31)])
+def test_bb_split_bitwise_every_pair_class(cfg1, shape):
+    # the pair-slot split over 1-4 waves on each pair-list variant (8, 16 and 32
+    # pairs per lane), in local optimisation and in the search
+    cfg, _, _ = cfg1
+    gc = _gc()
+    import paper_2303_09916_amd as D
+    rec, box = cfg["receptor"], box32(cfg["box"])
+    g = gc.GpuGrid(rec.xyz, rec.types, box, list(PALETTE_T9))
+    na, nt = shape
+    lig = make_ligand(na, nt, seed=7 * na + nt, palette=PALETTE_T9)
+    L = O.LigandModel(lig)
+    n_pairs, _ = D.dsdp_ligand_info(D.Ligand.from_synth(lig))
+    rng = np.random.default_rng(na)
+    lo = np.asarray(g.origin, dtype=np.float64)
+    hi = lo + (np.asarray(g.n) - 1) * box["spacing"]
+    P = random_poses(L.n_tors, 32, lo, hi, rng)
+    lo_out, dock_out = [], []
+    for waves in (1, 2, 3, 4):
+        prm = D.dsdp_params_default(optimizer=D.DSDP_OPT_BB, bb_iters=25, intra_form=1, waves_per_chain=waves)
+        Pg, Eg, Ng = gc.gpu_local_opt(g, lig, P, prm)
+        assert np.all(Ng == 26)
+        lo_out.append((Pg.tobytes(), Eg.tobytes()))
+        poses, _, chains, st = gc.gpu_dock(g, lig, 16, 4, 5, 3, prm)
+        assert st.pose_evals == 16 * 4 * 26
+        dock_out.append(([bytes(p) for p in poses], [bytes(c) for c in chains]))
+    log(f"[bb split {na} atoms, {n_pairs} pairs] waves 1-4 bitwise equal")
+    assert all(x == lo_out[0] for x in lo_out[1:])
+    assert all(x == dock_out[0] for x in dock_out[1:])
 
 
 def test_bb_dock_distribution_matches_oracle(cfg1):

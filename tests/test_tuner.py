@@ -1,4 +1,4 @@
-"""The batched search's launch-plan tuner (batch keys, candidate plans, fastest-pick
+"""The search's launch tuner (batch and dock keys, candidate plans, fastest-pick
 selection, per-device cache, concurrent callers) on the host, under
 AddressSanitizer and UBSan, with a scripted measurement in place of trial
 launches."""

@@ -1,6 +1,6 @@
-// Host unit check of the batched search's launch-plan tuner (bucket keys,
-// candidate plans, selection and cache logic) with a scripted measurement in
-// place of trial launches.  Built and run by tests/test_tuner.py with
+// Host unit check of the search's launch tuner (bucket keys, request kinds,
+// candidate plans of batches and docks, selection and cache logic) with a
+// scripted measurement in place of trial launches.  Built and run by tests/test_tuner.py with
 // AddressSanitizer and UBSan.
 #include "tuner.h"
 
@@ -42,6 +42,16 @@ int main()
         const TuneKey k4 = tune_key(0, 128, {s1, s1, s1, s1, s2});   // 4 rounds alike
         CHECK(k4 == k3);
         CHECK(!(tune_key(0, 64, {s1, s2, s1}) == k1) && !(tune_key(1, 128, {s1, s2, s1}) == k1));
+        // the kind of request is part of the key
+        const TuneKey d1 = tune_key(0, 128, {s1}, kTuneDockBfgs), d2 = tune_key(0, 128, {s1}, kTuneDockBb);
+        CHECK(!(d1 == d2) && !(d1 == tune_key(0, 128, {s1})) && d1 == tune_key(0, 128, {s1}, kTuneDockBfgs));
+    }
+    // dock candidates: pair lists at 4, 3, 2, 1 waves, then atom lists alike
+    {
+        CHECK(kDockCandidates == 8 && candidates_of(kTuneBatch) == kPlans && candidates_of(kTuneDockBb) == 8);
+        const int form[8] = {1, 1, 1, 1, 2, 2, 2, 2}, waves[8] = {4, 3, 2, 1, 4, 3, 2, 1};
+        for (int i = 0; i < 8; i++) CHECK(dock_candidate(i).form == form[i] && dock_candidate(i).waves == waves[i]);
+        CHECK(dock_candidate(-1).waves == 4 && dock_candidate(8).form == 1);
     }
     // candidate plans: plan 0 is the fixed rule (atom lists, one wave); the
     // layout of a ligand follows its pair class
@@ -73,6 +83,15 @@ int main()
         CHECK(t.entries(1).empty());
         const TuneKey k1 = tune_key(1, 128, {shape_bucket(32, 355, 13)});   // another device measures again
         CHECK(t.pick(k1, m, p) && calls == 2 * kPlans && t.entries(1).size() == 1);
+        // a dock key of the same shape is another entry, over the dock candidates
+        const TuneKey kd = tune_key(0, 128, {shape_bucket(32, 355, 13)}, kTuneDockBfgs);
+        int q = -1;
+        CHECK(!t.find(kd, q) && q == -1);
+        CHECK(t.pick(kd, [&](int c) { calls++; return c == 6 ? 1.0f : 2.0f; }, q) && q == 6);
+        CHECK(calls == 2 * kPlans + kDockCandidates && t.entries(0).size() == 2);
+        int r = -1;
+        CHECK(t.find(kd, r) && r == 6);   // read from the cache, nothing measured
+        CHECK(calls == 2 * kPlans + kDockCandidates);
         t.clear();
         CHECK(t.entries(0).empty() && t.hits() == 0);
     }
