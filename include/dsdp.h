@@ -319,7 +319,10 @@ dsdp_status dsdp_local_opt(dsdp_grids g, const dsdp_ligand *lig, const float *d_
  *   stats      nullable host: work counters and device time.
  * Synchronous: returns after the results are on the host.  A chain result
  * depends only on (seed, chain index, ligand, grids, params): not on n_chains,
- * on other chains or on launch shape.
+ * on other chains or on launch shape.  With prm->tune = 1 and layout and waves
+ * left to the library, the first dock of a make-up (optimiser, ligand shape,
+ * chain count) on a device first times the candidate launch shapes on a short
+ * trial in d_ws (see dsdp_tune_entries); later docks reuse the pick.
  */
 dsdp_status dsdp_dock(dsdp_grids g, const dsdp_ligand *lig, int32_t n_chains, int32_t n_steps, uint64_t seed,
                       const dsdp_params *prm, int32_t top_k, void *d_ws, size_t ws_bytes, void *stream,
