@@ -339,7 +339,7 @@ struct ChainL {
 
 constexpr int kMaxWaves = 4;     // waves per chain (concurrent line-search trials)
 constexpr int kMiscGp = 40;      // slot of g.p in misc
-constexpr int kMiscBBa = 41;     // slot of the Barzilai-Borwein step length in misc
+constexpr int kMiscBBa = 41;     // slots 41, 42: the Barzilai-Borwein step length (alternating rounds)
 constexpr int kOptBB = 1;        // SearchParams::optimizer value of Barzilai-Borwein
 
 __host__ __device__ inline int rup4(int v) { return (v + 3) & ~3; }
@@ -1162,14 +1162,98 @@ __device__ inline float bfgs_step_any(const ChainL &C, int D, int nq, bool upd, 
     return wave_sum(pl * gl);
 }
 
-// Local optimisation of the chain's pose x (LDS, in place), run by all W waves of
-// the workgroup together: BFGS with Armijo backtracking, or the Barzilai-Borwein
-// gradient method (no line search: one point per iteration, the lowest-energy
-// iterate is returned).  Barzilai-Borwein with pair lists spreads each
-// evaluation's intra-ligand pairs over the W waves (eval_energy with parts = W;
-// wave 0 takes the gradient and the step); with atom lists wave 0 works alone,
-// since splitting an atom's list would change the order of its sums.
-//
+// The Barzilai-Borwein gradient method (the paper's local optimiser, Section 2,
+// second modification) on the chain's pose x (LDS, in place), run by all W waves
+// of the workgroup: iters steps x <- x (+) a p with p = -g and a = s.s / s.y
+// after a step with s.y > 0 (capped at bb_step_max), else bb_step0; no line
+// search; the lowest-energy iterate is returned (and left in x).  With pair
+// lists each evaluation's pairs are spread over the W waves (eval_energy with
+// parts = W); with atom lists wave 0 works alone, since splitting an atom's list
+// would change the order of its sums.  Wave 0 keeps the iteration in registers
+// (lane l: pose coordinate l, gradient component l), so a step costs no LDS
+// round trip besides the gradient's; the other waves form the same trial poses
+// from the gradient and step length wave 0 leaves in LDS at each round's end.
+template <int PPL, int NBW>
+__device__ Energy local_opt_bb(const LigL &L, const Layout &lay, float *wave_base, const ChainL &C,
+                               const IntraRegs<PPL, NBW> &pr, const GridView &G, const SearchParams &P, float *x,
+                               int &evals, int W)
+{
+    const int lane = lane_id(), w = wave_id(), D = L.D, nx = L.nx;
+    const WaveL S = make_wave(wave_base + w * lay.wave_words, lay);
+    const bool split = PPL > 0 && W > 1;
+    float4 *const pf0 = make_wave(wave_base, lay).pf;
+    if (split || w == 0) {
+        float xr = lane < nx ? x[lane] : 0.f;   // the current iterate
+        float xbr = xr;                         // the lowest-energy iterate (wave 0)
+        float gr = 0.f;                         // its gradient, lane l < D: component l
+        float a = P.bb_step0;                   // the step length
+        Energy Eb;
+        for (int it = 0; it <= P.bb_iters; it++) {
+            float tr = xr;
+            if (it > 0) {
+                // trial = x (+) a p, p = -g: position and torsions lane by lane
+                // (torsion lane l takes gradient component l - 1), the rotation as
+                // a quaternion product; the same roundings as stepping along a
+                // stored direction -g
+                const float gsh = dpp<0x138>(gr);   // wave_shr:1, lane l gets lane l - 1
+                const float4 dq = quat_of_rotvec(a * -read_lane(gr, 3), a * -read_lane(gr, 4), a * -read_lane(gr, 5));
+                const float4 q = quat_normalize(
+                    quat_mul(dq, make_float4(read_lane(xr, 3), read_lane(xr, 4), read_lane(xr, 5), read_lane(xr, 6))));
+                const bool tors = lane >= 7 && lane < nx;
+                const float lin = xr + a * -(lane < 3 ? gr : (tors ? gsh : 0.f));
+                const float qc = lane == 3 ? q.x : (lane == 4 ? q.y : (lane == 5 ? q.z : q.w));
+                const float th = wrap_angle(tors ? lin : 0.f);
+                tr = lane < 3 ? lin : (lane < 7 ? qc : th);
+            }
+            if (lane < nx) S.trial[lane] = tr;
+            wave_sync();
+            const Energy e = eval_energy(L, S, pr, G, S.trial, P.wall_slope, split ? w : 0, split ? W : 1, pf0);
+            evals++;
+            if (w == 0) {
+                eval_gradient(L, S, pr, G, S.trial, P.wall_slope, S.gt);
+                const float gn = lane < D ? S.gt[lane] : 0.f;
+                if (it > 0) {
+                    // s = a p, y = g_new - g; the next length s.s / s.y when s.y > 0
+                    const float sl = lane < D ? a * -gr : 0.f, yl = lane < D ? gn - gr : 0.f;
+                    const float sy = wave_sum(sl * yl), ss = wave_sum(sl * sl);
+                    a = sy > 0.f ? fminf(ss / sy, P.bb_step_max) : P.bb_step0;
+                    if (e.total < Eb.total) {
+                        Eb = e;
+                        xbr = tr;
+                    }
+                } else {
+                    Eb = e;
+                    xbr = tr;
+                }
+                gr = gn;
+                if (split && it < P.bb_iters) {
+                    // two alternating slots (C.g, C.s: unused by this method): a
+                    // round's are read before the next round's energy barrier,
+                    // after which wave 0 writes the other
+                    if (lane < D) C.g[(it & 1) * (C.s - C.g) + lane] = gr;
+                    if (lane == 0) C.misc[kMiscBBa + (it & 1)] = a;
+                }
+            }
+            xr = tr;
+            if (split && it < P.bb_iters) {
+                __syncthreads();   // wave 0's gradient and step length are stored
+                if (w != 0) {
+                    gr = lane < D ? C.g[(it & 1) * (C.s - C.g) + lane] : 0.f;
+                    a = C.misc[kMiscBBa + (it & 1)];
+                }
+            }
+        }
+        if (w == 0) {
+            if (lane < nx) x[lane] = xbr;
+            put_energy(C.et, Eb);
+        }
+    } else {
+        evals += P.bb_iters + 1;   // the count wave 0 makes
+    }
+    __syncthreads();
+    return get_energy(C.et);
+}
+
 // BFGS with Armijo backtracking on the chain's pose x (LDS, in place), run by all
 // W waves of the workgroup together.  The line search evaluates the energies of
 // W consecutive trials at once (alpha_t = shrink^t, one per wave) and accepts
@@ -1185,19 +1269,14 @@ __device__ Energy local_opt_group(const LigL &L, const Layout &lay, float *wave_
                                   const IntraRegs<PPL, NBW> &pr, const GridView &G, const SearchParams &P, float *x,
                                   int &evals, int W)
 {
+    if (P.optimizer == kOptBB) return local_opt_bb(L, lay, wave_base, C, pr, G, P, x, evals, W);
     const int lane = lane_id(), w = wave_id(), D = L.D;
     const WaveL S = make_wave(wave_base + w * lay.wave_words, lay);
-    const bool bb = P.optimizer == kOptBB;
-    const bool split = bb && PPL > 0 && W > 1;   // every wave takes part in each evaluation
-    float4 *const pf0 = make_wave(wave_base, lay).pf;
-    const int iters = bb ? P.bb_iters : P.bfgs_iters;
-    Energy Ex, Eb;
+    Energy Ex;
     float gp = 0.f;
     int it = 0;           // iterations done
     int t0 = -1;          // first line-search trial of this round; -1: the start evaluation
     float alpha0 = 1.f;   // alpha of the round's first trial
-    float bb_a = P.bb_step0;   // Barzilai-Borwein step length (wave 0)
-    float *xb = C.H;           // Barzilai-Borwein: lowest-energy iterate (the matrix is unused)
     const int Dp = lay.Dp;
     float s_l = 0.f, y_l = 0.f, g_l = 0.f, ys = 0.f;   // wave 0: this iteration's s, y, new g; s.y
     // Every evaluation of the local optimisation goes through the one energy call
@@ -1207,11 +1286,8 @@ __device__ Energy local_opt_group(const LigL &L, const Layout &lay, float *wave_
     for (;;) {
         bool active;
         if (t0 < 0) {
-            active = split || w == 0;
+            active = w == 0;
             if (active && lane < L.nx) S.trial[lane] = x[lane];
-        } else if (bb) {
-            active = split || w == 0;
-            if (active) pose_step(L, x, bb_a, C.p, S.trial);
         } else {
             active = t0 + w < P.ls_trials;
             if (active) {
@@ -1222,17 +1298,16 @@ __device__ Energy local_opt_group(const LigL &L, const Layout &lay, float *wave_
         }
         if (active) {
             wave_sync();
-            const Energy e = eval_energy(L, S, pr, G, S.trial, P.wall_slope, split ? w : 0, split ? W : 1, pf0);
-            if (!split || w == 0) put_energy(C.et + 4 * w, e);
+            put_energy(C.et + 4 * w, eval_energy(L, S, pr, G, S.trial, P.wall_slope));
         }
         __syncthreads();
         // the one evaluation of this round whose gradient is needed: wave 0's for
-        // the start point and a Barzilai-Borwein iterate; in a line search, the
-        // accepted trial's (decided alike in every wave, so the barrier below is
-        // taken by all or none), and none when every trial is rejected
+        // the start point; in a line search, the accepted trial's (decided alike
+        // in every wave, so the barrier below is taken by all or none), and none
+        // when every trial is rejected
         int gw = 0, acc_slot = -1;
         float alpha_acc = 0.f;
-        if (t0 >= 0 && !bb) {
+        if (t0 >= 0) {
             float a = alpha0;
             float4 et4[kMaxWaves];
 #pragma unroll
@@ -1272,7 +1347,7 @@ __device__ Energy local_opt_group(const LigL &L, const Layout &lay, float *wave_
             if (w == 0 && lane < Dp) {
                 g_l = lane < D ? S.gt[lane] : 0.f;
                 C.g[lane] = g_l;
-                if (!bb && lane < D) {
+                if (lane < D) {
                     float4 *row = reinterpret_cast<float4 *>(C.H + lane * C.hs);
                     for (int q = 0; q < (Dp >> 2); q++) {
                         const int c = 4 * q;
@@ -1281,32 +1356,6 @@ __device__ Energy local_opt_group(const LigL &L, const Layout &lay, float *wave_
                     }
                 }
             }
-            if (bb) {
-                Eb = Ex;
-                if (w == 0 && lane < L.nx) xb[lane] = x[lane];
-            }
-        } else if (bb) {
-            // s = a p (p = -g), y = g_new - g; the next length is s.s / s.y when
-            // s.y > 0 (capped), else the first length; keep the lowest iterate
-            const Energy En = get_energy(C.et);
-            evals++;
-            if (w == 0) {
-                float sl = 0.f, yl = 0.f;
-                if (lane < D) {
-                    sl = bb_a * C.p[lane];
-                    yl = S.gt[lane] - C.g[lane];
-                    C.g[lane] = S.gt[lane];
-                }
-                const float sy = wave_sum(sl * yl), ss = wave_sum(sl * sl);
-                bb_a = sy > 0.f ? fminf(ss / sy, P.bb_step_max) : P.bb_step0;
-                if (split && lane == 0) C.misc[kMiscBBa] = bb_a;
-                if (lane < L.nx) {
-                    x[lane] = S.trial[lane];
-                    if (En.total < Eb.total) xb[lane] = S.trial[lane];
-                }
-            }
-            if (En.total < Eb.total) Eb = En;
-            it++;
         } else {
             const Energy Et = get_energy(C.et + 4 * acc_slot);
             if (w == acc_slot) {
@@ -1331,21 +1380,17 @@ __device__ Energy local_opt_group(const LigL &L, const Layout &lay, float *wave_
             Ex = Et;
             it++;
         }
-        if (it >= iters) break;
-        // direction of the next iteration: p = -g (Barzilai-Borwein; after the
-        // start evaluation of BFGS, where H = I), else the BFGS update of H with
-        // this iteration's s, y when s.y > 0 and p = -H g (by the accepted trial's
-        // wave, which holds s, y and g)
-        if (w == 0 && (bb || t0 < 0)) {
+        if (it >= P.bfgs_iters) break;
+        // direction of the next iteration: p = -g after the start evaluation
+        // (H = I), else the BFGS update of H with this iteration's s, y when
+        // s.y > 0 and p = -H g (by the accepted trial's wave, which holds s, y
+        // and g)
+        if (w == 0 && t0 < 0) {
             wave_sync();
-            if (bb) {
-                if (lane < D) C.p[lane] = -C.g[lane];
-            } else {
-                const float pl = -g_l;
-                if (lane < Dp) C.p[lane] = pl;
-                const float g_p = wave_sum(pl * g_l);
-                if (lane == 0) C.misc[kMiscGp] = g_p;
-            }
+            const float pl = -g_l;
+            if (lane < Dp) C.p[lane] = pl;
+            const float g_p = wave_sum(pl * g_l);
+            if (lane == 0) C.misc[kMiscGp] = g_p;
         } else if (w == gw) {
             const bool upd = ys > 0.f;
             float g_p;
@@ -1359,13 +1404,8 @@ __device__ Energy local_opt_group(const LigL &L, const Layout &lay, float *wave_
         }
         __syncthreads();
         gp = C.misc[kMiscGp];
-        if (split && t0 >= 0) bb_a = C.misc[kMiscBBa];
         t0 = 0;
         alpha0 = 1.f;
-    }
-    if (bb) {
-        if (w == 0 && lane < L.nx) x[lane] = xb[lane];
-        Ex = Eb;
     }
     __syncthreads();
     return Ex;
