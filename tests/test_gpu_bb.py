@@ -43,7 +43,7 @@ def cfg1():
     return cfg, ref, g
 
 
-@pytest.mark.parametrize("iters", [2, 5])
+@pytest.mark.parametrize("iters", [0, 1, 2, 5])
 def test_bb_local_opt_parity_short(cfg1, iters):
     cfg, ref, g = cfg1
     gc = _gc()
@@ -133,14 +133,16 @@ def test_bb_local_opt_split_bitwise(cfg1):
     rng = np.random.default_rng(13)
     lo, hi = ref.origin, ref.origin + (ref.n - 1) * ref.h
     P = random_poses(L.n_tors, 64, lo, hi, rng)
-    out = []
-    for form, waves in ((1, 1), (1, 2), (1, 3), (1, 4), (2, 1), (2, 4)):
-        prm = D.dsdp_params_default(optimizer=D.DSDP_OPT_BB, bb_iters=40, intra_form=form, waves_per_chain=waves)
-        Pg, Eg, Ng = gc.gpu_local_opt(g, lig, P, prm)
-        assert np.all(Ng == 41)
-        out.append((form, waves, Pg.tobytes(), Eg.tobytes()))
-    for form, waves, p, e in out[1:]:
-        assert p == out[0][2] and e == out[0][3], (form, waves)
+    for iters in (40, 1, 0):
+        out = []
+        for form, waves in ((1, 1), (1, 2), (1, 3), (1, 4), (2, 1), (2, 4)):
+            prm = D.dsdp_params_default(optimizer=D.DSDP_OPT_BB, bb_iters=iters, intra_form=form,
+                                        waves_per_chain=waves)
+            Pg, Eg, Ng = gc.gpu_local_opt(g, lig, P, prm)
+            assert np.all(Ng == iters + 1)
+            out.append((form, waves, Pg.tobytes(), Eg.tobytes()))
+        for form, waves, p, e in out[1:]:
+            assert p == out[0][2] and e == out[0][3], (iters, form, waves)
 
 
 @pytest.mark.parametrize("shape", [(20, 4), (45, 10), (64, 31)])

@@ -62,3 +62,21 @@ def test_dock_tuner_pick_cache_and_bits(grid, optimizer, shape):
     s = D.dsdp_dock_static(grid.handle, L, 48, 5, 21, 4, D.dsdp_params_default(**base), want_chains=True)
     assert [bytes(p) for p in s[0]] == ref[0] and [bytes(c) for c in s[2]] == ref[1]
     assert D.dsdp_tune_entries(kind) == [e]
+
+
+def test_dock_tuner_edges(grid):
+    # one chain, one step, and zero steps (no trial: the fixed rule); every pick
+    # gives the fixed rule's bits
+    import gpu_common as gc
+    import paper_2303_09916_amd as D
+    lig = make_ligand(24, 5, seed=77, palette=PALETTE_T9)
+    D.dsdp_tune_reset()
+    for n_chains, n_steps in ((1, 1), (1, 3), (5, 2)):
+        a = gc.gpu_dock(grid, lig, n_chains, n_steps, 3, 1, D.dsdp_params_default())
+        b = gc.gpu_dock(grid, lig, n_chains, n_steps, 3, 1, D.dsdp_params_default(tune=0))
+        assert chains_bytes(a) == chains_bytes(b), (n_chains, n_steps)
+    e = D.dsdp_tune_entries(D.DSDP_TUNE_DOCK_BFGS)
+    assert sorted(x["chains"] for x in e) == [1, 5]          # one entry per make-up, whatever the length
+    before = D.dsdp_tune_entries()
+    z = gc.gpu_dock(grid, lig, 7, 0, 3, 1, D.dsdp_params_default())
+    assert z[3].pose_evals == 0 and D.dsdp_tune_entries() == before   # zero steps: nothing measured
