@@ -4,6 +4,8 @@ documented status codes before touching the device."""
 import ctypes as C
 import os
 import re
+import shutil
+import subprocess
 
 import numpy as np
 import pytest
@@ -177,3 +179,21 @@ def test_scheduler_host_logic():
     info = D.dsdp_sched_get_info(h)
     assert (info.queued, info.running, info.ticks, info.completed) == (0, 0, 0, 0)
     D.dsdp_sched_destroy(h)
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="needs gcc")
+def test_struct_layouts_match_header(tmp_path):
+    """Every public struct's size and field offsets as the C compiler lays them
+    out from include/dsdp.h equal the Python binding's ctypes mirrors."""
+    exe = str(tmp_path / "abi_layout_check")
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"),
+                    os.path.join(ROOT, "tests", "abi_layout_check.c"), "-o", exe], check=True)
+    out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout
+    n = 0
+    for line in out.splitlines():
+        struct, field, value = line.split()
+        T = getattr(D, struct)
+        got = C.sizeof(T) if field == "sizeof" else getattr(T, field).offset
+        assert got == int(value), (struct, field, got, value)
+        n += 1
+    assert n > 40
