@@ -122,8 +122,8 @@ def test_eval_parity_grid_stress_maps():
     eval_check(ref, g, lig, P, "cfg3 eval")
 
 
-def endpoint_check(ref, g, lig, iters, n, seed, label):
-    """BFGS endpoints after `iters` iterations from n random starts near the
+def endpoint_check(ref, g, lig, iters, n, seed, label, bb=False):
+    """BFGS (or, with bb, Barzilai-Borwein) endpoints after `iters` iterations from n random starts near the
     pocket and across the box.  The oracle's own endpoints move under float32-level
     input noise (1e-7 relative) by more than 1e-3 A for a share of the starts
     that grows with the iterations and with the receptor's clashes (the first
@@ -136,8 +136,12 @@ def endpoint_check(ref, g, lig, iters, n, seed, label):
     gc = _gc()
     import paper_2303_09916_amd as D
     L = O.LigandModel(lig)
-    prm_o = O.default_params(bfgs_iters=iters)
-    prm_g = D.dsdp_params_default(bfgs_iters=iters)
+    if bb:
+        prm_o = O.default_params(optimizer=O.OPT_BB, bb_iters=iters)
+        prm_g = D.dsdp_params_default(optimizer=D.DSDP_OPT_BB, bb_iters=iters)
+    else:
+        prm_o = O.default_params(bfgs_iters=iters)
+        prm_g = D.dsdp_params_default(bfgs_iters=iters)
     rng = np.random.default_rng(seed)
     lo, hi = ref.origin, ref.origin + (ref.n - 1) * ref.h
     c = 0.5 * (lo + hi)
@@ -177,6 +181,13 @@ def endpoint_check(ref, g, lig, iters, n, seed, label):
 def test_local_opt_endpoints_dsdp_shaped(cfg2, iters):
     cfg, ref, g = cfg2
     endpoint_check(ref, g, cfg["ligands"][0], iters, 300, 40 + iters, f"cfg2 local opt K={iters}")
+
+
+@pytest.mark.parametrize("iters", [2, 5])
+def test_bb_local_opt_endpoints_dsdp_shaped(cfg2, iters):
+    # the paper's optimiser at the benchmark's size (register-resident step)
+    cfg, ref, g = cfg2
+    endpoint_check(ref, g, cfg["ligands"][0], iters, 300, 60 + iters, f"cfg2 BB local opt K={iters}", bb=True)
 
 
 def chain_replay(L, ref, prm, seed, c, steps, noise=0.0, rng=None):
