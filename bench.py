@@ -23,8 +23,10 @@ Printed JSON line (one):
                events on the call's stream), against the gather roofline measured
                on the same maps (dsdp_gather_probe with the device full of waves),
                with the HBM peak beside it; also its VALU FP32 rate against the
-               non-packed vector peak (78.6 TFLOP/s) and the measured VALU busy
-               fraction from the committed counter profile;
+               published FP32 vector peak (157.3 TFLOP/s) and against the rate of
+               plain FP32 fused multiply-adds measured by dsdp_valu_probe, and its
+               VALU wave-instruction rate (committed counter profile) over the
+               probe's; and the same kernel's gather rate at 1024-8192 chains;
   grid_build   the grid-build stress workload (12000-atom receptor, 40 A box,
                107^3 nodes x 9 maps): device time, receptor pair terms per second,
                VALU rate, and the oracle's cell-list and brute-force builds;
@@ -63,10 +65,9 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 METRIC = "pose evals/s + ligands docked/s on 1 GPU vs plain; p50/p99 dock latency"
-FP32_VALU_PEAK_TFLOPS = 78.6   # 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz (no packed FP32)
+FP32_VALU_PEAK_TFLOPS = 157.3   # MI355X's published FP32 vector peak
 HBM_PEAK_GBPS = 8000.0
-DEVICE_SIMDS = 1024
-CLOCK_GHZ = 2.4
+FLOPS_PER_VALU_INST = 128.0     # a wave64 FP32 fused multiply-add (the VALU probe's instruction)
 
 
 def flops_model(lig, n_pairs, D):
@@ -93,6 +94,24 @@ def flops_model(lig, n_pairs, D):
     energy = 65 * lig.n_atoms + 45 * n_pairs + sum(85 + 63 * depth[k] for k in range(nf))
     gradient = 66 * lig.n_atoms + 18 * n_pairs + sum(23 + 18 * sub[k] for k in range(nf))
     return energy, gradient, 10 * D * D + 60
+
+
+def valu_probe(D, torch, stream, blocks=8192, iters=32768):
+    """Attainable FP32 vector rate of plain (non-packed) fused multiply-adds with
+    the device full of waves (dsdp_valu_probe), and the wave-instruction rate
+    it implies."""
+    ws = torch.empty(D.dsdp_gather_probe_workspace_bytes(blocks), dtype=torch.uint8, device="cuda")
+    flops = max(D.dsdp_valu_probe(blocks, iters, ws, stream=stream) for _ in range(3))
+    del ws
+    print(f"[bench] VALU probe: {flops / 1e12:.1f} TFLOP/s of plain FP32 FMA ({blocks * 4} waves)",
+          file=sys.stderr, flush=True)
+    return {"TFLOPs": flops / 1e12, "waves": blocks * 4, "valu_insts_per_s": flops / FLOPS_PER_VALU_INST}
+
+
+def issue_frac(insts_per_s, probe):
+    """A kernel's VALU wave-instruction rate (from its committed counters) as a
+    fraction of the probe's."""
+    return insts_per_s / probe["valu_insts_per_s"] if insts_per_s and probe else None
 
 
 def profile_value(name, key, source, mc_steps=None):
@@ -525,7 +544,7 @@ def grid_flops_per_pair(T):
     return 10 + 40 * T
 
 
-def grid_leg(D, torch, cfg, stream, reps=5, oracle=True):
+def grid_leg(D, torch, cfg, stream, reps=5, oracle=True, vprobe=None):
     """Grid-build stress: dsdp_build_grids on the 12000-atom receptor and 40 A box
     (107^3 nodes x 9 XS maps).  Device time from HIP events on the call's stream
     (the ~0.2 MB atom upload and the build kernel; the host's binning of the
@@ -584,8 +603,9 @@ def grid_leg(D, torch, cfg, stream, reps=5, oracle=True):
         "valu": {"flops_per_pair": grid_flops_per_pair(T), "achieved_TFLOPs": flops / (ms * 1e-3) / 1e12,
                  "peak_TFLOPs": FP32_VALU_PEAK_TFLOPS,
                  "frac": flops / (ms * 1e-3) / 1e12 / FP32_VALU_PEAK_TFLOPS,
-                 "valu_busy_frac": profile_value("grid_build_kernel_grid_stress.md", "valu_busy_frac",
-                                                 "grid_build.hip")},
+                 "probe_TFLOPs": vprobe["TFLOPs"] if vprobe else None,
+                 "valu_issue_frac_of_probe": issue_frac(
+                     profile_value("grid_build_kernel_grid_stress.md", "valu_insts_per_s", "grid_build.hip"), vprobe)},
     }
     print(f"[bench] grid build: {n[0]}^3 x {T} maps from {rec.n} atoms in {ms:.2f} ms (device), "
           f"{pairs * T / (ms * 1e-3) / 1e9:.1f} G pair terms/s", file=sys.stderr, flush=True)
@@ -776,7 +796,9 @@ def main():
     valu_tflops = flops_launch / avg_search_s / 1e12
     gather_gbps = evals_per_launch * lig.n_atoms * 128 / avg_search_s / 1e9
     traffic = profile_value("tick_kernel_dsdp_shaped_traffic.md", "traffic_bytes_per_launch", "search.hip", n_steps)
-    valu_busy = profile_value("tick_kernel_dsdp_shaped_instruction_mix.md", "valu_busy_frac", "search.hip")
+    vprobe = valu_probe(D, torch, stream)
+    valu_issue = issue_frac(profile_value("tick_kernel_dsdp_shaped_instruction_mix.md", "valu_insts_per_s",
+                                          "search.hip"), vprobe)
 
     out = {
         "metric": METRIC,
@@ -822,7 +844,8 @@ def main():
             "gather_probe": probe,
             "occupancy": occupancy,
             "valu": {"flops_per_eval": fpe, "achieved_TFLOPs": valu_tflops, "peak_TFLOPs": FP32_VALU_PEAK_TFLOPS,
-                     "frac": valu_tflops / FP32_VALU_PEAK_TFLOPS, "valu_busy_frac": valu_busy},
+                     "frac": valu_tflops / FP32_VALU_PEAK_TFLOPS, "probe_TFLOPs": vprobe["TFLOPs"],
+                     "frac_of_probe": valu_tflops / vprobe["TFLOPs"], "valu_issue_frac_of_probe": valu_issue},
         },
         "cpu_baseline": None,
         "batched": None,
@@ -831,7 +854,7 @@ def main():
     }
 
     if "cfg3" in inp:
-        out["grid_build"] = grid_leg(D, torch, inp["cfg3"], stream, oracle=not args.no_cpu_baseline)
+        out["grid_build"] = grid_leg(D, torch, inp["cfg3"], stream, oracle=not args.no_cpu_baseline, vprobe=vprobe)
     if not args.no_optimizer_leg:
         out["optimizers"] = optimizer_leg(D, torch, cfg, n_steps)
     if not args.no_optimizer_leg:

@@ -238,6 +238,18 @@ size_t dsdp_gather_probe_workspace_bytes(int32_t blocks);
 dsdp_status dsdp_gather_probe(dsdp_grids g, int32_t blocks, int32_t rounds, uint64_t seed, void *d_ws,
                               size_t ws_bytes, void *stream, double *bytes_per_s);
 
+/*
+ * FP32 vector-ALU probe (a measurement entry, not part of the method): blocks x
+ * 256 threads each run eight independent chains of `iters` plain (non-packed)
+ * FP32 fused multiply-adds, the instruction form every kernel here is built
+ * with; *flops_per_s = 2 x 8 x iters x threads / device time (HIP events), the
+ * attainable rate of that arithmetic.  d_ws: device workspace of
+ * dsdp_gather_probe_workspace_bytes(blocks).  blocks in [1, 2^20], iters in
+ * [1, 2^20], else DSDP_ERR_INVALID_ARG.  Synchronous (waits for the stream).
+ */
+dsdp_status dsdp_valu_probe(int32_t blocks, int32_t iters, void *d_ws, size_t ws_bytes, void *stream,
+                            double *flops_per_s);
+
 /* Device workspace bytes for dsdp_site_points with top_n points (0 if top_n is out of range). */
 size_t dsdp_site_points_workspace_bytes(int32_t top_n);
 

@@ -123,6 +123,7 @@ _SIGS = {
                                     C.POINTER(dsdp_dock_stats)]),
     "dsdp_grids_set_site": (C.c_int32, [_vp, C.POINTER(C.c_float), C.c_int32, C.c_float]),
     "dsdp_gather_probe_workspace_bytes": (C.c_size_t, [C.c_int32]),
+    "dsdp_valu_probe": (C.c_int32, [C.c_int32, C.c_int32, _vp, C.c_size_t, _vp, C.POINTER(C.c_double)]),
     "dsdp_gather_probe": (C.c_int32, [_vp, C.c_int32, C.c_int32, C.c_uint64, _vp, C.c_size_t, _vp,
                                       C.POINTER(C.c_double)]),
     "dsdp_site_points_workspace_bytes": (C.c_size_t, [C.c_int32]),
@@ -414,6 +415,13 @@ def dsdp_gather_probe(grids, blocks, rounds, d_ws, seed=1, stream=None):
     r = C.c_double()
     _check(lib().dsdp_gather_probe(grids, int(blocks), int(rounds), C.c_uint64(int(seed)), _ptr(d_ws), _nbytes(d_ws),
                                    _stream(stream), C.byref(r)))
+    return r.value
+
+
+def dsdp_valu_probe(blocks, iters, d_ws, stream=None):
+    """Attainable FP32 fused-multiply-add rate (flops/s) of plain vector instructions."""
+    r = C.c_double()
+    _check(lib().dsdp_valu_probe(int(blocks), int(iters), _ptr(d_ws), _nbytes(d_ws), _stream(stream), C.byref(r)))
     return r.value
 
 

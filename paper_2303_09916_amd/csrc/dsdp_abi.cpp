@@ -847,6 +847,28 @@ dsdp_status dsdp_gather_probe(dsdp_grids g, int32_t blocks, int32_t rounds, uint
     return DSDP_OK;
 }
 
+dsdp_status dsdp_valu_probe(int32_t blocks, int32_t iters, void *d_ws, size_t ws_bytes, void *stream,
+                            double *flops_per_s)
+{
+    if (!flops_per_s) return fail(DSDP_ERR_INVALID_ARG, "result is NULL");
+    if (blocks < 1 || blocks > (1 << 20) || iters < 1 || iters > (1 << 20))
+        return fail(DSDP_ERR_INVALID_ARG, "blocks and iters must be in [1, 2^20]");
+    const size_t need = dsdp_gather_probe_workspace_bytes(blocks);
+    if (!d_ws || ws_bytes < need) return fail(DSDP_ERR_WORKSPACE_TOO_SMALL, "workspace needs %zu bytes", need);
+    hipStream_t s = (hipStream_t)stream;
+    Events ev;
+    HIP_TRY(ev.create(), "event");
+    HIP_TRY(launch_valu_probe(blocks, 1, 1.f, (float *)d_ws, s), "probe launch");
+    HIP_TRY(hipEventRecord(ev.e[0], s), "event");
+    HIP_TRY(launch_valu_probe(blocks, iters, 2.f, (float *)d_ws, s), "probe launch");
+    HIP_TRY(hipEventRecord(ev.e[1], s), "event");
+    HIP_TRY(hipEventSynchronize(ev.e[1]), "probe");
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, ev.e[0], ev.e[1]), "event");
+    *flops_per_s = 2.0 * 8.0 * (double)iters * (double)blocks * 256.0 / (ms * 1e-3);
+    return DSDP_OK;
+}
+
 size_t dsdp_site_points_workspace_bytes(int32_t top_n)
 {
     if (top_n < 1 || top_n > kMaxSitePoints) return 0;

@@ -167,6 +167,7 @@ hipError_t launch_grid_build(const float4 *atoms, const int *cell_start, const i
 size_t search_lds_bytes(const LigHeader &h, int waves);
 // Gather-throughput probe: blocks x 256 threads, rounds of 8-corner gathers each;
 // sink: blocks * 256 floats.
+hipError_t launch_valu_probe(int blocks, int iters, float seed, float *sink, hipStream_t stream);
 hipError_t launch_gather_probe(const GridView &g, int blocks, int rounds, uint32_t seed, float *sink,
                                hipStream_t stream);
 hipError_t launch_eval(const uint32_t *blob, int blob_words, const LigHeader &h, const GridView &g,

@@ -1,5 +1,7 @@
 // Gather-throughput probe of a set of maps on gfx950: the attainable rate of
-// the search's memory access pattern, used as the roofline of its gathers.
+// the search's memory access pattern, used as the roofline of its gathers; and
+// an FP32 vector-ALU probe: the attainable rate of plain (non-packed) fused
+// multiply-adds, the arithmetic the kernels are built with.
 //
 // Every wave picks a centre in the box per round and its 64 lanes gather the
 // eight corners (8 float4 = 128 B) of the cell at centre + a per-lane offset of
@@ -55,7 +57,34 @@ __global__ __launch_bounds__(256) void gather_probe_kernel(GridView G, int round
     sink[blockIdx.x * blockDim.x + threadIdx.x] = acc;
 }
 
+// Every thread runs eight independent chains of `iters` FP32 fused
+// multiply-adds (enough independent work per wave to issue back to back).
+__global__ __launch_bounds__(256) void valu_probe_kernel(int iters, float seed, float *sink)
+{
+    const float t = (float)(threadIdx.x + 1) * 1e-7f;
+    const float m = 0.999f + t, c = seed * 1e-3f;
+    float a[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++) a[k] = seed + (float)k;
+#pragma unroll 4
+    for (int i = 0; i < iters; i++) {
+#pragma unroll
+        for (int k = 0; k < 8; k++) a[k] = fmaf(a[k], m, c);
+    }
+    float s = 0.f;
+#pragma unroll
+    for (int k = 0; k < 8; k++) s += a[k];
+    sink[blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
 }  // namespace
+
+hipError_t launch_valu_probe(int blocks, int iters, float seed, float *sink, hipStream_t stream)
+{
+    if (blocks < 1 || iters < 1) return hipErrorInvalidValue;
+    valu_probe_kernel<<<blocks, 256, 0, stream>>>(iters, seed, sink);
+    return hipGetLastError();
+}
 
 hipError_t launch_gather_probe(const GridView &g, int blocks, int rounds, uint32_t seed, float *sink,
                                hipStream_t stream)
