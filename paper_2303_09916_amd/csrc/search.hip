@@ -825,9 +825,12 @@ __device__ Energy eval_energy(const LigL &L, const WaveL &S, const IntraRegs<PPL
                     const float2 es = pair_term(r2, xa.w + xj[b].w, e >> 6);
                     const bool use = e != kNbrNone && r2 < kCutoff2;
                     e_lane += (use && a < j) ? es.x : 0.f;
-                    fnb.x = use ? add_product(fnb.x, es.y, dx) : fnb.x;
-                    fnb.y = use ? add_product(fnb.y, es.y, dy) : fnb.y;
-                    fnb.z = use ? add_product(fnb.z, es.y, dz) : fnb.z;
+                    // an unused pair adds a zero product, as its zero entry does in
+                    // the pair-list gather (the sum is never -0, so the bits agree)
+                    const float sp = use ? es.y : 0.f;
+                    fnb.x = add_product(fnb.x, sp, dx);
+                    fnb.y = add_product(fnb.y, sp, dy);
+                    fnb.z = add_product(fnb.z, sp, dz);
                 }
                 word = nword;
 #pragma unroll
