@@ -198,15 +198,20 @@ def _box(box):
     return b
 
 
+_ATOM_DTYPE = np.dtype([("x", np.float32), ("y", np.float32), ("z", np.float32), ("xs_type", np.int32)])
+
+
 def atoms_array(xyz, types):
-    """(n,3) coordinates + (n,) XS types -> ctypes dsdp_atom array."""
+    """(n,3) coordinates + (n,) XS types -> ctypes dsdp_atom array (one copy of
+    a packed numpy record array)."""
     xyz = np.asarray(xyz, dtype=np.float32).reshape(-1, 3)
     types = np.asarray(types, dtype=np.int32).reshape(-1)
-    arr = (dsdp_atom * max(len(types), 1))()
-    for i in range(len(types)):
-        arr[i].x, arr[i].y, arr[i].z = (float(v) for v in xyz[i])
-        arr[i].xs_type = int(types[i])
-    return arr
+    n = len(types)
+    rec = np.zeros(max(n, 1), dtype=_ATOM_DTYPE)
+    rec["x"][:n], rec["y"][:n], rec["z"][:n] = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+    rec["xs_type"][:n] = types
+    assert _ATOM_DTYPE.itemsize == C.sizeof(dsdp_atom)
+    return (dsdp_atom * max(n, 1)).from_buffer_copy(rec.tobytes())
 
 
 class Ligand:
