@@ -1,18 +1,22 @@
-// Pose evaluation, BFGS local optimisation, Monte Carlo chains and ranking on gfx950.
+// Pose evaluation, local optimisation (BFGS or Barzilai-Borwein), Monte Carlo
+// chains and ranking on gfx950.
 //
 // Paper: Section 2, "Binding pose search" (Vina scoring kept; score-and-gradient
 // grids with trilinear interpolation, Appendix eqs. 2 and 4; Vina's BFGS local
-// optimiser, ref. [36]) and the parallelisation paragraph (many short,
-// independent Monte Carlo copies; results post-processed into ranked poses).
+// optimiser, ref. [36], or the Barzilai-Borwein method of the second
+// modification) and the parallelisation paragraph (many short, independent
+// Monte Carlo copies; results post-processed into ranked poses).
 //
-// Execution model: one 64-lane wavefront per chain (or per pose).  Lanes map to
-// ligand atoms for kinematics and grid gathers, to atom pairs (strided) for the
-// intra-ligand terms, to fragments for the torque tree and to tangent
-// coordinates for the BFGS vectors.  The ligand description lives in LDS (shared
-// by the waves of a workgroup); each wave owns an LDS region with its
-// coordinates, forces, frames, BFGS matrix and poses.  All cross-lane traffic
-// is LDS or butterfly shuffles in a fixed order, so a chain's arithmetic does not
-// depend on which wave, workgroup or launch runs it.
+// Execution model: one workgroup of 1-4 wavefronts per chain (one wavefront per
+// pose for plain evaluations).  Lanes map to ligand atoms for kinematics and
+// grid gathers, to atom pairs (strided) for the intra-ligand terms, to fragments
+// for the torque tree and to tangent coordinates for the BFGS vectors; a chain's
+// extra waves evaluate concurrent line-search trials (BFGS) or share one
+// evaluation's pairs (Barzilai-Borwein).  The ligand description and the chain's
+// state live in LDS (shared by the waves of a workgroup); each wave owns an LDS
+// region with its coordinates, forces, frames and trial pose.  All cross-lane
+// traffic is LDS, DPP or lane reads in a fixed order, so a chain's arithmetic
+// does not depend on which wave, workgroup or launch runs it.
 #include "dsdp_internal.h"
 
 #include <mutex>
