@@ -26,7 +26,10 @@ Printed JSON line (one):
                published FP32 vector peak (157.3 TFLOP/s) and against the rate of
                plain FP32 fused multiply-adds measured by dsdp_valu_probe, and its
                VALU wave-instruction rate (committed counter profile) over the
-               probe's; and the same kernel's gather rate at 1024-8192 chains;
+               probe's; the same kernel's gather rate at 1024-8192 chains; and
+               the pose-scoring kernel alone (energy and gradient of 2^20
+               independent poses of the same ligand, dsdp_eval_poses) against the
+               same gather roofline;
   grid_build   the grid-build stress workload (12000-atom receptor, 40 A box,
                107^3 nodes x 9 maps): device time, receptor pair terms per second,
                VALU rate, and the oracle's cell-list and brute-force builds;
@@ -654,6 +657,47 @@ def gather_probe(D, torch, rec, box, types, maps, gws, stream, n_chains):
             "search_waves": waves, "bytes_per_gather": 128}
 
 
+def scoring_leg(D, torch, cfg, L, maps, gws, stream, peak_GBps, n_poses=1 << 20, reps=10):
+    """The pose-scoring kernel alone (dsdp_eval_poses: energy and gradient of
+    independent poses, one wave per pose) on the workload's ligand and maps, for
+    poses drawn as chains start (root position uniform in the box, uniform
+    random orientation, torsions uniform in [-pi, pi)); inputs resident before
+    the timed calls, each call timed with HIP events on its stream."""
+    rec, box, lig, types = cfg["receptor"], cfg["box"], cfg["ligands"][0], cfg["map_types"]
+    g = D.dsdp_build_grids(rec.xyz, rec.types, box, types, maps, gws, stream)
+    rng = np.random.default_rng(cfg["seed"] + 17)
+    nx = 7 + lig.n_torsions
+    P = np.empty((n_poses, nx), dtype=np.float32)
+    P[:, 0:3] = box["centre"] - box["size"] / 2 + rng.random((n_poses, 3)) * box["size"]
+    q = rng.standard_normal((n_poses, 4))
+    P[:, 3:7] = q / np.linalg.norm(q, axis=1, keepdims=True)
+    P[:, 7:] = rng.uniform(-np.pi, np.pi, (n_poses, lig.n_torsions))
+    d_p = torch.from_numpy(P).to("cuda")
+    d_e = torch.empty((n_poses, 4), dtype=torch.float32, device="cuda")
+    d_g = torch.empty((n_poses, L.D), dtype=torch.float32, device="cuda")
+    ws = torch.empty(D.dsdp_dock_workspace_bytes(L, n_poses), dtype=torch.uint8, device="cuda")
+    D.dsdp_eval_poses(g, L, d_p, n_poses, d_e, d_g, None, ws, stream=stream)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    torch.cuda.synchronize()
+    for e0, e1 in ev:
+        e0.record(stream)
+        D.dsdp_eval_poses(g, L, d_p, n_poses, d_e, d_g, None, ws, stream=stream)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in ev]))
+    finite = bool(torch.isfinite(d_e).all()) and bool(torch.isfinite(d_g).all())
+    D.dsdp_grids_release(g)
+    del d_p, d_e, d_g, ws
+    gbps = n_poses * lig.n_atoms * 128 / (ms * 1e-3) / 1e9
+    print(f"[bench] scoring kernel: {n_poses} poses in {ms:.3f} ms ({n_poses / ms / 1e3:.0f} M poses/s), "
+          f"{gbps:.0f} GB/s of gathers, {gbps / peak_GBps:.2f} of the probe", file=sys.stderr, flush=True)
+    return {"kernel": "eval_kernel", "entry": "dsdp_eval_poses", "poses": n_poses, "calls": reps,
+            "avg_call_ms": ms, "poses_per_s": n_poses / (ms * 1e-3), "bytes_per_pose": lig.n_atoms * 128,
+            "achieved_GBps": gbps, "frac": gbps / peak_GBps, "frac_of_hbm_peak": gbps / HBM_PEAK_GBPS,
+            "outputs_finite": finite,
+            "traffic": profile_value("eval_kernel_dsdp_shaped_scoring.md", "traffic_bytes_per_launch", "search.hip")}
+
+
 def occupancy_leg(D, torch, cfg, L, maps, gws, stream, peak_GBps, chain_counts=(1024, 4096, 8192), n_steps=100):
     """The same search kernel, request and maps with more chains than the
     workload's: the gather rate it reaches once enough chains run at once to
@@ -707,6 +751,8 @@ def main():
                     help="skip the grid-build stress workload (12000 atoms, 107^3 x 9 maps)")
     ap.add_argument("--no-occupancy-leg", dest="occupancy_leg", action="store_false",
                     help="skip the search kernel at 1024-8192 chains (the gather rate with the device full)")
+    ap.add_argument("--no-scoring-leg", dest="scoring_leg", action="store_false",
+                    help="skip the pose-scoring kernel alone (dsdp_eval_poses on 2^20 poses)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one plain device copy of this size (for counter calibration)")
     args = ap.parse_args()
@@ -779,6 +825,7 @@ def main():
     probe = gather_probe(D, torch, rec, box, types, maps, gws, stream, n_chains)
     del dws
     occupancy = occupancy_leg(D, torch, cfg, L, maps, gws, stream, probe["full_GBps"]) if args.occupancy_leg else None
+    scoring = scoring_leg(D, torch, cfg, L, maps, gws, stream, probe["full_GBps"]) if args.scoring_leg else None
     del maps, gws
 
     value = evals / elapsed
@@ -799,6 +846,9 @@ def main():
     vprobe = valu_probe(D, torch, stream)
     valu_issue = issue_frac(profile_value("tick_kernel_dsdp_shaped_instruction_mix.md", "valu_insts_per_s",
                                           "search.hip"), vprobe)
+    if scoring is not None:
+        scoring["valu_issue_frac_of_probe"] = issue_frac(
+            profile_value("eval_kernel_dsdp_shaped_scoring.md", "valu_insts_per_s", "search.hip"), vprobe)
 
     out = {
         "metric": METRIC,
@@ -843,6 +893,7 @@ def main():
             "frac_of_hbm_peak": gather_gbps / HBM_PEAK_GBPS,
             "gather_probe": probe,
             "occupancy": occupancy,
+            "scoring_kernel": scoring,
             "valu": {"flops_per_eval": fpe, "achieved_TFLOPs": valu_tflops, "peak_TFLOPs": FP32_VALU_PEAK_TFLOPS,
                      "frac": valu_tflops / FP32_VALU_PEAK_TFLOPS, "probe_TFLOPs": vprobe["TFLOPs"],
                      "frac_of_probe": valu_tflops / vprobe["TFLOPs"], "valu_issue_frac_of_probe": valu_issue},
