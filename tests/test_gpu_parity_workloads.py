@@ -3,7 +3,8 @@ step.
 
   * Pose energies and gradients on the DSDP-shaped maps (81^3 x 8, the 32-atom /
     7-torsion ligand) and on the grid-stress maps (107^3 x 9), same tolerance
-    rule as the small-box tests.
+    rule as the small-box tests; sampled poses of the benchmark's 2^20-pose
+    scoring launch.
   * Local-optimisation endpoints after 1, 2 and 3 BFGS iterations on the
     DSDP-shaped maps: as close to the oracle's as the oracle's own endpoints are
     to themselves under float32-level input noise, every further miss explained
@@ -101,6 +102,51 @@ def test_eval_parity_dsdp_shaped(cfg2, form):
                form)
     eval_check(ref, g, lig, random_poses(L.n_tors, 40, lo, hi, rng, margin=6.0), f"cfg2 eval form {form} walls",
                form)
+
+
+def test_eval_parity_scoring_launch(cfg2):
+    """The pose-scoring launch as the benchmark times it: 2^20 poses of the
+    DSDP-shaped ligand in one dsdp_eval_poses call (no coordinate output); 96
+    sampled poses against the oracle one by one with the same tolerance rule, the
+    rest finite, and the sampled poses' results equal to a small call's (the
+    launch size does not change a pose's bits)."""
+    import torch
+    import paper_2303_09916_amd as D
+    gc = _gc()
+    cfg, ref, g = cfg2
+    lig = cfg["ligands"][0]
+    L = O.LigandModel(lig)
+    Lg = D.Ligand.from_synth(lig)
+    lo, hi = ref.origin, ref.origin + (ref.n - 1) * ref.h
+    rng = np.random.default_rng(77)
+    n = 1 << 20
+    P = random_poses(L.n_tors, n, lo, hi, rng)
+    d_p = torch.from_numpy(P).cuda()
+    d_e = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+    d_g = torch.empty((n, Lg.D), dtype=torch.float32, device="cuda")
+    ws = gc.dev_bytes(torch, D.dsdp_dock_workspace_bytes(Lg, n))
+    D.dsdp_eval_poses(g.handle, Lg, d_p, n, d_e, d_g, None, ws)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(d_e).all()) and bool(torch.isfinite(d_g).all())
+    idx = np.sort(np.concatenate([[0, n - 1], rng.choice(n, 94, replace=False)]))
+    E = d_e[torch.from_numpy(idx).cuda()].cpu().numpy()
+    G = d_g[torch.from_numpy(idx).cuda()].cpu().numpy()
+    del d_p, d_e, d_g, ws
+    worstE = worstG = 0.0
+    for j, k in enumerate(idx):
+        Eo, go, parts, xo, mass = L.eval(ref, P[k].astype(np.float64), want_mass=True)
+        lever = 1.0 + np.max(np.linalg.norm(xo - P[k, :3], axis=1))
+        tolE = 1e-4 * (mass[0] + mass[1]) + mass[2] + 1e-5
+        tolG = 1e-4 * (np.max(np.abs(go)) + mass[1] * lever) + mass[3] * lever + 1e-5
+        eE = max(abs(E[j, 0] - Eo), abs(E[j, 1] - parts[0]), abs(E[j, 2] - parts[1]), abs(E[j, 3] - parts[2]))
+        eG = np.max(np.abs(G[j] - go))
+        worstE, worstG = max(worstE, eE / tolE), max(worstG, eG / tolG)
+        assert eE <= tolE, (k, E[j], Eo, parts, mass)
+        assert eG <= tolG, (k, G[j], go, mass)
+    Es, Gs, _ = gc.gpu_eval(g, lig, P[idx])
+    assert np.array_equal(Es, E) and np.array_equal(Gs, G)
+    log(f"[cfg2 scoring launch] n={n}, {len(idx)} sampled: worst |dE|/tol = {worstE:.3g}, "
+        f"worst |dg|/tol = {worstG:.3g}; bits equal to a {len(idx)}-pose call")
 
 
 def test_eval_parity_grid_stress_maps():
