@@ -1,4 +1,5 @@
-"""Build libdsdp.so (HIP kernels for gfx950 + the C-ABI host code) in-tree with hipcc."""
+"""Build libdsdp.so (HIP kernels for gfx950 + the C-ABI host code) in-tree with hipcc,
+and the plain C client of its ABI that the tests run (tests/c_client)."""
 import os
 import subprocess
 import sys
@@ -28,6 +29,22 @@ def build(verbose=False, extra=()):
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB
+
+
+def build_c_client(verbose=False):
+    """tests/c_client: a C11 program that uses the library through include/dsdp.h
+    and the HIP runtime only (gcc, no hipcc, no device code of its own)."""
+    exe = os.path.join(ROOT, "tests", "c_client")
+    cmd = ["gcc", "-std=c11", "-O2", "-Wall", "-Wextra", "-D__HIP_PLATFORM_AMD__",
+           "-I", os.path.join(ROOT, "include"), "-I", "/opt/rocm/include",
+           os.path.join(ROOT, "tests", "c_client.c"), "-o", exe + ".tmp",
+           "-L", HERE, "-ldsdp", "-Wl,-rpath,$ORIGIN/../paper_2303_09916_amd",
+           "-L", "/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(exe + ".tmp", exe)
+    return exe
 
 
 if __name__ == "__main__":
