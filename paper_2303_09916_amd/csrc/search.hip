@@ -1789,7 +1789,7 @@ hipError_t launch_eval(const uint32_t *blob, int blob_words, const LigHeader &h,
     const Layout c = make_layout(h.n_atoms, h.n_frags, pf_pairs(h), 6 + h.n_tors, 7 + h.n_tors);
     const size_t wb = (size_t)c.wave_words * 4, bb = (size_t)blob_words * 4;
     const int w = pick_eval_waves(bb, wb);
-    const int blocks = (n + w - 1) / w;
+    const int blocks = (int)(((long)n + w - 1) / w);   // n may be close to INT_MAX
     const size_t lds = bb + w * wb;
 #define DSDP_EVAL(A, B) \
     eval_kernel<A, B><<<blocks, 64 * w, lds, stream>>>(blob, blob_words, g, p, poses, n, energy, grad, xyz)
