@@ -325,6 +325,11 @@ dsdp_status dsdp_local_opt(dsdp_grids g, const dsdp_ligand *lig, const float *d_
  * block), then ranking by e_total and greedy heavy-atom RMSD clustering
  * (keep a pose if its RMSD to every kept pose exceeds rmsd_cluster), up to top_k.
  *   prm        nullable (defaults);
+ *   n_steps    >= 0; a chain counts its evaluations in 32 bits, so n_steps times
+ *              the most one local optimisation can make (1 + bfgs_iters *
+ *              ls_trials, or 1 + bb_iters) must stay below 2^31, else
+ *              DSDP_ERR_UNSUPPORTED (the same limit holds in dsdp_dock_batch and
+ *              dsdp_sched_submit);
  *   out        host [top_k] ranked poses;  out_xyz nullable host [top_k][n_atoms][3];
  *   n_out      number of poses written (<= top_k);
  *   chains_out nullable host [n_chains]: every chain's best pose;

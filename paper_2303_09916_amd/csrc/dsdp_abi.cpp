@@ -450,6 +450,23 @@ dsdp_status check_params(const dsdp_params *p)
     return DSDP_OK;
 }
 
+// A chain counts its evaluations in 32 bits: n_steps local optimisations of at
+// most 1 + bfgs_iters * ls_trials (BFGS) or 1 + bb_iters (Barzilai-Borwein)
+// evaluations each must stay below 2^31.
+dsdp_status check_work(const dsdp_params *p, int32_t n_steps)
+{
+    dsdp_params d;
+    if (!p) {
+        dsdp_params_default(&d);
+        p = &d;
+    }
+    const double per_step = p->optimizer == DSDP_OPT_BB ? 1.0 + p->bb_iters : 1.0 + (double)p->bfgs_iters * p->ls_trials;
+    if ((double)n_steps * per_step >= 2147483647.0)
+        return fail(DSDP_ERR_UNSUPPORTED, "n_steps %d x %.0f evaluations per step: a chain's count would exceed 2^31",
+                    n_steps, per_step);
+    return DSDP_OK;
+}
+
 // Workspace layout of the search calls.  The host-written sections (blob arena,
 // tasks, grid views, ranking segments) come first and are uploaded in one copy.
 struct SearchWs {
@@ -1137,6 +1154,7 @@ dsdp_status dock_impl(dsdp_grids g, const dsdp_ligand *lig, int32_t n_chains, in
     if (top_k < 0 || top_k > n_chains) return fail(DSDP_ERR_INVALID_ARG, "top_k %d outside 0..n_chains", top_k);
     if (top_k > 0 && (!out || !n_out)) return fail(DSDP_ERR_INVALID_ARG, "out/n_out is NULL");
     dsdp_status st = check_params(prm);
+    if (!st) st = check_work(prm, n_steps);
     if (st) return st;
     Prepared pl0, alt;
     st = prepare_ligand(lig, g->map_of_type, pl0, intra_ctx(prm, n_chains, false));
@@ -1461,6 +1479,7 @@ dsdp_status dsdp_dock_batch(dsdp_grids g, const dsdp_ligand *ligs, int32_t n_lig
     if (top_k < 0 || top_k > n_chains) return fail(DSDP_ERR_INVALID_ARG, "top_k %d outside 0..n_chains", top_k);
     if (top_k > 0 && (!out || !n_out)) return fail(DSDP_ERR_INVALID_ARG, "out/n_out is NULL");
     dsdp_status st = check_params(prm);
+    if (!st) st = check_work(prm, n_steps);
     if (st) return st;
     dsdp_params def;
     dsdp_params_default(&def);

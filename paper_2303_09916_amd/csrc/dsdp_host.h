@@ -53,6 +53,7 @@ dsdp_status prepare_ligand(const dsdp_ligand *lig, const int *map_of_type, Prepa
 // blob words of the larger of the two forms (workspace sizing without params); 0 on invalid input
 size_t max_blob_words(const dsdp_ligand *lig);
 dsdp_status check_params(const dsdp_params *p);
+dsdp_status check_work(const dsdp_params *p, int32_t n_steps);
 SearchParams to_search(const dsdp_params *p);
 int device_cus();
 size_t device_max_lds();

@@ -343,8 +343,10 @@ dsdp_status dsdp_sched_submit(dsdp_sched s, int32_t receptor_id, const dsdp_liga
         return fail(DSDP_ERR_INVALID_ARG, "n_chains %d outside 1..slot capacity %d", n_chains, s->capacity);
     if (n_steps < 0) return fail(DSDP_ERR_INVALID_ARG, "n_steps < 0");
     if (top_k < 0 || top_k > n_chains) return fail(DSDP_ERR_INVALID_ARG, "top_k %d outside 0..n_chains", top_k);
+    dsdp_status st = check_work(&s->prm, n_steps);
+    if (st) return st;
     std::unique_ptr<Request> q(new Request());
-    dsdp_status st = prepare_ligand(lig, s->receptors[(size_t)receptor_id].map_of_type, q->pl,
+    st = prepare_ligand(lig, s->receptors[(size_t)receptor_id].map_of_type, q->pl,
                                     intra_ctx(&s->prm, s->capacity, true));
     if (st) return st;
     if (search_lds_bytes(q->pl.h, 1) > device_max_lds())

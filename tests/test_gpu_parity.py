@@ -368,6 +368,20 @@ def test_edge_cases(cfg1):
     if not set(lig.types.tolist()) <= set(cfg["map_types"]):
         with pytest.raises(D.DsdpError):
             gc.gpu_dock(g, lig, 4, 2, 1, 2)
+    # a chain counts its evaluations in 32 bits: requests whose worst case would
+    # overflow the count (steps x evaluations per local optimisation >= 2^31) are
+    # rejected before any launch, in every entry point
+    L = D.Ligand.from_synth(cfg["ligands"][0])
+    ws = gc.dev_bytes(g.torch, max(D.dsdp_dock_workspace_bytes(L, 4), D.dsdp_dock_batch_workspace_bytes([L], 4)))
+    bb = D.dsdp_params_default(optimizer=D.DSDP_OPT_BB, bb_iters=1000)
+    for call in (lambda: D.dsdp_dock(g.handle, L, 4, 20_000_000, 1, 2, ws),        # 20 M x 201
+                 lambda: D.dsdp_dock(g.handle, L, 4, 3_000_000, 1, 2, ws, bb),     # 3 M x 1001
+                 lambda: D.dsdp_dock_batch(g.handle, [L], 4, 20_000_000, [1], 2, ws)):
+        with pytest.raises(D.DsdpError) as e:
+            call()
+        assert e.value.status == D.DSDP_ERR_UNSUPPORTED
+    # the largest accepted request of the default search: nothing launched here
+    assert 10_000_000 * 201 < 2 ** 31
 
 
 @pytest.mark.parametrize("shape", [(20, 4), (32, 7), (45, 12), (60, 15), (64, 31), (12, 0), (2, 1)])

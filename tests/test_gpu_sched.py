@@ -146,5 +146,12 @@ def test_sched_cancel_running_and_queued():
         ws = gc.dev_bytes(torch, D.dsdp_dock_workspace_bytes(L, 16))
         p_alone = D.dsdp_dock(g.handle, L, 16, 4, 3, 3, ws, want_xyz=False)[0]
         assert [bytes(p) for p in poses] == [bytes(p) for p in p_alone]
+        # a request whose chains' 32-bit evaluation counts could overflow is
+        # refused at submission and leaves the scheduler as it was
+        with pytest.raises(D.DsdpError) as e:
+            D.dsdp_sched_submit(h, rid, L, 16, 20_000_000, 4, 3)
+        assert e.value.status == D.DSDP_ERR_UNSUPPORTED
+        info = D.dsdp_sched_get_info(h)
+        assert (info.running, info.queued, info.free_slots) == (0, 0, cap)
     finally:
         D.dsdp_sched_destroy(h)
