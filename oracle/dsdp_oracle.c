@@ -399,8 +399,8 @@ enum { ORC_MODE_EQ4 = 0, ORC_MODE_EQ3 = 1, ORC_MODE_DIRECT = 2 };
  *   [0, n-1] is clamped onto the box face; the atom then pays the wall energy
  *   wall_slope * (distance outside, in A) and its gradient along that axis is the
  *   wall's outward slope (the map gradient along a clamped axis is dropped, since
- *   the clamped energy does not change along it).  Reading of "a restrained wall
- *   is needed" (Section 3, site-prediction paragraph).
+ *   the clamped energy does not change along it).  This is our reading of the
+ *   wall restraint that Section 3 calls for (site-prediction paragraph).
  *   Cell index i = min(floor(u), n-2), fraction p = u - i (a point on the upper
  *   face gets i = n-2, p = 1).  Corner weights are products of p and 1-p (eq. 2).
  *   mode EQ4: gradient = the same weights applied to the stored gradients (eq. 4).

@@ -1,10 +1,10 @@
 // Host side of libdsdp.so: the C ABI declared in include/dsdp.h.
 //
 // Validates inputs, prepares the receptor (cell binning) and the ligand (torsion
-// tree, intra-ligand pair list, packed blob) on the host -- the paper's "copies
-// are initialised and packaged on the CPU" step (Section 2, parallelisation
-// paragraph; Figure 4) -- uploads them, launches the gfx950 kernels and turns
-// the ranked chain results into output poses.
+// tree, intra-ligand pair list, packed blob) on the host -- the step in which
+// the paper prepares the copies' initial data on the CPU (Section 2,
+// parallelisation paragraph; Figure 4) -- uploads them, launches the gfx950
+// kernels and turns the ranked chain results into output poses.
 #include "../../include/dsdp.h"
 #include "dsdp_internal.h"
 #include "dsdp_host.h"
