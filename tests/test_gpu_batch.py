@@ -52,6 +52,34 @@ def test_batch_equals_alone(site, steps_per_tick):
     assert st.local_opts == len(ligs) * n_chains * n_steps
 
 
+@pytest.mark.parametrize("form", [0, 1])
+def test_batch_equals_alone_barzilai_borwein(site, form):
+    """The paper's optimiser in a batch: every ligand's result is bitwise that of
+    docking it alone with the same parameters, with the library's layouts (atom
+    lists in a mixed launch, one wave per chain) and with pair lists forced
+    (each evaluation's pairs spread over the chain's waves) against a different
+    wave count alone."""
+    import gpu_common as gc
+    import paper_2303_09916_amd as D
+    g = site
+    ligs = ligands()
+    Ls = [D.Ligand.from_synth(l) for l in ligs]
+    n_chains, n_steps, top_k = 16, 4, 5
+    seeds = [2000 + 13 * k for k in range(len(ligs))]
+    prm_b = D.dsdp_params_default(optimizer=D.DSDP_OPT_BB, bb_iters=12, intra_form=form,
+                                  waves_per_chain=3 if form == 1 else 0)
+    prm_a = D.dsdp_params_default(optimizer=D.DSDP_OPT_BB, bb_iters=12, intra_form=form,
+                                  waves_per_chain=2 if form == 1 else 0)
+    ws = gc.dev_bytes(g.torch, D.dsdp_dock_batch_workspace_bytes(Ls, n_chains))
+    res, st = D.dsdp_dock_batch(g.handle, Ls, n_chains, n_steps, seeds, top_k, ws, prm_b, steps_per_tick=3)
+    total = 0
+    for k, lig in enumerate(ligs):
+        alone, _, _, st1 = gc.gpu_dock(g, lig, n_chains, n_steps, seeds[k], top_k, prm_a)
+        assert poses_bytes(res[k]) == poses_bytes(alone), (k, lig.n_atoms)
+        total += st1.pose_evals
+    assert st.pose_evals == total == len(ligs) * n_chains * n_steps * 13
+
+
 def test_batch_mixed_wave_counts(site):
     """Forcing 1 or 3 waves per chain in the batch changes nothing."""
     import gpu_common as gc

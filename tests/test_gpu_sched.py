@@ -26,17 +26,17 @@ def requests():
             for k, (r, (na, nt), c, s, sd, tk) in enumerate(spec)]
 
 
-def alone(handle, lig, c, s, sd, tk):
+def alone(handle, lig, c, s, sd, tk, params=None):
     import gpu_common as gc
     import paper_2303_09916_amd as D
     torch = gc.torch_cuda()
     L = D.Ligand.from_synth(lig)
     ws = gc.dev_bytes(torch, D.dsdp_dock_workspace_bytes(L, c))
-    poses, _, _, st = D.dsdp_dock(handle, L, c, s, sd, tk, ws, want_xyz=False)
+    poses, _, _, st = D.dsdp_dock(handle, L, c, s, sd, tk, ws, params, want_xyz=False)
     return poses, st
 
 
-def run_sched(pool_bytes_extra, capacity, spt, stagger, evict=False):
+def run_sched(pool_bytes_extra, capacity, spt, stagger, evict=False, params=None):
     import gpu_common as gc
     import paper_2303_09916_amd as D
     torch = gc.torch_cuda()
@@ -45,7 +45,7 @@ def run_sched(pool_bytes_extra, capacity, spt, stagger, evict=False):
     need = [D.dsdp_grids_bytes(b, len(types)) + D.dsdp_build_grids_workspace_bytes(r.n, b) + 1024 for r, b in S]
     maps_part = max(need) + (1 << 20) if evict else sum(need) + (1 << 20)
     pool = gc.dev_bytes(torch, D.dsdp_sched_fixed_bytes(capacity) + maps_part + pool_bytes_extra)
-    h = D.dsdp_sched_create(pool, capacity, spt)
+    h = D.dsdp_sched_create(pool, capacity, spt, params)
     try:
         rids = [D.dsdp_sched_add_receptor(h, r.xyz, r.types, b, types) for r, b in S]
         reqs = requests()
@@ -77,18 +77,28 @@ def run_sched(pool_bytes_extra, capacity, spt, stagger, evict=False):
         D.dsdp_sched_destroy(h)
 
 
-def check_against_alone(out, S, reqs):
+def check_against_alone(out, S, reqs, params=None):
     import gpu_common as gc
     types = list(PALETTE_T9)
     grids = [gc.GpuGrid(r.xyz, r.types, b, types) for r, b in S]
     for k, (r, lig, c, s, sd, tk) in enumerate(reqs):
-        p_alone, st_alone = alone(grids[r].handle, lig, c, s, sd, tk)
+        p_alone, st_alone = alone(grids[r].handle, lig, c, s, sd, tk, params)
         p_s, st_s = out[k]
         assert len(p_s) == len(p_alone), k
         for a, b in zip(p_s, p_alone):
             assert bytes(a) == bytes(b), (k, a.chain, b.chain, a.e_total, b.e_total)
         assert (st_s.pose_evals, st_s.local_opts, st_s.accepted) == \
             (st_alone.pose_evals, st_alone.local_opts, st_alone.accepted), k
+
+
+def test_sched_equals_alone_barzilai_borwein():
+    """The paper's optimiser under the scheduler: every request, submitted in two
+    waves between ticks, equals docking it alone with the same parameters."""
+    import paper_2303_09916_amd as D
+    prm = D.dsdp_params_default(optimizer=D.DSDP_OPT_BB, bb_iters=12)
+    out, info, S, reqs = run_sched(4 << 20, 256, 3, 3, params=prm)
+    assert (info.running, info.queued) == (0, 0)
+    check_against_alone(out, S, reqs, prm)
 
 
 @pytest.mark.parametrize("spt,stagger", [(4, 0), (3, 3), (50, 5)])
