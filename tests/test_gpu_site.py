@@ -1,7 +1,8 @@
 """GPU parity of the adaptive search space (Section 2, "Binding pose search",
 third modification; Figure 3) against the FP64 oracle, through the C ABI:
 pose energies and gradients with the root-position restraint, initial
-positions inside the space, and full searches."""
+positions inside the space, full searches, and batches on restricted maps
+(bitwise the lone docks)."""
 import time
 
 import numpy as np
@@ -104,3 +105,24 @@ def test_site_dock_distribution(site_grids):
     log(f"[site dock distribution] gpu q {qg}, oracle q {qo}, KS p {ks.pvalue:.3f} ({time.time() - t0:.1f}s)")
     assert ks.pvalue > 0.01
     assert np.max(np.abs(qg - qo)) <= 0.25
+
+
+def test_site_batch_equals_alone(site_grids):
+    """A batch on maps with a search space set gives every ligand bitwise the
+    result of its lone dock on the same maps, and every chain starts inside the
+    space."""
+    cfg, pts, ref, g = site_grids
+    import gpu_common as gc
+    import paper_2303_09916_amd as D
+    ligs = [make_ligand(na, nt, seed=500 + na, palette=PALETTE_T9) for na, nt in ((14, 2), (30, 6), (47, 12))]
+    Ls = [D.Ligand.from_synth(l) for l in ligs]
+    n_chains, n_steps, top_k, seeds = 24, 6, 4, [3, 4, 5]
+    ws = gc.dev_bytes(g.torch, D.dsdp_dock_batch_workspace_bytes(Ls, n_chains))
+    res, _ = D.dsdp_dock_batch(g.handle, Ls, n_chains, n_steps, seeds, top_k, ws, steps_per_tick=4)
+    for k, lig in enumerate(ligs):
+        alone, _, _, _ = gc.gpu_dock(g, lig, n_chains, n_steps, seeds[k], top_k)
+        assert [bytes(p) for p in res[k]] == [bytes(p) for p in alone], k
+    _, _, chains, _ = gc.gpu_dock(g, ligs[1], n_chains, 0, seeds[1], 1)
+    P = np.array([list(c.pos) for c in chains], dtype=np.float64)
+    d = np.min(np.linalg.norm(P[:, None, :] - pts[None, :, :].astype(np.float64), axis=2), axis=1)
+    assert np.all(d <= 7.0 + 1e-4)
