@@ -134,6 +134,7 @@ _SIGS = {
     "dsdp_sched_create": (C.c_int32, [_vp, C.c_size_t, C.c_int32, C.c_int32, C.POINTER(dsdp_params), _vp,
                                       C.POINTER(_vp)]),
     "dsdp_sched_destroy": (None, [_vp]),
+    "dsdp_sched_set_site": (C.c_int32, [_vp, C.c_int32, C.POINTER(C.c_float), C.c_int32, C.c_float]),
     "dsdp_sched_add_receptor": (C.c_int32, [_vp, C.POINTER(dsdp_atom), C.c_int32, C.POINTER(dsdp_box),
                                             C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32)]),
     "dsdp_sched_submit": (C.c_int32, [_vp, C.c_int32, C.POINTER(dsdp_ligand), C.c_int32, C.c_int32, C.c_uint64,
@@ -150,12 +151,18 @@ EXPORTED = tuple(_SIGS)
 
 
 def lib():
-    """Load libdsdp.so (built in-tree by build.py).  Raises if it is missing."""
+    """Load libdsdp.so (built in-tree by build.py).  Raises if it is missing.
+
+    torch is imported first: the library then binds to the HIP runtime torch
+    loads (same soname), so the process holds one runtime.  Loaded the other way
+    round, torch would load a second copy of the runtime beside the library's,
+    and whichever initialises second finds no device."""
     global _LIB
     if _LIB is not None:
         return _LIB
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is not built; run paper_2303_09916_amd/build.py (or __graft_entry__.build())")
+    import torch  # noqa: F401  (loads the process's HIP runtime before the library)
     L = C.CDLL(LIB_PATH)
     for name, (res, args) in _SIGS.items():
         f = getattr(L, name)
@@ -474,6 +481,14 @@ def dsdp_sched_add_receptor(h, rec_xyz, rec_types, box, types):
     _check(lib().dsdp_sched_add_receptor(h, atoms, int(np.asarray(rec_types).size), C.byref(_box(box)),
                                          tarr.ctypes.data_as(C.POINTER(C.c_int32)), len(tarr), C.byref(rid)))
     return rid.value
+
+
+def dsdp_sched_set_site(h, receptor_id, points, radius=7.0):
+    """Search space of a receptor's later requests: the box intersected with balls
+    of `radius` around the points ([n, 3]; empty: the plain box)."""
+    pts = np.ascontiguousarray(np.asarray(points, dtype=np.float32).reshape(-1, 3))
+    _check(lib().dsdp_sched_set_site(h, int(receptor_id), pts.ctypes.data_as(C.POINTER(C.c_float)), len(pts),
+                                     float(radius)))
 
 
 def dsdp_sched_submit(h, receptor_id, lig, n_chains, n_steps, seed, top_k):
