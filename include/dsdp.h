@@ -467,6 +467,20 @@ dsdp_status dsdp_sched_add_receptor(dsdp_sched s, const dsdp_atom *rec, int32_t 
                                     const int32_t *types, int32_t n_types, int32_t *receptor_id);
 
 /*
+ * The adaptive search space of a receptor's requests (Section 2, "Binding pose
+ * search", third modification; as dsdp_grids_set_site): the box intersected with
+ * balls of `radius` around n_points points (host [n_points][3], copied; 0 points:
+ * the whole box).  Requests admitted afterwards search in it, each with the
+ * result dsdp_dock gives on maps with the same points set.  The points are kept
+ * in the pool next to the receptor's maps (16 bytes each).  Arguments as in
+ * dsdp_grids_set_site; DSDP_ERR_BUSY while a request of this receptor is queued
+ * or running (a running search keeps its space); resident maps are rebuilt on
+ * next use.
+ */
+dsdp_status dsdp_sched_set_site(dsdp_sched s, int32_t receptor_id, const float *points, int32_t n_points,
+                                float radius);
+
+/*
  * Queue a dock request (as dsdp_dock with the scheduler's parameters).  The ligand
  * is validated and copied now.  Admission happens in dsdp_sched_tick, in arrival
  * order, as soon as n_chains slots, arena space and the receptor's maps fit.

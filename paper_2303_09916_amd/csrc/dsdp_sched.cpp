@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -36,8 +37,10 @@ struct Receptor {
     dsdp_box box;
     std::vector<int32_t> types;
     int map_of_type[kNXS];
+    std::vector<float4> site;   // search-space points (none: the whole box)
+    float site_r = 0.f;
     bool resident = false;
-    size_t maps_off = 0, maps_bytes = 0;
+    size_t maps_off = 0, maps_bytes = 0;   // maps, then the site points, in one pool range
     int active = 0;
     uint64_t last_use = 0;
 };
@@ -121,7 +124,8 @@ dsdp_status ensure_resident(dsdp_sched s, int id)
 {
     Receptor &r = s->receptors[(size_t)id];
     if (r.resident) return DSDP_OK;
-    const size_t maps = align256(dsdp_grids_bytes(&r.box, (int32_t)r.types.size()));
+    const size_t maps_only = align256(dsdp_grids_bytes(&r.box, (int32_t)r.types.size()));
+    const size_t maps = maps_only + align256(r.site.size() * sizeof(float4));
     const size_t wsb = align256(dsdp_build_grids_workspace_bytes((int32_t)r.atoms.size(), &r.box));
     size_t mo = 0, wo = 0;
     for (;;) {
@@ -141,21 +145,31 @@ dsdp_status ensure_resident(dsdp_sched s, int id)
     }
     dsdp_grids g = nullptr;
     dsdp_status st = dsdp_build_grids(r.atoms.data(), (int32_t)r.atoms.size(), &r.box, r.types.data(),
-                                      (int32_t)r.types.size(), s->pool + mo, maps, s->pool + wo, wsb, s->stream, &g);
+                                      (int32_t)r.types.size(), s->pool + mo, maps_only, s->pool + wo, wsb, s->stream,
+                                      &g);
     if (st) {
         s->mem.release(mo, maps);
         s->mem.release(wo, wsb);
         return st;
     }
-    // the build reads the workspace: wait before handing it back
-    hipError_t e = hipStreamSynchronize(s->stream);
+    hipError_t e = hipSuccess;
+    if (!r.site.empty())
+        e = hipMemcpyAsync(s->pool + mo + maps_only, r.site.data(), r.site.size() * sizeof(float4),
+                           hipMemcpyHostToDevice, s->stream);
+    // the build reads the workspace (and the copy the host points): wait before
+    // handing them back
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     s->mem.release(wo, wsb);
     if (e != hipSuccess) {
         dsdp_grids_release(g);
         s->mem.release(mo, maps);
         return hip_fail(e, "map build");
     }
-    s->h_grids[(size_t)id] = g->view;
+    GridView v = g->view;
+    v.n_site = (int)r.site.size();
+    v.site_r = r.site_r;
+    v.site = v.n_site ? (const float4 *)(s->pool + mo + maps_only) : nullptr;
+    s->h_grids[(size_t)id] = v;
     dsdp_grids_release(g);
     s->grids_dirty = true;
     r.resident = true;
@@ -333,6 +347,41 @@ dsdp_status dsdp_sched_add_receptor(dsdp_sched s, const dsdp_atom *rec, int32_t 
     return DSDP_OK;
 }
 
+dsdp_status dsdp_sched_set_site(dsdp_sched s, int32_t receptor_id, const float *points, int32_t n_points,
+                                float radius)
+{
+    if (!s) return fail(DSDP_ERR_INVALID_ARG, "scheduler is NULL");
+    if (receptor_id < 0 || receptor_id >= (int)s->receptors.size())
+        return fail(DSDP_ERR_INVALID_ARG, "unknown receptor %d", receptor_id);
+    if (n_points < 0 || n_points > kMaxSite) return fail(DSDP_ERR_INVALID_ARG, "n_points %d outside 0..%d", n_points, kMaxSite);
+    if (n_points > 0 && (!points || !(radius > 0.f) || !std::isfinite(radius)))
+        return fail(DSDP_ERR_INVALID_ARG, "site points missing or radius not positive");
+    std::vector<float4> site((size_t)n_points);
+    for (int i = 0; i < n_points; i++) {
+        const float x = points[3 * i], y = points[3 * i + 1], z = points[3 * i + 2];
+        if (!std::isfinite(x) || !std::isfinite(y) || !std::isfinite(z))
+            return fail(DSDP_ERR_INVALID_ARG, "site point %d is not finite", i);
+        site[(size_t)i] = make_float4(x, y, z, 0.f);
+    }
+    Receptor &r = s->receptors[(size_t)receptor_id];
+    // a running request keeps the search space it started with: change it only
+    // while none of this receptor's requests is queued or running
+    if (r.active > 0) return fail(DSDP_ERR_BUSY, "receptor %d has running requests", receptor_id);
+    for (const Request *q : s->queue)
+        if (q->receptor == receptor_id) return fail(DSDP_ERR_BUSY, "receptor %d has queued requests", receptor_id);
+    const size_t need = align256(dsdp_grids_bytes(&r.box, (int32_t)r.types.size())) +
+                        align256(site.size() * sizeof(float4)) +
+                        align256(dsdp_build_grids_workspace_bytes((int32_t)r.atoms.size(), &r.box));
+    if (need > s->mem.total)
+        return fail(DSDP_ERR_WORKSPACE_TOO_SMALL, "receptor maps and site need %zu bytes, the pool has %zu", need,
+                    s->mem.total);
+    // resident maps are rebuilt with the new points when next needed
+    if (r.resident) evict(s, r);
+    r.site.swap(site);
+    r.site_r = n_points ? radius : 0.f;
+    return DSDP_OK;
+}
+
 dsdp_status dsdp_sched_submit(dsdp_sched s, int32_t receptor_id, const dsdp_ligand *lig, int32_t n_chains,
                               int32_t n_steps, uint64_t seed, int32_t top_k, int64_t *ticket)
 {
@@ -354,6 +403,7 @@ dsdp_status dsdp_sched_submit(dsdp_sched s, int32_t receptor_id, const dsdp_liga
     // an idle scheduler must be able to admit it: its ligand next to its receptor's maps
     const Receptor &r = s->receptors[(size_t)receptor_id];
     const size_t need = align256(q->pl.blob.size() * 4) + align256(dsdp_grids_bytes(&r.box, (int32_t)r.types.size())) +
+                        align256(r.site.size() * sizeof(float4)) +
                         align256(dsdp_build_grids_workspace_bytes((int32_t)r.atoms.size(), &r.box));
     if (need > s->mem.total)
         return fail(DSDP_ERR_WORKSPACE_TOO_SMALL, "request needs %zu pool bytes, the pool has %zu", need, s->mem.total);

@@ -4,7 +4,7 @@ and when receptor maps are evicted and rebuilt to fit a small pool."""
 import numpy as np
 import pytest
 
-from synth import make_config, make_ligand, make_receptor, make_box, PALETTE_T9
+from synth import make_config, make_ligand, make_receptor, make_box, make_site_points, PALETTE_T9
 from helpers import box32
 
 pytestmark = pytest.mark.gpu
@@ -36,7 +36,7 @@ def alone(handle, lig, c, s, sd, tk, params=None):
     return poses, st
 
 
-def run_sched(pool_bytes_extra, capacity, spt, stagger, evict=False, params=None):
+def run_sched(pool_bytes_extra, capacity, spt, stagger, evict=False, params=None, site=None):
     import gpu_common as gc
     import paper_2303_09916_amd as D
     torch = gc.torch_cuda()
@@ -48,6 +48,8 @@ def run_sched(pool_bytes_extra, capacity, spt, stagger, evict=False, params=None
     h = D.dsdp_sched_create(pool, capacity, spt, params)
     try:
         rids = [D.dsdp_sched_add_receptor(h, r.xyz, r.types, b, types) for r, b in S]
+        if site is not None:
+            D.dsdp_sched_set_site(h, rids[site[0]], site[1], site[2])
         reqs = requests()
         tickets = {}
         first = reqs[:stagger] if stagger else reqs
@@ -77,10 +79,13 @@ def run_sched(pool_bytes_extra, capacity, spt, stagger, evict=False, params=None
         D.dsdp_sched_destroy(h)
 
 
-def check_against_alone(out, S, reqs, params=None):
+def check_against_alone(out, S, reqs, params=None, site=None):
     import gpu_common as gc
+    import paper_2303_09916_amd as D
     types = list(PALETTE_T9)
     grids = [gc.GpuGrid(r.xyz, r.types, b, types) for r, b in S]
+    if site is not None:
+        D.dsdp_grids_set_site(grids[site[0]].handle, site[1], site[2])
     for k, (r, lig, c, s, sd, tk) in enumerate(reqs):
         p_alone, st_alone = alone(grids[r].handle, lig, c, s, sd, tk, params)
         p_s, st_s = out[k]
@@ -99,6 +104,73 @@ def test_sched_equals_alone_barzilai_borwein():
     out, info, S, reqs = run_sched(4 << 20, 256, 3, 3, params=prm)
     assert (info.running, info.queued) == (0, 0)
     check_against_alone(out, S, reqs, prm)
+
+
+def test_sched_site_equals_alone():
+    """A receptor's adaptive search space under the scheduler (Section 2, third
+    modification): its requests equal docking alone on maps with the same site
+    points set, the other receptor's requests the plain box."""
+    rec0 = sites()[0][0]
+    pts = make_site_points(rec0, n=80, radius=5.0, clearance=2.5)
+    site = (0, pts, 6.0)
+    out, info, S, reqs = run_sched(1 << 20, 256, 4, 3, site=site)
+    assert info.completed == len(reqs) and info.evictions == 0
+    check_against_alone(out, S, reqs, site=site)
+
+
+def test_sched_site_busy_and_validation():
+    """The search space changes only while none of the receptor's requests is
+    queued or running; resident maps are rebuilt with the new points; malformed
+    points are rejected."""
+    import gpu_common as gc
+    import paper_2303_09916_amd as D
+    torch = gc.torch_cuda()
+    (rec, box), _ = sites()
+    types = list(PALETTE_T9)
+    pool = gc.dev_bytes(torch, D.dsdp_sched_fixed_bytes(64) + D.dsdp_grids_bytes(box, len(types))
+                        + D.dsdp_build_grids_workspace_bytes(rec.n, box) + (4 << 20))
+    h = D.dsdp_sched_create(pool, 64, 3)
+    try:
+        rid = D.dsdp_sched_add_receptor(h, rec.xyz, rec.types, box, types)
+        pts = make_site_points(rec, n=40, radius=5.0, clearance=2.5)
+        for args in ((np.zeros((257, 3)), 7.0), (pts, 0.0), (np.full((3, 3), np.nan), 7.0)):
+            with pytest.raises(D.DsdpError) as e:
+                D.dsdp_sched_set_site(h, rid, *args)
+            assert e.value.status == D.DSDP_ERR_INVALID_ARG
+        with pytest.raises(D.DsdpError) as e:
+            D.dsdp_sched_set_site(h, rid + 1, pts, 7.0)
+        assert e.value.status == D.DSDP_ERR_INVALID_ARG
+        L = D.Ligand.from_synth(make_ligand(20, 4, seed=5, palette=PALETTE_T9))
+        t = D.dsdp_sched_submit(h, rid, L, 16, 6, 9, 3)
+        with pytest.raises(D.DsdpError) as e:          # queued
+            D.dsdp_sched_set_site(h, rid, pts, 7.0)
+        assert e.value.status == D.DSDP_ERR_BUSY
+        D.dsdp_sched_tick(h)
+        with pytest.raises(D.DsdpError) as e:          # running
+            D.dsdp_sched_set_site(h, rid, pts, 7.0)
+        assert e.value.status == D.DSDP_ERR_BUSY
+        for _ in range(20):
+            if D.dsdp_sched_poll(h, t, 3)[0] == D.DSDP_REQ_DONE:
+                break
+            D.dsdp_sched_tick(h)
+        plain = D.dsdp_sched_poll(h, t, 3)[1]
+        builds = D.dsdp_sched_get_info(h).map_builds
+        D.dsdp_sched_set_site(h, rid, pts, 7.0)        # idle: accepted, maps evicted
+        t2 = D.dsdp_sched_submit(h, rid, L, 16, 6, 9, 3)
+        for _ in range(20):
+            if D.dsdp_sched_poll(h, t2, 3)[0] == D.DSDP_REQ_DONE:
+                break
+            D.dsdp_sched_tick(h)
+        restricted = D.dsdp_sched_poll(h, t2, 3)[1]
+        assert D.dsdp_sched_get_info(h).map_builds == builds + 1
+        g = gc.GpuGrid(rec.xyz, rec.types, box, types)
+        ws = gc.dev_bytes(torch, D.dsdp_dock_workspace_bytes(L, 16))
+        assert [bytes(p) for p in plain] == [bytes(p) for p in D.dsdp_dock(g.handle, L, 16, 6, 9, 3, ws)[0]]
+        D.dsdp_grids_set_site(g.handle, pts, 7.0)
+        assert [bytes(p) for p in restricted] == [bytes(p) for p in D.dsdp_dock(g.handle, L, 16, 6, 9, 3, ws)[0]]
+        assert [bytes(p) for p in restricted] != [bytes(p) for p in plain]
+    finally:
+        D.dsdp_sched_destroy(h)
 
 
 @pytest.mark.parametrize("spt,stagger", [(4, 0), (3, 3), (50, 5)])
